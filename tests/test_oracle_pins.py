@@ -1,0 +1,284 @@
+"""Pins of the CPU oracle against mathematics that does not go through it.
+
+Every check here is independent of the oracle's own code path: mpmath special
+functions, closed forms, numerical differentiation, brute-force quadrature,
+symmetry and invariance properties, and finite differences.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import pins
+from paper_2406_11185_amd import molgen
+
+rng_cases = np.random.default_rng(20240617)
+
+
+# --- Boys function -------------------------------------------------------------
+
+@pytest.mark.parametrize("T", [0.0, 1e-12, 1e-6, 0.05, 0.7, 2.5, 9.9, 17.3, 29.999, 30.0,
+                               30.001, 45.0, 80.0, 200.0])
+def test_boys_matches_incomplete_gamma(T):
+    F = oracle.boys(12, T)
+    for m in range(13):
+        ref = float(pins.boys_mp(m, T))
+        assert abs(F[m] - ref) <= 2e-15 * abs(ref) + 1e-300, (m, T, F[m], ref)
+
+
+def test_boys_at_zero_and_asymptote():
+    F = oracle.boys(10, 0.0)
+    for m in range(11):
+        assert F[m] == pytest.approx(1.0 / (2 * m + 1), rel=1e-15)
+    T = 150.0
+    F = oracle.boys(9, T)
+    for m in range(10):
+        dfac = math.prod(range(2 * m - 1, 0, -2)) if m > 0 else 1
+        asym = dfac / 2 ** (m + 1) * math.sqrt(math.pi / T ** (2 * m + 1))
+        assert F[m] == pytest.approx(asym, rel=1e-13)
+
+
+def test_boys_recurrences_hold():
+    for T in (0.3, 4.0, 29.0, 31.0, 60.0):
+        F = oracle.boys(10, T)
+        e = math.exp(-T)
+        for m in range(10):
+            assert (2 * m + 1) * F[m] == pytest.approx(2 * T * F[m + 1] + e, rel=1e-14)
+
+
+# --- primitive integrals --------------------------------------------------------
+
+def _rand_prims(rng, pows):
+    ex = rng.uniform(0.1, 4.0, 4)
+    C = [rng.uniform(-1.5, 1.5, 3) for _ in range(4)]
+    args = []
+    for k in range(4):
+        args += [pows[k], ex[k], C[k]]
+    return args
+
+
+def test_ssss_closed_form():
+    rng = np.random.default_rng(1)
+    z = (0, 0, 0)
+    for _ in range(20):
+        args = _rand_prims(rng, [z, z, z, z])
+        o = oracle.prim_eri(*args)
+        ref = float(pins.ssss_closed(args[1], args[2], args[4], args[5], args[7], args[8],
+                                     args[10], args[11]))
+        assert o == pytest.approx(ref, rel=1e-14)
+    # coincident centres: T = 0 branch
+    A = np.zeros(3)
+    o = oracle.prim_eri(z, 0.7, A, z, 0.3, A, z, 1.1, A, z, 0.2, A)
+    ref = float(pins.ssss_closed(0.7, A, 0.3, A, 1.1, A, 0.2, A))
+    assert o == pytest.approx(ref, rel=1e-14)
+
+
+DERIV_CASES = [
+    ((1, 0, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0)),
+    ((0, 0, 1), (0, 1, 0), (0, 0, 0), (0, 0, 0)),
+    ((2, 0, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0)),
+    ((1, 1, 0), (0, 0, 0), (0, 0, 1), (0, 0, 0)),
+    ((0, 1, 0), (0, 0, 0), (0, 1, 0), (1, 0, 0)),
+    ((0, 0, 0), (0, 0, 2), (0, 0, 0), (0, 1, 0)),
+]
+
+
+@pytest.mark.parametrize("pows", DERIV_CASES)
+def test_prim_eri_as_centre_derivatives(pows):
+    rng = np.random.default_rng(hash(pows) % 2**32)
+    args = _rand_prims(rng, list(pows))
+    o = oracle.prim_eri(*args)
+    ref = pins.eri_by_derivs(*args)
+    assert abs(o - ref) <= 1e-12 * max(abs(ref), 1e-3), (o, ref)
+
+
+QUAD_CASES = [
+    ((0, 0, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0)),
+    ((1, 0, 0), (0, 1, 0), (0, 0, 0), (0, 0, 1)),
+    ((2, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 0)),
+    ((0, 1, 1), (1, 0, 1), (2, 0, 0), (0, 1, 1)),
+    ((1, 0, 1), (0, 2, 0), (1, 1, 0), (0, 0, 2)),
+    ((0, 0, 2), (0, 0, 2), (0, 0, 2), (0, 0, 2)),
+    ((3, 0, 0), (0, 1, 1), (0, 2, 0), (1, 0, 0)),   # one centre at l+1 (gradient)
+]
+
+
+@pytest.mark.parametrize("pows", QUAD_CASES)
+def test_prim_eri_by_quadrature(pows):
+    rng = np.random.default_rng(sum(sum(p) * (i + 3) for i, p in enumerate(pows)))
+    args = _rand_prims(rng, list(pows))
+    o = oracle.prim_eri(*args)
+    ref = pins.eri_quadrature(*args)
+    assert abs(o - ref) <= 1e-11 * max(abs(ref), 1e-6), (o, ref)
+
+
+def test_prim_eri_axis_permutation_and_inversion():
+    rng = np.random.default_rng(3)
+    perm = [1, 2, 0]
+    for _ in range(10):
+        pows = [tuple(int(x) for x in rng.integers(0, 2, 3)) for _ in range(4)]
+        args = _rand_prims(rng, pows)
+        o = oracle.prim_eri(*args)
+        pa = list(args)
+        for k in range(4):
+            pa[3 * k] = tuple(args[3 * k][i] for i in perm)
+            pa[3 * k + 2] = np.asarray(args[3 * k + 2])[perm]
+        assert oracle.prim_eri(*pa) == pytest.approx(o, rel=1e-13, abs=1e-16)
+        inv = list(args)
+        for k in range(4):
+            inv[3 * k + 2] = -np.asarray(args[3 * k + 2])
+        ltot = sum(sum(p) for p in pows)
+        assert oracle.prim_eri(*inv) == pytest.approx((-1) ** ltot * o, rel=1e-13, abs=1e-16)
+
+
+# --- contracted shell quartets --------------------------------------------------
+
+@pytest.fixture(scope="module")
+def w4():
+    return molgen.workload("w4")
+
+
+def test_eightfold_symmetry(w4):
+    b = oracle.Basis(w4)
+    rng = np.random.default_rng(11)
+    for _ in range(12):
+        A, B, C, D = (int(x) for x in rng.integers(0, w4.n_shells, 4))
+        ref = oracle.shell_quartet(b, A, B, C, D)
+        perms = {
+            (B, A, C, D): (1, 0, 2, 3), (A, B, D, C): (0, 1, 3, 2), (B, A, D, C): (1, 0, 3, 2),
+            (C, D, A, B): (2, 3, 0, 1), (D, C, A, B): (3, 2, 0, 1), (C, D, B, A): (2, 3, 1, 0),
+            (D, C, B, A): (3, 2, 1, 0),
+        }
+        for (a, bb, c, d), axes in perms.items():
+            other = oracle.shell_quartet(b, a, bb, c, d)
+            # other[i_a, i_b, i_c, i_d] with the roles permuted back to (A B | C D)
+            back = np.transpose(other, np.argsort(axes))
+            np.testing.assert_allclose(back, ref, rtol=1e-13, atol=1e-16)
+
+
+def test_schwarz_inequality_and_positive_diagonal(w4):
+    b = oracle.Basis(w4)
+    Q = oracle.schwarz(b)
+    rng = np.random.default_rng(12)
+    for _ in range(200):
+        A, B, C, D = (int(x) for x in rng.integers(0, w4.n_shells, 4))
+        blk = oracle.shell_quartet(b, A, B, C, D)
+        assert np.abs(blk).max() <= Q[A, B] * Q[C, D] * (1 + 1e-12) + 1e-18
+    for A in range(w4.n_shells):
+        blk = oracle.shell_quartet(b, A, A, A, A)
+        n = blk.shape[0]
+        M = blk.reshape(n * n, n * n)
+        assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > -1e-12
+
+
+def test_translation_invariance(w4):
+    J0, K0, _ = oracle.jk(w4, 0.0)
+    shifted = w4.with_xyz(w4.xyz + np.array([0.37, -1.2, 2.05]))
+    J1, K1, _ = oracle.jk(shifted, 0.0)
+    np.testing.assert_allclose(J1, J0, atol=1e-12)
+    np.testing.assert_allclose(K1, K0, atol=1e-12)
+
+
+# --- J and K --------------------------------------------------------------------
+
+def test_unique_digestion_equals_definition_blocks(w4):
+    """Symmetry-unique digestion against the plain sums for every shell pair."""
+    J, K, kept = oracle.jk(w4, 0.0)
+    assert kept == 171 * 172 // 2
+    ns = w4.n_shells
+    bf0 = w4.shell_bf0
+    pairs = [(m, n) for m in range(ns) for n in range(ns) if (m * 7 + n) % 5 == 0]
+    blocks = oracle.jk_blocks(w4, 0.0, pairs)
+    for (m, n), (jb, kb) in zip(pairs, blocks):
+        nm, nn = jb.shape[1:]
+        np.testing.assert_allclose(J[0, bf0[m]:bf0[m] + nm, bf0[n]:bf0[n] + nn], jb[0],
+                                   atol=1e-13, rtol=1e-12)
+        np.testing.assert_allclose(K[0, bf0[m]:bf0[m] + nm, bf0[n]:bf0[n] + nn], kb[0],
+                                   atol=1e-13, rtol=1e-12)
+
+
+def test_full_tensor_brute_force():
+    """Tiny molecule: full n^4 ERI tensor from ordered quartets, J/K by einsum."""
+    mol = molgen.make_molecule(1, 1, seed=7)
+    b = oracle.Basis(mol)
+    n, ns = mol.n_bf, mol.n_shells
+    bf0 = mol.shell_bf0
+    nc = [molgen.ncart(int(l)) for l in mol.shell_l]
+    eri = np.zeros((n, n, n, n))
+    for A in range(ns):
+        for B in range(ns):
+            for C in range(ns):
+                for D in range(ns):
+                    eri[bf0[A]:bf0[A] + nc[A], bf0[B]:bf0[B] + nc[B], bf0[C]:bf0[C] + nc[C],
+                        bf0[D]:bf0[D] + nc[D]] = oracle.shell_quartet(b, A, B, C, D)
+    Dm = mol.D[0]
+    Jref = np.einsum("ijkl,kl->ij", eri, Dm)
+    Kref = np.einsum("ikjl,kl->ij", eri, Dm)
+    J, K, _ = oracle.jk(mol, 0.0)
+    np.testing.assert_allclose(J[0], Jref, atol=1e-13, rtol=1e-12)
+    np.testing.assert_allclose(K[0], Kref, atol=1e-13, rtol=1e-12)
+
+
+def test_rank_one_identity_and_positivity(w4):
+    """D = c c^T: (Jc)_mu = (mu phi|phi phi) = (Kc)_mu; E_J, E_K >= 0 for D = C C^T."""
+    rng = np.random.default_rng(2)
+    c = rng.normal(size=w4.n_bf)
+    D1 = np.outer(c, c)
+    J, K, _ = oracle.jk(w4, 0.0, D=D1)
+    np.testing.assert_allclose(J[0] @ c, K[0] @ c, rtol=1e-11, atol=1e-11)
+    J, K, _ = oracle.jk(w4, 0.0)
+    EJ, EK = oracle.energy(J, K, w4.D)
+    assert EJ[0] > 0 and EK[0] > 0
+    np.testing.assert_allclose(J, J.transpose(0, 2, 1), atol=1e-14)
+    np.testing.assert_allclose(K, K.transpose(0, 2, 1), atol=1e-14)
+
+
+def test_screening_error_is_bounded():
+    mol = molgen.make_molecule(3, 3, seed=21)
+    J0, K0, k0 = oracle.jk(mol, 0.0)
+    tol = 1e-4  # small molecule: every pair bound is above 3e-3, so screen coarsely
+    J1, K1, k1 = oracle.jk(mol, tol)
+    assert k1 < k0
+    dmax = np.abs(mol.D).max()
+    bound = (k0 - k1) * tol * dmax * 2 * 36
+    assert np.abs(J1 - J0).max() <= bound
+    assert np.abs(K1 - K0).max() <= bound
+    assert np.abs(J1 - J0).max() > 0
+
+
+# --- gradient -------------------------------------------------------------------
+
+def _energy(mol):
+    J, K, _ = oracle.jk(mol, 0.0)
+    EJ, EK = oracle.energy(J, K, mol.D)
+    return EJ - EK
+
+
+def test_gradient_central_differences():
+    mol = molgen.make_molecule(1, 1, seed=7)
+    G = oracle.grad(mol, 0.0)
+    h = 1e-4
+    for a in range(mol.n_atoms):
+        for x in range(3):
+            xp = mol.xyz.copy(); xp[a, x] += h
+            xm = mol.xyz.copy(); xm[a, x] -= h
+            fd = (_energy(mol.with_xyz(xp)) - _energy(mol.with_xyz(xm))) / (2 * h)
+            assert abs(G[0, a, x] - fd[0]) <= 1e-7, (a, x, G[0, a, x], fd)
+
+
+def test_gradient_translation_sum_and_s_only_rotation():
+    mol = molgen.make_molecule(1, 2, seed=9)
+    G = oracle.grad(mol, 0.0)
+    np.testing.assert_allclose(G[0].sum(axis=0), 0.0, atol=1e-11)
+    # s-only basis: E is rotation invariant, so the torque sum_A R_A x g_A vanishes
+    s_only = [i for i, l in enumerate(mol.shell_l) if l == 0]
+    sub = molgen.Molecule(mol.xyz, mol.Z, mol.shell_atom[s_only], mol.shell_l[s_only],
+                          mol.shell_nprim[s_only], mol.shell_prim0[s_only], mol.exps,
+                          mol.coefs)
+    rng = np.random.default_rng(4)
+    Cm = rng.normal(size=(sub.n_bf, 3))
+    sub = sub.with_D(Cm @ Cm.T)
+    Gs = oracle.grad(sub, 0.0)[0]
+    torque = np.cross(sub.xyz, Gs).sum(axis=0)
+    np.testing.assert_allclose(torque, 0.0, atol=1e-11)
