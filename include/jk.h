@@ -1,0 +1,155 @@
+/* jk.h -- C ABI of the MI355X (gfx950) direct-SCF Coulomb/exchange build.
+ *
+ * The library evaluates, on one GPU, the Coulomb and exchange matrices of the
+ * paper's Kohn-Sham Fock build (arXiv 2406.11185, section "DFT Calculation
+ * Flow", Fock-matrix equation):
+ *
+ *     J[mu][nu] = sum_{lam,sig} D[lam][sig] (mu nu|lam sig)
+ *     K[mu][nu] = sum_{lam,sig} D[lam][sig] (mu lam|nu sig)
+ *
+ * with the electron-repulsion integrals of the "Electron Repulsion Integrals"
+ * paragraph ("Key Components Redesign and Implementation"),
+ *
+ *     (mu nu|lam sig) = double integral phi_mu(r) phi_nu(r) phi_lam(r') phi_sig(r') / |r - r'|,
+ *
+ * over contracted Cartesian Gaussian shells, Cauchy-Schwarz screening of shell
+ * quartets against a tolerance, and the paper's single/double precision
+ * dispatch (same paragraph, third item).  K is returned without the hybrid
+ * exchange factor c_x (c_x = 1); the energy convention used for the gradient
+ * is E = 1/2 tr(D J) - 1/4 tr(D K).
+ *
+ * Conventions shared by every entry point
+ *   - Units: bohr and hartree; exponents in bohr^-2.
+ *   - A shell is a segmented contraction of unnormalised primitives
+ *     x^lx y^ly z^lz exp(-a r^2) centred on its atom; coefficients multiply
+ *     these primitives as given (the library normalises nothing).
+ *   - Basis functions are numbered shell by shell, in the order of the shells;
+ *     inside a shell the Cartesian components run over descending powers of x,
+ *     then y: p = x, y, z; d = xx, xy, xz, yy, yz, zz.
+ *   - Matrices are dense, row-major, FP64, [n_dm][n_bf][n_bf].  D must be
+ *     symmetric (only the symmetric part enters the results).
+ *   - Ownership: the caller owns every pointer.  The basis is host memory and
+ *     is read during the call only.  D, J, K and dEdR are DEVICE pointers on the
+ *     context's device.  J, K and dEdR are overwritten, never accumulated into.
+ *   - Streams: all device work is enqueued on `hip_stream` (a hipStream_t; NULL
+ *     means the legacy default stream).  The call returns after the work is
+ *     enqueued; results are valid once that stream reaches this point.  The
+ *     call itself synchronises the stream once, after the screening step, to
+ *     size the integral launches.
+ *   - Errors: every function returns JK_OK (0) or a JK_E* code.  All argument
+ *     checks run before any device work, so on an argument error the outputs
+ *     are untouched.  jk_last_error() returns a message for the last failure on
+ *     that context.  No C++ exception crosses this interface.
+ *   - Calls on one context must not overlap (the context owns scratch memory).
+ */
+#ifndef JK_H_
+#define JK_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JK_OK 0
+#define JK_EINVAL 1        /* bad argument or basis                                  */
+#define JK_EUNSUPPORTED 2  /* valid request outside what the library implements      */
+#define JK_ENOMEM 3        /* device memory exhausted or over opts.max_scratch_bytes */
+#define JK_EHIP 4          /* a HIP runtime call failed                              */
+
+#define JK_FP64 0   /* every kept quartet in FP64                                         */
+#define JK_MIXED 1  /* FP32 integrals where the Schwarz bound is below opts.fp32_below  */
+
+#define JK_MAX_L 2        /* s, p and Cartesian d shells                  */
+#define JK_MAX_NPRIM 8    /* primitives per shell                          */
+#define JK_MAX_NDM 16     /* densities sharing one pass over the integrals */
+#define JK_NCLASS 21      /* canonical shell-quartet classes over s, p, d  */
+
+typedef struct jk_ctx jk_ctx;
+
+/* Molecule and basis (host memory). */
+typedef struct {
+  int32_t n_atoms;
+  const double* xyz;          /* [n_atoms][3] atom positions, bohr                      */
+  int32_t n_shells;
+  const int32_t* shell_atom;  /* [n_shells] atom carrying the shell, 0..n_atoms-1        */
+  const int32_t* shell_l;     /* [n_shells] angular momentum 0..2 (3+ -> JK_EUNSUPPORTED) */
+  const int32_t* shell_nprim; /* [n_shells] primitives, 1..JK_MAX_NPRIM                  */
+  const int32_t* shell_prim0; /* [n_shells] first primitive in exps/coefs                */
+  const double* exps;         /* primitive exponents, > 0                                */
+  const double* coefs;        /* contraction coefficients (of unnormalised primitives)   */
+} jk_basis;
+
+/* Options.  jk_opts_default() fills the defaults noted here. */
+typedef struct {
+  int32_t precision;          /* JK_FP64 (default) or JK_MIXED                           */
+  double fp32_below;          /* JK_MIXED: quartets with tol <= Q_AB*Q_CD < fp32_below use
+                                 FP32 integrals (default 1e-4); FP64 at or above it      */
+  double boys_fp64_T;         /* FP32 kernels evaluate F_m(T) in FP64 for T > this value;
+                                 0 < value <= 30 (default 30)                            */
+  int32_t n_dm;               /* densities in D/J/K (or dEdR), 1..JK_MAX_NDM (default 1) */
+  int32_t deterministic;      /* must be 0: results are summed with device atomics      */
+  int32_t timing;             /* 1: time each integral kernel with HIP events (stats)    */
+  uint64_t max_scratch_bytes; /* 0 = no limit; else JK_ENOMEM if more scratch is needed */
+} jk_opts;
+
+/* Counters of the last jk_build / jk_grad on a context. */
+typedef struct {
+  int64_t quartets_fp64[JK_NCLASS];   /* kept quartets computed in FP64, per class        */
+  int64_t quartets_fp32[JK_NCLASS];   /* kept quartets computed in FP32, per class        */
+  int64_t quartets_skipped;           /* unique quartets dropped by the Schwarz screen    */
+  int64_t n_pairs;                    /* unique shell pairs                               */
+  int64_t work_items;                 /* (bra pair, ket range) launches units             */
+  double ms_kernel_fp64[JK_NCLASS];   /* timing=1: summed kernel time per class (ms)      */
+  double ms_kernel_fp32[JK_NCLASS];
+  double ms_setup;                    /* timing=1: pair data, bounds, sort, work lists    */
+  double ms_total;                    /* timing=1: whole call on the stream               */
+  int32_t launches_fp64[JK_NCLASS];   /* integral kernel launches per class               */
+  int32_t launches_fp32[JK_NCLASS];
+  int32_t class_l[JK_NCLASS][4];      /* (la, lb, lc, ld) of each class index             */
+} jk_stats;
+
+/* Fill `opts` with the defaults.  Returns JK_EINVAL if opts is NULL. */
+int jk_opts_default(jk_opts* opts);
+
+/* Create a context on HIP device `device` (allocates the Boys-function tables).
+ * On success *out receives the context; on failure *out is set to NULL. */
+int jk_ctx_create(jk_ctx** out, int device);
+
+/* Release a context and all device memory it holds.  NULL is accepted. */
+int jk_ctx_destroy(jk_ctx* ctx);
+
+/* Check a basis on the host only (no HIP call).  On success, *n_bf_out (if not
+ * NULL) receives the number of basis functions.  JK_EUNSUPPORTED for l > 2 or
+ * more than JK_MAX_NPRIM primitives; JK_EINVAL for anything malformed. */
+int jk_validate_basis(const jk_basis* basis, int32_t* n_bf_out);
+
+/* Coulomb and exchange build ("Electron Repulsion Integrals" paragraph and the
+ * Fock-matrix equation of the paper).  For each of the opts->n_dm densities in
+ * D ([n_dm][n_bf][n_bf], device), writes J and K (same shape, device).
+ * A shell quartet (AB|CD) is computed iff Q_AB * Q_CD >= tol, where
+ * Q_AB = sqrt(max over components of (ab|ab)); tol = 0 keeps every quartet.
+ * opts may be NULL (defaults). */
+int jk_build(jk_ctx* ctx, const jk_basis* basis, const double* D, double* J, double* K,
+             double tol, const jk_opts* opts, void* hip_stream);
+
+/* Nuclear gradient of E = 1/2 tr(D J) - 1/4 tr(D K) at fixed D (basis functions
+ * move with their atoms), under the same screening rule as jk_build.  Writes
+ * dEdR ([n_dm][n_atoms][3], device, hartree/bohr). */
+int jk_grad(jk_ctx* ctx, const jk_basis* basis, const double* D, double* dEdR, double tol,
+            const jk_opts* opts, void* hip_stream);
+
+/* Counters of the last successful jk_build / jk_grad.  With opts.timing = 1
+ * this waits for the recorded events. */
+int jk_get_stats(jk_ctx* ctx, jk_stats* out);
+
+/* Message of the last failure on ctx ("" if none); ctx NULL -> last failure of
+ * jk_ctx_create in this thread. */
+const char* jk_last_error(const jk_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JK_H_ */

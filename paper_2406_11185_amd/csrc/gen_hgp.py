@@ -1,0 +1,534 @@
+"""Generate the per-class Head-Gordon-Pople integral code for the HIP kernels.
+
+The paper's GPU design gives every angular-momentum combination its own
+computational path produced by code generation ("Key Components Redesign and
+Implementation", ERI paragraph, second item).  This script writes that code
+as straight-line C++ for each of the 21 canonical shell-quartet classes over
+s, p and Cartesian d shells:
+
+  * vrr   -- Obara-Saika vertical recurrences (the HGP form) that build the
+             primitive integrals [e0|f0]^(0) for |e| in [la, la+lb] and
+             |f| in [lc, lc+ld] from the scaled Boys values (00|00)^(m) and add
+             them to the contracted accumulators;
+  * hrr   -- horizontal recurrences that move angular momentum from A to B
+             and from C to D after contraction, fused with the J/K digestion;
+  * diag  -- the same HRR restricted to the diagonal components (ab|ab), for
+             the Cauchy-Schwarz bound of a shell pair.
+
+Recurrences (P = Gaussian product centre of the bra, Q of the ket,
+W = (pP + qQ)/(p+q), rho = pq/(p+q)):
+  [e+1_i,0|f0]^m = PA_i [e0|f0]^m + WP_i [e0|f0]^{m+1}
+                 + e_i/(2p) ([e-1_i,0|f0]^m - rho/p [e-1_i,0|f0]^{m+1})
+                 + f_i/(2(p+q)) [e0|f-1_i,0]^{m+1}
+  [e0|f+1_i,0]^m = QC_i [e0|f0]^m + WQ_i [e0|f0]^{m+1}
+                 + f_i/(2q) ([e0|f-1_i,0]^m - rho/q [e0|f-1_i,0]^{m+1})
+                 + e_i/(2(p+q)) [e-1_i,0|f0]^{m+1}
+  (a, b+1_i| = (a+1_i, b| + AB_i (a, b|      |c, d+1_i) = |c+1_i, d) + CD_i |c, d)
+
+It also reports the floating-point operation count of each generated body,
+which the benchmark uses as the algorithmic work per quartet.
+
+Usage: python gen_hgp.py OUTDIR
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+
+PAIR_CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
+LNAME = "spd"
+
+
+def cart(l):
+    return [(lx, ly, l - lx - ly) for lx in range(l, -1, -1) for ly in range(l - lx, -1, -1)]
+
+
+def ncart(l):
+    return (l + 1) * (l + 2) // 2
+
+
+def quartet_classes():
+    out = []
+    for X in range(len(PAIR_CLASSES)):
+        for Y in range(X + 1):
+            la, lb = PAIR_CLASSES[X]
+            lc, ld = PAIR_CLASSES[Y]
+            out.append((X, Y, la, lb, lc, ld))
+    return out
+
+
+def cls_name(la, lb, lc, ld):
+    return f"{LNAME[la]}{LNAME[lb]}{LNAME[lc]}{LNAME[ld]}"
+
+
+def sub(v, i, k=1):
+    w = list(v)
+    w[i] -= k
+    return tuple(w)
+
+
+def add(v, i, k=1):
+    w = list(v)
+    w[i] += k
+    return tuple(w)
+
+
+XYZ = "xyz"
+
+
+class Code:
+    def __init__(self, prefix):
+        self.lines = []
+        self.memo = {}
+        self.n = 0
+        self.prefix = prefix
+        self.flops = 0
+
+    def emit(self, expr, flops):
+        name = f"{self.prefix}{self.n}"
+        self.n += 1
+        self.lines.append(f"const T {name} = {expr};")
+        self.flops += flops
+        return name
+
+
+class VRR(Code):
+    """Vertical recurrences for one class; nodes are [e0|f0]^(m)."""
+
+    def __init__(self, L):
+        super().__init__("v")
+        self.L = L
+
+    def node(self, e, f, m):
+        key = (e, f, m)
+        if key in self.memo:
+            return self.memo[key]
+        if any(x < 0 for x in e) or any(x < 0 for x in f):
+            return None
+        if sum(e) == 0 and sum(f) == 0:
+            name = f"F[{m}]"
+            self.memo[key] = name
+            return name
+        if sum(f) == 0:
+            name = self._bra(e, m)
+        else:
+            name = self._ket(e, f, m)
+        self.memo[key] = name
+        return name
+
+    def _pick(self, cands, children):
+        best, best_cost = None, None
+        for i in cands:
+            cost = sum(1 for k in children(i) if k is not None and k not in self.memo)
+            if best is None or cost < best_cost:
+                best, best_cost = i, cost
+        return best
+
+    def _bra(self, e, m):
+        f0 = (0, 0, 0)
+        cands = [i for i in range(3) if e[i] > 0]
+
+        def ch(i):
+            e1 = sub(e, i)
+            ks = [(e1, f0, m), (e1, f0, m + 1)]
+            if e1[i] > 0:
+                ks += [(sub(e1, i), f0, m), (sub(e1, i), f0, m + 1)]
+            return ks
+
+        i = self._pick(cands, ch)
+        e1 = sub(e, i)
+        a = self.node(e1, f0, m)
+        b = self.node(e1, f0, m + 1)
+        terms = [f"PA{XYZ[i]} * {a}", f"WP{XYZ[i]} * {b}"]
+        fl = 3
+        if e1[i] > 0:
+            c = self.node(sub(e1, i), f0, m)
+            d = self.node(sub(e1, i), f0, m + 1)
+            k = e1[i]
+            terms.append(f"T({k}) * (oo2p * {c} - oo2p_rp * {d})" if k > 1 else
+                         f"(oo2p * {c} - oo2p_rp * {d})")
+            fl += 4 + (1 if k > 1 else 0)
+        return self.emit(" + ".join(terms), fl)
+
+    def _ket(self, e, f, m):
+        cands = [i for i in range(3) if f[i] > 0]
+
+        def ch(i):
+            f1 = sub(f, i)
+            ks = [(e, f1, m), (e, f1, m + 1)]
+            if f1[i] > 0:
+                ks += [(e, sub(f1, i), m), (e, sub(f1, i), m + 1)]
+            if e[i] > 0:
+                ks += [(sub(e, i), f1, m + 1)]
+            return ks
+
+        i = self._pick(cands, ch)
+        f1 = sub(f, i)
+        a = self.node(e, f1, m)
+        b = self.node(e, f1, m + 1)
+        terms = [f"QC{XYZ[i]} * {a}", f"WQ{XYZ[i]} * {b}"]
+        fl = 3
+        if f1[i] > 0:
+            c = self.node(e, sub(f1, i), m)
+            d = self.node(e, sub(f1, i), m + 1)
+            k = f1[i]
+            terms.append(f"T({k}) * (oo2q * {c} - oo2q_rq * {d})" if k > 1 else
+                         f"(oo2q * {c} - oo2q_rq * {d})")
+            fl += 4 + (1 if k > 1 else 0)
+        if e[i] > 0:
+            g = self.node(sub(e, i), f1, m + 1)
+            k = e[i]
+            terms.append(f"T({k}) * oo2pq * {g}" if k > 1 else f"oo2pq * {g}")
+            fl += 2 + (1 if k > 1 else 0)
+        return self.emit(" + ".join(terms), fl)
+
+
+def e_set(la, lb):
+    return [c for l in range(la, la + lb + 1) for c in cart(l)]
+
+
+class HRR(Code):
+    """Horizontal recurrences on contracted [e0|f0]; nodes are (a b|c d)."""
+
+    def __init__(self, la, lb, lc, ld):
+        super().__init__("h")
+        self.E = {c: i for i, c in enumerate(e_set(la, lb))}
+        self.Fs = {c: i for i, c in enumerate(e_set(lc, ld))}
+        self.nf = len(self.Fs)
+
+    def node(self, a, b, c, d):
+        key = (a, b, c, d)
+        if key in self.memo:
+            return self.memo[key]
+        if sum(d) > 0:
+            i = next(k for k in range(3) if d[k] > 0)
+            x = self.node(a, b, add(c, i), sub(d, i))
+            y = self.node(a, b, c, sub(d, i))
+            name = self.emit(f"{x} + CD{XYZ[i]} * {y}", 2)
+        elif sum(b) > 0:
+            i = next(k for k in range(3) if b[k] > 0)
+            x = self.node(add(a, i), sub(b, i), c, d)
+            y = self.node(a, sub(b, i), c, d)
+            name = self.emit(f"{x} + AB{XYZ[i]} * {y}", 2)
+        else:
+            name = f"acc[{self.E[a] * self.nf + self.Fs[c]}]"
+        self.memo[key] = name
+        return name
+
+
+def gen_class(la, lb, lc, ld):
+    L = la + lb + lc + ld
+    name = cls_name(la, lb, lc, ld)
+    E = e_set(la, lb)
+    Fs = e_set(lc, ld)
+    ne, nf = len(E), len(Fs)
+    na, nb, nc, nd = ncart(la), ncart(lb), ncart(lc), ncart(ld)
+
+    vrr = VRR(L)
+    acc_lines = []
+    for ie, e in enumerate(E):
+        for jf, f in enumerate(Fs):
+            v = vrr.node(e, f, 0)
+            acc_lines.append(f"acc[{ie * nf + jf}] += {v};")
+    vrr_flops = vrr.flops + len(acc_lines)
+
+    hrr = HRR(la, lb, lc, ld)
+    dig = []
+    A, B, C, D = cart(la), cart(lb), cart(lc), cart(ld)
+    for ia, a in enumerate(A):
+        for ib, b in enumerate(B):
+            for ic, c in enumerate(C):
+                for id_, d in enumerate(D):
+                    h = hrr.node(a, b, c, d)
+                    dig.append(
+                        f"{{ const double v = double({h}) * fq;"
+                        f" jab[{ia * nb + ib}] += Dcd[{ic * nd + id_}] * v;"
+                        f" jcd[{ic * nd + id_}] += Dab[{ia * nb + ib}] * v;"
+                        f" kac[{ia * nc + ic}] += Dbd[{ib * nd + id_}] * v;"
+                        f" kad[{ia * nd + id_}] += Dbc[{ib * nc + ic}] * v;"
+                        f" kbc[{ib * nc + ic}] += Dad[{ia * nd + id_}] * v;"
+                        f" kbd[{ib * nd + id_}] += Dac[{ia * nc + ic}] * v; }}")
+    hrr_flops = hrr.flops
+    dig_flops = 13 * len(dig)
+
+    diag_code = None
+    if (la, lb) == (lc, ld):
+        dh = HRR(la, lb, lc, ld)
+        out = []
+        for ia, a in enumerate(A):
+            for ib, b in enumerate(B):
+                h = dh.node(a, b, a, b)
+                out.append(f"mx = fmax(mx, double({h}));")
+        diag_code = (dh.lines, out)
+
+    s = []
+    s.append(f"// class ({LNAME[la]}{LNAME[lb]}|{LNAME[lc]}{LNAME[ld]}): L = {L}, "
+             f"{ne}x{nf} contracted [e0|f0], {na * nb * nc * nd} integrals")
+    s.append(f"struct Cls_{name} {{")
+    s.append(f"  static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld}, L = {L};")
+    s.append(f"  static constexpr int NA = {na}, NB = {nb}, NC = {nc}, ND = {nd};")
+    s.append(f"  static constexpr int NE = {ne}, NF = {nf}, NACC = {ne * nf};")
+    s.append(f"  static constexpr int VRR_FLOPS = {vrr_flops}, HRR_FLOPS = {hrr_flops}, "
+             f"DIGEST_FLOPS = {dig_flops};")
+    s.append("  template <typename T>")
+    s.append("  __device__ __forceinline__ static void vrr(const T* __restrict__ F, const VrrCoef<T>& c,"
+             " T* __restrict__ acc) {")
+    s.append("    const T PAx = c.PAx, PAy = c.PAy, PAz = c.PAz, WPx = c.WPx, WPy = c.WPy, WPz = c.WPz;")
+    s.append("    const T QCx = c.QCx, QCy = c.QCy, QCz = c.QCz, WQx = c.WQx, WQy = c.WQy, WQz = c.WQz;")
+    s.append("    const T oo2p = c.oo2p, oo2p_rp = c.oo2p_rp, oo2q = c.oo2q, oo2q_rq = c.oo2q_rq, "
+             "oo2pq = c.oo2pq;")
+    s.append("    (void)PAx; (void)PAy; (void)PAz; (void)WPx; (void)WPy; (void)WPz; (void)QCx; (void)QCy;"
+             " (void)QCz; (void)WQx; (void)WQy; (void)WQz; (void)oo2p; (void)oo2p_rp; (void)oo2q;"
+             " (void)oo2q_rq; (void)oo2pq;")
+    s += ["    " + x for x in vrr.lines]
+    s += ["    " + x for x in acc_lines]
+    s.append("  }")
+    s.append("  template <typename T>")
+    s.append("  __device__ __forceinline__ static void hrr_digest(const T* __restrict__ acc, T ABx, T ABy, T ABz,"
+             " T CDx, T CDy, T CDz, double fq, const double* Dab, const double* Dcd,"
+             " const double* Dac, const double* Dad, const double* Dbc, const double* Dbd,"
+             " double* jab, double* jcd, double* kac, double* kad, double* kbc, double* kbd) {")
+    s.append("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz;")
+    s += ["    " + x for x in hrr.lines]
+    s += ["    " + x for x in dig]
+    s.append("  }")
+    if diag_code is not None:
+        s.append("  template <typename T>")
+        s.append("  __device__ __forceinline__ static double diag_max(const T* __restrict__ acc, T ABx, T ABy,"
+                 " T ABz) {")
+        s.append("    const T CDx = ABx, CDy = ABy, CDz = ABz;")
+        s.append("    (void)CDx; (void)CDy; (void)CDz; (void)ABx; (void)ABy; (void)ABz;")
+        s.append("    double mx = 0.0;")
+        s += ["    " + x for x in diag_code[0]]
+        s += ["    " + x for x in diag_code[1]]
+        s.append("    return mx;")
+        s.append("  }")
+    s.append("};")
+    info = dict(name=name, la=la, lb=lb, lc=lc, ld=ld, L=L, nacc=ne * nf,
+                nint=na * nb * nc * nd, vrr_flops=vrr_flops, hrr_flops=hrr_flops,
+                digest_flops=dig_flops, vrr_nodes=vrr.n, hrr_nodes=hrr.n)
+    return "\n".join(s) + "\n", info
+
+
+SPLIT_NACC = 160   # classes with more contracted accumulators use the multi-pass form
+PASS_ACC = 128     # accumulators per pass in the multi-pass form
+
+
+class KetHRR(Code):
+    """|c d) from |f 0) for one bra component: nodes keyed (c, d)."""
+
+    def __init__(self, lc, ld):
+        super().__init__("k")
+        self.Fs = {c: i for i, c in enumerate(e_set(lc, ld))}
+
+    def node(self, c, d):
+        key = (c, d)
+        if key in self.memo:
+            return self.memo[key]
+        if sum(d) > 0:
+            i = next(k for k in range(3) if d[k] > 0)
+            x = self.node(add(c, i), sub(d, i))
+            y = self.node(c, sub(d, i))
+            name = self.emit(f"{x} + CD{XYZ[i]} * {y}", 2)
+        else:
+            name = f"f[{self.Fs[c]}]"
+        self.memo[key] = name
+        return name
+
+
+class BraHRR(Code):
+    """(a b| from (e 0| for one ket component: nodes keyed (a, b)."""
+
+    def __init__(self, la, lb):
+        super().__init__("b")
+        self.E = {c: i for i, c in enumerate(e_set(la, lb))}
+
+    def node(self, a, b):
+        key = (a, b)
+        if key in self.memo:
+            return self.memo[key]
+        if sum(b) > 0:
+            i = next(k for k in range(3) if b[k] > 0)
+            x = self.node(add(a, i), sub(b, i))
+            y = self.node(a, sub(b, i))
+            name = self.emit(f"{x} + AB{XYZ[i]} * {y}", 2)
+        else:
+            name = f"e[{self.E[a]}]"
+        self.memo[key] = name
+        return name
+
+
+VRR_PROLOGUE = [
+    "const T PAx = c.PAx, PAy = c.PAy, PAz = c.PAz, WPx = c.WPx, WPy = c.WPy, WPz = c.WPz;",
+    "const T QCx = c.QCx, QCy = c.QCy, QCz = c.QCz, WQx = c.WQx, WQy = c.WQy, WQz = c.WQz;",
+    "const T oo2p = c.oo2p, oo2p_rp = c.oo2p_rp, oo2q = c.oo2q, oo2q_rq = c.oo2q_rq, oo2pq = c.oo2pq;",
+    "(void)PAx; (void)PAy; (void)PAz; (void)WPx; (void)WPy; (void)WPz; (void)QCx; (void)QCy;"
+    " (void)QCz; (void)WQx; (void)WQy; (void)WQz; (void)oo2p; (void)oo2p_rp; (void)oo2q;"
+    " (void)oo2q_rq; (void)oo2pq;",
+]
+
+
+def gen_split_class(la, lb, lc, ld):
+    """Multi-pass form: each pass accumulates E x (a chunk of F) in registers."""
+    L = la + lb + lc + ld
+    name = cls_name(la, lb, lc, ld)
+    E = e_set(la, lb)
+    Fs = e_set(lc, ld)
+    ne, nf = len(E), len(Fs)
+    na, nb, nc, nd = ncart(la), ncart(lb), ncart(lc), ncart(ld)
+    chunk = max(1, PASS_ACC // ne)
+    chunks = [list(range(i, min(i + chunk, nf))) for i in range(0, nf, chunk)]
+    s = []
+    s.append(f"// class ({LNAME[la]}{LNAME[lb]}|{LNAME[lc]}{LNAME[ld]}): L = {L}, "
+             f"{ne}x{nf} contracted [e0|f0] built in {len(chunks)} passes, "
+             f"{na * nb * nc * nd} integrals")
+    s.append(f"struct Cls_{name} {{")
+    s.append(f"  static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld}, L = {L};")
+    s.append(f"  static constexpr int NA = {na}, NB = {nb}, NC = {nc}, ND = {nd};")
+    s.append(f"  static constexpr int NE = {ne}, NF = {nf}, NACC = {ne * nf};")
+    s.append(f"  static constexpr int NPASS = {len(chunks)}, FCHUNK = {chunk};")
+    vrr_flops = 0
+    for j, ch in enumerate(chunks):
+        v = VRR(L)
+        lines = []
+        for ie, e in enumerate(E):
+            for jj, jf in enumerate(ch):
+                lines.append(f"acc[{ie * len(ch) + jj}] += {v.node(e, Fs[jf], 0)};")
+        vrr_flops += v.flops + len(lines)
+        s.append(f"  static constexpr int PASS{j}_F0 = {ch[0]}, PASS{j}_NF = {len(ch)};")
+        s.append("  template <typename T>")
+        s.append(f"  __device__ __forceinline__ static void vrr_p{j}(const T* __restrict__ F, "
+                 "const VrrCoef<T>& c, T* __restrict__ acc) {")
+        s += ["    " + x for x in VRR_PROLOGUE]
+        s += ["    " + x for x in v.lines]
+        s += ["    " + x for x in lines]
+        s.append("  }")
+    s.append("  template <int J, typename T>")
+    s.append("  __device__ __forceinline__ static void vrr_pass(const T* __restrict__ F, "
+             "const VrrCoef<T>& c, T* __restrict__ acc) {")
+    for j in range(len(chunks)):
+        kw = "if" if j == 0 else "else if"
+        s.append(f"    {kw} constexpr (J == {j}) vrr_p{j}<T>(F, c, acc);")
+    s.append("  }")
+    s.append("  template <int J> struct Pass;")
+    kh = KetHRR(lc, ld)
+    outs = []
+    for ic, cc in enumerate(cart(lc)):
+        for id_, dd in enumerate(cart(ld)):
+            outs.append(f"out[{ic * nd + id_}] = {kh.node(cc, dd)};")
+    s.append("  template <typename T>")
+    s.append("  __device__ __forceinline__ static void ket_hrr(const T* __restrict__ f, T CDx, T CDy, "
+             "T CDz, T* __restrict__ out) {")
+    s.append("    (void)CDx; (void)CDy; (void)CDz;")
+    s += ["    " + x for x in kh.lines]
+    s += ["    " + x for x in outs]
+    s.append("  }")
+    bh = BraHRR(la, lb)
+    outs = []
+    for ia, aa in enumerate(cart(la)):
+        for ib, bb in enumerate(cart(lb)):
+            outs.append(f"out[{ia * nb + ib}] = {bh.node(aa, bb)};")
+    s.append("  template <typename T>")
+    s.append("  __device__ __forceinline__ static void bra_hrr(const T* __restrict__ e, T ABx, T ABy, "
+             "T ABz, T* __restrict__ out) {")
+    s.append("    (void)ABx; (void)ABy; (void)ABz;")
+    s += ["    " + x for x in bh.lines]
+    s += ["    " + x for x in outs]
+    s.append("  }")
+    hrr_flops = kh.flops * ne + bh.flops * nc * nd
+    dig_flops = 13 * na * nb * nc * nd
+    s.append(f"  static constexpr int VRR_FLOPS = {vrr_flops}, HRR_FLOPS = {hrr_flops}, "
+             f"DIGEST_FLOPS = {dig_flops};")
+    s.append("};")
+    for j, ch in enumerate(chunks):
+        s.append(f"template <> struct Cls_{name}::Pass<{j}> {{ static constexpr int F0 = {ch[0]}, "
+                 f"NF = {len(ch)}; }};")
+    info = dict(name=name, la=la, lb=lb, lc=lc, ld=ld, L=L, nacc=ne * nf,
+                nint=na * nb * nc * nd, vrr_flops=vrr_flops, hrr_flops=hrr_flops,
+                digest_flops=dig_flops, npass=len(chunks), split=True)
+    return "\n".join(s) + "\n", info
+
+
+PAIR_NAME = {pc: LNAME[pc[0]] + LNAME[pc[1]] for pc in PAIR_CLASSES}
+
+
+def wrapper(info):
+    n = info["name"]
+    kern = "eri_jk_split_kernel" if info["split"] else "eri_jk_kernel"
+    skern = "schwarz_split_kernel" if info["split"] else "schwarz_kernel"
+    w = [f"// generated by gen_hgp.py -- do not edit",
+         '#include "jk_device.hpp"',
+         "namespace jk {",
+         f'#include "cls_{n}.inc"',
+         f"void launch_eri_{n}(const EriLaunch& a, int fp32, hipStream_t s) {{",
+         "  const dim3 grid((a.nitems + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);",
+         f"  if (fp32) hipLaunchKernelGGL(({kern}<Cls_{n}, float>), grid, block, 0, s, a);",
+         f"  else hipLaunchKernelGGL(({kern}<Cls_{n}, double>), grid, block, 0, s, a);",
+         "}"]
+    if info["bra_class"] == info["ket_class"]:
+        w += [f"void launch_schwarz_{n}(const EriLaunch& a, double* Q, hipStream_t s) {{",
+              f"  hipLaunchKernelGGL(({skern}<Cls_{n}>), dim3((a.bra.n + kBlock - 1) / kBlock),"
+              " dim3(kBlock), 0, s, a, Q);",
+              "}"]
+    w.append("}  // namespace jk")
+    return "\n".join(w) + "\n"
+
+
+def table(infos):
+    t = ["// generated by gen_hgp.py -- do not edit", '#include "jk_classes.hpp"', "namespace jk {"]
+    for i in infos:
+        t.append(f"void launch_eri_{i['name']}(const EriLaunch&, int, hipStream_t);")
+        if i["bra_class"] == i["ket_class"]:
+            t.append(f"void launch_schwarz_{i['name']}(const EriLaunch&, double*, hipStream_t);")
+    t.append("void launch_eri(int cls, int fp32, const EriLaunch& a, hipStream_t s) {")
+    t.append("  switch (cls) {")
+    for q, i in enumerate(infos):
+        t.append(f"    case {q}: launch_eri_{i['name']}(a, fp32, s); break;")
+    t.append("    default: break;")
+    t.append("  }")
+    t.append("}")
+    t.append("void launch_schwarz(int pair_class, const EriLaunch& a, double* Q, hipStream_t s) {")
+    t.append("  switch (pair_class) {")
+    for i in infos:
+        if i["bra_class"] == i["ket_class"]:
+            t.append(f"    case {i['bra_class']}: launch_schwarz_{i['name']}(a, Q, s); break;")
+    t.append("    default: break;")
+    t.append("  }")
+    t.append("}")
+    t.append("}  // namespace jk")
+    return "\n".join(t) + "\n"
+
+
+def write_if_changed(path, text):
+    if not os.path.exists(path) or open(path).read() != text:
+        with open(path, "w") as fh:
+            fh.write(text)
+
+
+def main(outdir):
+    os.makedirs(outdir, exist_ok=True)
+    infos = []
+    for X, Y, la, lb, lc, ld in quartet_classes():
+        ne, nf = len(e_set(la, lb)), len(e_set(lc, ld))
+        if ne * nf > SPLIT_NACC:
+            code, info = gen_split_class(la, lb, lc, ld)
+        else:
+            code, info = gen_class(la, lb, lc, ld)
+            info["split"] = False
+        info.update(bra_class=X, ket_class=Y)
+        infos.append(info)
+        name = info["name"]
+        write_if_changed(os.path.join(outdir, f"cls_{name}.inc"),
+                         "// generated by gen_hgp.py -- do not edit\n" + code)
+        write_if_changed(os.path.join(outdir, f"cls_{name}.hip"), wrapper(info))
+    write_if_changed(os.path.join(outdir, "jk_classes_table.hip"), table(infos))
+    write_if_changed(os.path.join(outdir, "classes.json"), json.dumps(infos, indent=1))
+    return infos
+
+
+if __name__ == "__main__":
+    infos = main(sys.argv[1] if len(sys.argv) > 1 else "generated")
+    for i in infos:
+        print(f"{i['name']}: L={i['L']} acc={i['nacc']} ints={i['nint']} vrr_flops={i['vrr_flops']}"
+              f" hrr={i['hrr_flops']} dig={i['digest_flops']}")

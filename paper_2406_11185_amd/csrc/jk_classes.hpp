@@ -1,0 +1,11 @@
+// Dispatch to the generated per-class kernels (one translation unit per class).
+#pragma once
+#include "jk_device.hpp"
+
+namespace jk {
+// Integral + digestion kernel of quartet class `cls` (0..20, bra class X >= ket
+// class Y, index X(X+1)/2 + Y over pair classes ss, ps, pp, ds, dp, dd).
+void launch_eri(int cls, int fp32, const EriLaunch& a, hipStream_t s);
+// Cauchy-Schwarz factors of the pairs of one bin of pair class 0..5.
+void launch_schwarz(int pair_class, const EriLaunch& a, double* Q, hipStream_t s);
+}  // namespace jk

@@ -1,0 +1,827 @@
+// Host side of the J/K library: C ABI, basis bookkeeping, setup kernels
+// (shell-pair data, Cauchy-Schwarz factors, screening and work lists) and the
+// dispatch of the per-class integral kernels.
+//
+// Steps of one jk_build (all device work on the caller's stream):
+//   1. shell pairs grouped into bins (angular-momentum class, primitive-pair
+//      count) on the host -- integer bookkeeping only;
+//   2. pair_data_kernel: Gaussian-product data of every primitive pair;
+//   3. schwarz_kernel per bin: Q_AB = sqrt(max (ab|ab)) with the class's own
+//      integral code;
+//   4. segmented radix sort of each bin by Q (descending), pair data rebuilt
+//      in that order;
+//   5. ranges_kernel: for each bra pair and ket bin, binary searches give the
+//      contiguous ket ranges with Q_bra*Q_ket >= fp32_below (FP64),
+//      tol <= Q_bra*Q_ket < fp32_below (FP32 in mixed mode), and the rest is
+//      skipped -- the paper's skip / single / double dispatch ("Electron
+//      Repulsion Integrals" paragraph, third item) without materialising
+//      quartet lists;
+//   6. scan + expand_kernel: work items {bra, ket begin, ket end} of at most
+//      kItemKets kets; one device->host copy of the per-class item counts;
+//   7. J, K cleared, one integral+digestion launch per (class pair, precision),
+//      then J = A + A^T, K = B + B^T in place (finalize_kernel).
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "jk.h"
+#include "jk_device.hpp"
+#include "jk_classes.hpp"
+
+using namespace jk;
+
+namespace {
+
+constexpr int kPairClass[3][3] = {{0, -1, -1}, {1, 2, -1}, {3, 4, 5}};  // [la][lb], la >= lb
+constexpr int kPairL[6][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}};
+
+inline int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+inline int quartet_class(int X, int Y) { return X * (X + 1) / 2 + Y; }  // X >= Y
+
+struct Fail {
+  int code;
+  std::string msg;
+};
+
+#define HIP_OK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw Fail{JK_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)};          \
+  } while (0)
+
+// ---------------------------------------------------------------------------------
+// Boys-function tables (host generation).  Each entry is the power series
+//   F_m(T) = e^{-T} sum_{k>=0} (2T)^k / ((2m+1)(2m+3)...(2m+2k+1))
+// summed in long double until the terms stop contributing.
+long double boys_series(int m, long double T) {
+  long double term = 1.0L / (2 * m + 1), sum = term;
+  for (int k = 1; k < 100000; ++k) {
+    term *= 2.0L * T / (2 * m + 2 * k + 1);
+    sum += term;
+    if (term < sum * 1e-21L) break;
+  }
+  return std::exp(-T) * sum;
+}
+
+void make_boys_tables(std::vector<double>& t64, std::vector<float>& t32) {
+  t64.assign(static_cast<size_t>(kBoysRows) * kBoysStride, 0.0);
+  for (int i = 0; i < kBoysRows; ++i) {
+    const long double T = static_cast<long double>(i) * 0.05L;
+    for (int m = 0; m < kBoysM; ++m) t64[i * kBoysStride + m] = static_cast<double>(boys_series(m, T));
+    t64[i * kBoysStride + kBoysStride - 1] = static_cast<double>(std::exp(-T));
+  }
+  t32.assign(static_cast<size_t>(kBoys32Rows) * kBoys32Stride, 0.0f);
+  for (int i = 0; i < kBoys32Rows; ++i) {
+    const long double T = static_cast<long double>(i) * 0.05L;
+    for (int m = 0; m < kBoys32M; ++m) t32[i * kBoys32Stride + m] = static_cast<float>(boys_series(m, T));
+    t32[i * kBoys32Stride + kBoys32Stride - 1] = static_cast<float>(std::exp(-T));
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Device data of the setup kernels.
+struct ShellDev {
+  const double* xyz;   // [n_shells][3] centre
+  const int* l;
+  const int* nprim;
+  const int* prim0;
+  const int* bf0;
+  const int* atom;
+  const double* exps;
+  const double* coefs;
+};
+
+struct PairOut {
+  double* prim;        // all bins, bin b at prim_off[b]
+  double* A;           // bin b at 3*pair_off[b], [3][n_b]
+  double* AB;
+  int* bf;             // bin b at 2*pair_off[b]
+  int* atoms;
+  double* fpair;       // bin b at pair_off[b]
+};
+
+__device__ __forceinline__ int find_bin(const int* off, int nbins, int g) {
+  int lo = 0, hi = nbins;  // off[lo] <= g < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Step 2: primitive-pair data.  For primitives a (on A) and b (on B):
+//   p = a + b,  P = (aA + bB)/p,  K_AB = c_a c_b exp(-ab/p |A-B|^2),
+//   Kt = sqrt(2) pi^{5/4} K_AB / p  (so that Kt_AB Kt_CD / sqrt(p+q) is the
+//   prefactor 2 pi^{5/2} K_AB K_CD / (pq sqrt(p+q)) of (00|00)^(m)).
+// Slot g of the output holds pair src[g] (identity if src is null).
+__global__ void pair_data_kernel(int npairs, const int* __restrict__ pair_s1,
+                                 const int* __restrict__ pair_s2, const int* __restrict__ src,
+                                 const int* __restrict__ bin_off, const int* __restrict__ bin_npp,
+                                 const long long* __restrict__ bin_prim_off, int nbins,
+                                 ShellDev sh, PairOut out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= npairs) return;
+  const int b = find_bin(bin_off, nbins, g);
+  const int n = bin_off[b + 1] - bin_off[b];
+  const int t = g - bin_off[b];
+  const int s = src ? src[g] : g;
+  const int s1 = pair_s1[s], s2 = pair_s2[s];
+  const double A[3] = {sh.xyz[3 * s1], sh.xyz[3 * s1 + 1], sh.xyz[3 * s1 + 2]};
+  const double B[3] = {sh.xyz[3 * s2], sh.xyz[3 * s2 + 1], sh.xyz[3 * s2 + 2]};
+  const double AB[3] = {A[0] - B[0], A[1] - B[1], A[2] - B[2]};
+  const double AB2 = AB[0] * AB[0] + AB[1] * AB[1] + AB[2] * AB[2];
+  const int po = 3 * bin_off[b];
+  for (int c = 0; c < 3; ++c) {
+    out.A[po + c * n + t] = A[c];
+    out.AB[po + c * n + t] = AB[c];
+  }
+  out.bf[2 * bin_off[b] + t] = sh.bf0[s1];
+  out.bf[2 * bin_off[b] + n + t] = sh.bf0[s2];
+  out.atoms[2 * bin_off[b] + t] = sh.atom[s1];
+  out.atoms[2 * bin_off[b] + n + t] = sh.atom[s2];
+  out.fpair[bin_off[b] + t] = (s1 == s2) ? 0.5 : 1.0;
+  const double kSqrt2Pi54 = 1.4142135623730950488 * 4.1798707165334034;  // sqrt(2) pi^{5/4}
+  const int n1 = sh.nprim[s1], n2 = sh.nprim[s2];
+  double* prim = out.prim + bin_prim_off[b];
+  for (int u = 0; u < n1; ++u)
+    for (int v = 0; v < n2; ++v) {
+      const int pp = u * n2 + v;
+      const double ea = sh.exps[sh.prim0[s1] + u], eb = sh.exps[sh.prim0[s2] + v];
+      const double ca = sh.coefs[sh.prim0[s1] + u], cb = sh.coefs[sh.prim0[s2] + v];
+      const double p = ea + eb, rp = 1.0 / p;
+      const double Kab = ca * cb * exp(-ea * eb * rp * AB2);
+      double* f = prim + static_cast<size_t>(pp) * kPrimFields * n + t;
+      f[kP * n] = p;
+      f[kOo2p * n] = 0.5 * rp;
+      f[kPAx * n] = -eb * rp * AB[0];   // P - A = b/p (B - A)
+      f[kPAy * n] = -eb * rp * AB[1];
+      f[kPAz * n] = -eb * rp * AB[2];
+      f[kKt * n] = kSqrt2Pi54 * Kab * rp;
+      f[kTwoA * n] = 2.0 * ea;
+      f[kTwoB * n] = 2.0 * eb;
+    }
+  (void)bin_npp;
+}
+
+__global__ void iota_kernel(int n, const int* __restrict__ bin_off, int nbins, int* out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  out[g] = g - bin_off[find_bin(bin_off, nbins, g)];
+}
+
+__global__ void local_to_global_kernel(int n, const int* __restrict__ bin_off, int nbins,
+                                       const int* __restrict__ local, int* out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  out[g] = bin_off[find_bin(bin_off, nbins, g)] + local[g];
+}
+
+// Step 5: screening and precision dispatch of one (bin pair, bra pair).
+struct RangeArgs {
+  int nt;                       // threads = sum over bin pairs of bra pairs
+  int nbp;
+  const int* bp_x;              // bra bin of each bin pair
+  const int* bp_y;              // ket bin
+  const int* bp_t0;             // first thread of each bin pair, [nbp+1]
+  const int* bin_off;           // pair offsets of the bins
+  const double* Q;              // sorted Q, all bins
+  double tol, thr;
+  int mixed;
+  int* cnt;                     // [2][nt] items (FP64, FP32)
+  int* rng;                     // [3][nt] k_lo, k_64, k_tol
+  unsigned long long* qstat;    // [nbp][3] FP64 quartets, FP32 quartets, skipped
+};
+
+__device__ __forceinline__ int first_below(const double* Qk, int lo, int hi, double qi, double bound) {
+  // first k in [lo, hi) with qi * Qk[k] < bound (Qk descending), hi if none
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (qi * Qk[mid] < bound) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+__global__ void ranges_kernel(RangeArgs r) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= r.nt) return;
+  const int bp = find_bin(r.bp_t0, r.nbp, t);
+  const int X = r.bp_x[bp], Y = r.bp_y[bp];
+  const int i = t - r.bp_t0[bp];
+  const double* QX = r.Q + r.bin_off[X];
+  const double* QY = r.Q + r.bin_off[Y];
+  const int nY = r.bin_off[Y + 1] - r.bin_off[Y];
+  const int klo = (X == Y) ? i : 0;
+  const double qi = QX[i];
+  const int ktol = (r.tol > 0.0) ? first_below(QY, klo, nY, qi, r.tol) : nY;
+  int k64 = ktol;
+  if (r.mixed) k64 = first_below(QY, klo, ktol, qi, r.thr);
+  const int n64 = k64 - klo, n32 = ktol - k64;
+  r.cnt[t] = (n64 + kItemKets - 1) / kItemKets;
+  r.cnt[r.nt + t] = (n32 + kItemKets - 1) / kItemKets;
+  r.rng[t] = klo;
+  r.rng[r.nt + t] = k64;
+  r.rng[2 * r.nt + t] = ktol;
+  atomicAdd(&r.qstat[3 * bp + 0], static_cast<unsigned long long>(n64));
+  atomicAdd(&r.qstat[3 * bp + 1], static_cast<unsigned long long>(n32));
+  atomicAdd(&r.qstat[3 * bp + 2], static_cast<unsigned long long>(nY - ktol));
+}
+
+__global__ void expand_kernel(int nt, const int* __restrict__ bp_t0, int nbp,
+                              const int* __restrict__ cnt, const int* __restrict__ off,
+                              const int* __restrict__ rng, int4* items) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const int bp = find_bin(bp_t0, nbp, t);
+  const int i = t - bp_t0[bp];
+  const int klo = rng[t], k64 = rng[nt + t], ktol = rng[2 * nt + t];
+  for (int pr = 0; pr < 2; ++pr) {
+    const int beg = pr == 0 ? klo : k64, end = pr == 0 ? k64 : ktol;
+    const int c = cnt[pr * nt + t];
+    const int base = off[pr * nt + t];
+    for (int j = 0; j < c; ++j) {
+      const int k0 = beg + j * kItemKets;
+      items[base + j] = make_int4(i, k0, min(k0 + kItemKets, end), 0);
+    }
+  }
+}
+
+// seg[pr][bp] = first item of bin pair bp in precision pr; seg[1][nbp] = total.
+__global__ void segments_kernel(int nt, int nbp, const int* __restrict__ bp_t0,
+                                const int* __restrict__ cnt, const int* __restrict__ off,
+                                int* seg) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > 2 * nbp + 1) return;
+  const int pr = j / (nbp + 1), bp = j % (nbp + 1);
+  const int t = pr * nt + bp_t0[bp];  // bp == nbp -> first thread of the next precision
+  seg[j] = (t < 2 * nt) ? off[t] : off[2 * nt - 1] + cnt[2 * nt - 1];
+}
+
+template <typename T>
+__global__ void fill_kernel(size_t n, T* a) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = T(0);
+}
+
+// J = A + A^T in place, per density (one thread per upper-triangle element).
+__global__ void finalize_kernel(int n, int n_dm, double* J, double* K) {
+  const size_t nn = static_cast<size_t>(n) * n;
+  const size_t id = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= nn * n_dm) return;
+  const int m = static_cast<int>(id / nn);
+  const size_t r = id % nn;
+  const int i = static_cast<int>(r / n), j = static_cast<int>(r % n);
+  if (j < i) return;
+  double* Jm = J + m * nn;
+  double* Km = K + m * nn;
+  const double sj = Jm[static_cast<size_t>(i) * n + j] + Jm[static_cast<size_t>(j) * n + i];
+  const double sk = Km[static_cast<size_t>(i) * n + j] + Km[static_cast<size_t>(j) * n + i];
+  Jm[static_cast<size_t>(i) * n + j] = sj;
+  Jm[static_cast<size_t>(j) * n + i] = sj;
+  Km[static_cast<size_t>(i) * n + j] = sk;
+  Km[static_cast<size_t>(j) * n + i] = sk;
+}
+
+inline unsigned grid_of(size_t n, int block) { return static_cast<unsigned>((n + block - 1) / block); }
+
+// ---------------------------------------------------------------------------------
+// Grow-only device buffers owned by a context.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+enum Slot {
+  sShellXyz, sShellI, sExps, sCoefs, sPairS, sBinOff, sBinNpp, sBinPrim, sPrimTmp, sPrim,
+  sA, sAB, sBf, sAtoms, sFpair, sAtmp, sABtmp, sBftmp, sAtomstmp, sFpairtmp, sQtmp, sQ,
+  sIdx, sIdxSorted, sPerm, sBp, sCnt, sOff, sRng, sQstat, sSeg, sItems, sCub, sNumSlots
+};
+
+}  // namespace
+
+struct jk_ctx {
+  int device = 0;
+  std::string err;
+  DevBuf buf[sNumSlots];
+  size_t scratch_limit = 0;
+  double* boys64 = nullptr;
+  float* boys32 = nullptr;
+  jk_stats stats{};
+  bool timed = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct Timed { int cls; int fp32; size_t e0; };
+  std::vector<Timed> timed_launches;
+  size_t ev_setup0 = 0, ev_setup1 = 0, ev_end = 0;
+  void* host_pinned = nullptr;
+  size_t host_pinned_bytes = 0;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+template <typename T>
+T* dev(jk_ctx* c, Slot s, size_t count) {
+  const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  DevBuf& b = c->buf[s];
+  if (c->scratch_limit) {
+    size_t total = 0;
+    for (int i = 0; i < sNumSlots; ++i) total += (i == s) ? std::max(b.bytes, bytes) : c->buf[i].bytes;
+    if (total > c->scratch_limit)
+      throw Fail{JK_ENOMEM, "scratch need of " + std::to_string(total) + " bytes is over max_scratch_bytes"};
+  }
+  if (b.bytes < bytes) {
+    if (b.p) HIP_OK(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Fail{JK_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
+    b.bytes = bytes;
+  }
+  return static_cast<T*>(b.p);
+}
+
+void* pinned(jk_ctx* c, size_t bytes) {
+  if (c->host_pinned_bytes < bytes) {
+    if (c->host_pinned) HIP_OK(hipHostFree(c->host_pinned));
+    c->host_pinned = nullptr;
+    c->host_pinned_bytes = 0;
+    HIP_OK(hipHostMalloc(&c->host_pinned, bytes, hipHostMallocDefault));
+    c->host_pinned_bytes = bytes;
+  }
+  return c->host_pinned;
+}
+
+size_t event(jk_ctx* c, hipStream_t s) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    HIP_OK(hipEventCreate(&e));
+    c->ev_pool.push_back(e);
+  }
+  HIP_OK(hipEventRecord(c->ev_pool[c->ev_used], s));
+  return c->ev_used++;
+}
+
+int validate(const jk_basis* b, int32_t* nbf) {
+  if (!b) return JK_EINVAL;
+  if (b->n_atoms < 1 || b->n_shells < 1 || !b->xyz || !b->shell_atom || !b->shell_l ||
+      !b->shell_nprim || !b->shell_prim0 || !b->exps || !b->coefs)
+    return JK_EINVAL;
+  for (int a = 0; a < 3 * b->n_atoms; ++a)
+    if (!std::isfinite(b->xyz[a])) return JK_EINVAL;
+  long long n = 0;
+  for (int s = 0; s < b->n_shells; ++s) {
+    const int l = b->shell_l[s], np = b->shell_nprim[s], p0 = b->shell_prim0[s];
+    if (b->shell_atom[s] < 0 || b->shell_atom[s] >= b->n_atoms) return JK_EINVAL;
+    if (l < 0 || np < 1 || p0 < 0) return JK_EINVAL;
+    if (l > JK_MAX_L || np > JK_MAX_NPRIM) return JK_EUNSUPPORTED;
+    for (int k = 0; k < np; ++k) {
+      const double e = b->exps[p0 + k], cf = b->coefs[p0 + k];
+      if (!(e > 0.0) || !std::isfinite(e) || !std::isfinite(cf)) return JK_EINVAL;
+    }
+    n += ncart(l);
+    if (n > (1 << 15)) return JK_EUNSUPPORTED;
+  }
+  if (nbf) *nbf = static_cast<int32_t>(n);
+  return JK_OK;
+}
+
+std::string validate_msg(int rc) {
+  return rc == JK_EUNSUPPORTED
+             ? "basis outside the supported set (l <= 2, <= 8 primitives, <= 32768 functions)"
+             : "malformed basis (counts, NULL arrays, atom index, exponents or coefficients)";
+}
+
+// Host bookkeeping of the shell pairs and their bins.
+struct Plan {
+  int n_bf = 0, n_shells = 0, n_atoms = 0, npairs = 0, nbins = 0;
+  std::vector<int> bin_cls, bin_npp, bin_off;      // bin_off [nbins+1]
+  std::vector<long long> bin_prim;                 // offset into prim (doubles), [nbins+1]
+  std::vector<int> pair_s1, pair_s2;               // canonical pairs in bin order
+  std::vector<int> bf0;
+  std::vector<int> bp_x, bp_y, bp_t0;              // bin pairs
+  int nt = 0;
+};
+
+Plan make_plan(const jk_basis* b) {
+  Plan P;
+  P.n_shells = b->n_shells;
+  P.n_atoms = b->n_atoms;
+  P.bf0.resize(b->n_shells);
+  int n = 0;
+  for (int s = 0; s < b->n_shells; ++s) { P.bf0[s] = n; n += ncart(b->shell_l[s]); }
+  P.n_bf = n;
+  // bins keyed by (pair class, primitive-pair count)
+  std::map<std::pair<int, int>, std::vector<std::pair<int, int>>> bins;
+  for (int i = 0; i < b->n_shells; ++i)
+    for (int j = 0; j <= i; ++j) {
+      int s1 = i, s2 = j;
+      if (b->shell_l[s2] > b->shell_l[s1]) std::swap(s1, s2);
+      const int cls = kPairClass[b->shell_l[s1]][b->shell_l[s2]];
+      const int npp = b->shell_nprim[s1] * b->shell_nprim[s2];
+      bins[{cls, npp}].push_back({s1, s2});
+    }
+  P.bin_off.push_back(0);
+  P.bin_prim.push_back(0);
+  for (auto& kv : bins) {
+    P.bin_cls.push_back(kv.first.first);
+    P.bin_npp.push_back(kv.first.second);
+    for (auto& pr : kv.second) { P.pair_s1.push_back(pr.first); P.pair_s2.push_back(pr.second); }
+    const int nb = static_cast<int>(kv.second.size());
+    P.bin_off.push_back(P.bin_off.back() + nb);
+    P.bin_prim.push_back(P.bin_prim.back() + static_cast<long long>(kv.first.second) * kPrimFields * nb);
+  }
+  P.nbins = static_cast<int>(P.bin_cls.size());
+  P.npairs = P.bin_off.back();
+  P.bp_t0.push_back(0);
+  for (int X = 0; X < P.nbins; ++X)
+    for (int Y = 0; Y <= X; ++Y) {
+      P.bp_x.push_back(X);
+      P.bp_y.push_back(Y);
+      P.bp_t0.push_back(P.bp_t0.back() + (P.bin_off[X + 1] - P.bin_off[X]));
+    }
+  P.nt = P.bp_t0.back();
+  return P;
+}
+
+template <typename T>
+void upload(const std::vector<T>& v, T* d, hipStream_t s) {
+  if (!v.empty()) HIP_OK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+BinView bin_view(const Plan& P, int b, double* prim, double* A, double* AB, int* bf, int* atoms,
+                 double* fpair, double* Q) {
+  BinView v;
+  const int o = P.bin_off[b];
+  v.n = P.bin_off[b + 1] - o;
+  v.npp = P.bin_npp[b];
+  v.prim = prim + P.bin_prim[b];
+  v.A = A + 3 * o;
+  v.AB = AB + 3 * o;
+  v.bf = bf + 2 * o;
+  v.atoms = atoms + 2 * o;
+  v.fpair = fpair + o;
+  v.Q = Q + o;
+  return v;
+}
+
+struct Setup {
+  Plan P;
+  double *prim, *A, *AB, *fpair, *Q;
+  int *bf, *atoms;
+  int4* items;
+  std::vector<int> seg;   // [2][nbp+1]
+  std::vector<unsigned long long> qstat;
+};
+
+// Steps 1-6.  Returns the sorted pair data, the work items and their segments.
+Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStream_t s) {
+  Setup S;
+  S.P = make_plan(b);
+  Plan& P = S.P;
+  const int ns = P.n_shells, np = P.npairs;
+  int nprim_total = 0;
+  for (int sh = 0; sh < ns; ++sh)
+    nprim_total = std::max(nprim_total, b->shell_prim0[sh] + b->shell_nprim[sh]);
+
+  // shells
+  std::vector<double> sxyz(3 * ns);
+  std::vector<int> si(5 * ns);
+  for (int sh = 0; sh < ns; ++sh) {
+    for (int k = 0; k < 3; ++k) sxyz[3 * sh + k] = b->xyz[3 * b->shell_atom[sh] + k];
+    si[sh] = b->shell_l[sh];
+    si[ns + sh] = b->shell_nprim[sh];
+    si[2 * ns + sh] = b->shell_prim0[sh];
+    si[3 * ns + sh] = P.bf0[sh];
+    si[4 * ns + sh] = b->shell_atom[sh];
+  }
+  double* d_sxyz = dev<double>(c, sShellXyz, sxyz.size());
+  int* d_si = dev<int>(c, sShellI, si.size());
+  double* d_exps = dev<double>(c, sExps, nprim_total);
+  double* d_coefs = dev<double>(c, sCoefs, nprim_total);
+  int* d_pairs = dev<int>(c, sPairS, 2 * static_cast<size_t>(np));
+  int* d_binoff = dev<int>(c, sBinOff, P.nbins + 1);
+  int* d_binnpp = dev<int>(c, sBinNpp, P.nbins);
+  long long* d_binprim = dev<long long>(c, sBinPrim, P.nbins + 1);
+  const size_t nprimd = static_cast<size_t>(P.bin_prim.back());
+  double* d_primtmp = dev<double>(c, sPrimTmp, nprimd);
+  S.prim = dev<double>(c, sPrim, nprimd);
+  S.A = dev<double>(c, sA, 3 * static_cast<size_t>(np));
+  S.AB = dev<double>(c, sAB, 3 * static_cast<size_t>(np));
+  S.bf = dev<int>(c, sBf, 2 * static_cast<size_t>(np));
+  S.atoms = dev<int>(c, sAtoms, 2 * static_cast<size_t>(np));
+  S.fpair = dev<double>(c, sFpair, np);
+  double* d_Atmp = dev<double>(c, sAtmp, 3 * static_cast<size_t>(np));
+  double* d_ABtmp = dev<double>(c, sABtmp, 3 * static_cast<size_t>(np));
+  int* d_bftmp = dev<int>(c, sBftmp, 2 * static_cast<size_t>(np));
+  int* d_atomstmp = dev<int>(c, sAtomstmp, 2 * static_cast<size_t>(np));
+  double* d_fpairtmp = dev<double>(c, sFpairtmp, np);
+  double* d_Qtmp = dev<double>(c, sQtmp, np);
+  S.Q = dev<double>(c, sQ, np);
+  int* d_idx = dev<int>(c, sIdx, np);
+  int* d_idxs = dev<int>(c, sIdxSorted, np);
+  int* d_perm = dev<int>(c, sPerm, np);
+
+  HIP_OK(hipMemcpyAsync(d_sxyz, sxyz.data(), sxyz.size() * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(d_si, si.data(), si.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(d_exps, b->exps, nprim_total * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(d_coefs, b->coefs, nprim_total * 8, hipMemcpyHostToDevice, s));
+  std::vector<int> pairs(2 * static_cast<size_t>(np));
+  std::copy(P.pair_s1.begin(), P.pair_s1.end(), pairs.begin());
+  std::copy(P.pair_s2.begin(), P.pair_s2.end(), pairs.begin() + np);
+  upload(pairs, d_pairs, s);
+  upload(P.bin_off, d_binoff, s);
+  upload(P.bin_npp, d_binnpp, s);
+  upload(P.bin_prim, d_binprim, s);
+
+  ShellDev sd{d_sxyz, d_si, d_si + ns, d_si + 2 * ns, d_si + 3 * ns, d_si + 4 * ns, d_exps, d_coefs};
+  // step 2 (unsorted), step 3
+  PairOut tmp{d_primtmp, d_Atmp, d_ABtmp, d_bftmp, d_atomstmp, d_fpairtmp};
+  hipLaunchKernelGGL(pair_data_kernel, dim3(grid_of(np, 256)), dim3(256), 0, s, np, d_pairs,
+                     d_pairs + np, static_cast<const int*>(nullptr), d_binoff, d_binnpp,
+                     d_binprim, P.nbins, sd, tmp);
+  HIP_OK(hipGetLastError());
+  for (int bb = 0; bb < P.nbins; ++bb) {
+    EriLaunch a{};
+    a.bra = bin_view(P, bb, d_primtmp, d_Atmp, d_ABtmp, d_bftmp, d_atomstmp, d_fpairtmp, d_Qtmp);
+    a.ket = a.bra;
+    a.boys64 = c->boys64;
+    a.boys32 = c->boys32;
+    launch_schwarz(P.bin_cls[bb], a, d_Qtmp + P.bin_off[bb], s);
+  }
+  // step 4: segmented sort by Q, descending, then pair data in sorted order
+  hipLaunchKernelGGL(iota_kernel, dim3(grid_of(np, 256)), dim3(256), 0, s, np, d_binoff, P.nbins, d_idx);
+  size_t cub_bytes = 0;
+  HIP_OK(hipcub::DeviceSegmentedRadixSort::SortPairsDescending(
+      nullptr, cub_bytes, d_Qtmp, S.Q, d_idx, d_idxs, np, P.nbins, d_binoff, d_binoff + 1, 0,
+      64, s));
+  void* d_cub = dev<char>(c, sCub, cub_bytes);
+  HIP_OK(hipcub::DeviceSegmentedRadixSort::SortPairsDescending(
+      d_cub, cub_bytes, d_Qtmp, S.Q, d_idx, d_idxs, np, P.nbins, d_binoff, d_binoff + 1, 0,
+      64, s));
+  hipLaunchKernelGGL(local_to_global_kernel, dim3(grid_of(np, 256)), dim3(256), 0, s, np,
+                     d_binoff, P.nbins, d_idxs, d_perm);
+  PairOut fin{S.prim, S.A, S.AB, S.bf, S.atoms, S.fpair};
+  hipLaunchKernelGGL(pair_data_kernel, dim3(grid_of(np, 256)), dim3(256), 0, s, np, d_pairs,
+                     d_pairs + np, d_perm, d_binoff, d_binnpp, d_binprim, P.nbins, sd, fin);
+  HIP_OK(hipGetLastError());
+
+  // step 5: ranges
+  const int nbp = static_cast<int>(P.bp_x.size());
+  const int nt = P.nt;
+  std::vector<int> bpv;
+  bpv.insert(bpv.end(), P.bp_x.begin(), P.bp_x.end());
+  bpv.insert(bpv.end(), P.bp_y.begin(), P.bp_y.end());
+  bpv.insert(bpv.end(), P.bp_t0.begin(), P.bp_t0.end());
+  int* d_bp = dev<int>(c, sBp, bpv.size());
+  upload(bpv, d_bp, s);
+  int* d_cnt = dev<int>(c, sCnt, 2 * static_cast<size_t>(nt));
+  int* d_off = dev<int>(c, sOff, 2 * static_cast<size_t>(nt));
+  int* d_rng = dev<int>(c, sRng, 3 * static_cast<size_t>(nt));
+  unsigned long long* d_qstat = dev<unsigned long long>(c, sQstat, 3 * static_cast<size_t>(nbp));
+  hipLaunchKernelGGL(fill_kernel<unsigned long long>, dim3(grid_of(3 * nbp, 256)), dim3(256), 0, s,
+                     static_cast<size_t>(3 * nbp), d_qstat);
+  RangeArgs ra{nt, nbp, d_bp, d_bp + nbp, d_bp + 2 * nbp, d_binoff, S.Q, tol,
+               o.precision == JK_MIXED ? o.fp32_below : 0.0, o.precision == JK_MIXED ? 1 : 0,
+               d_cnt, d_rng, d_qstat};
+  hipLaunchKernelGGL(ranges_kernel, dim3(grid_of(nt, 256)), dim3(256), 0, s, ra);
+  HIP_OK(hipGetLastError());
+  // step 6: scan, segments, read back, expand
+  size_t scan_bytes = 0;
+  HIP_OK(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, d_cnt, d_off, 2 * nt, s));
+  d_cub = dev<char>(c, sCub, std::max(scan_bytes, cub_bytes));
+  HIP_OK(hipcub::DeviceScan::ExclusiveSum(d_cub, scan_bytes, d_cnt, d_off, 2 * nt, s));
+  int* d_seg = dev<int>(c, sSeg, 2 * (nbp + 1));
+  hipLaunchKernelGGL(segments_kernel, dim3(grid_of(2 * (nbp + 1), 256)), dim3(256), 0, s, nt,
+                     nbp, d_bp + 2 * nbp, d_cnt, d_off, d_seg);
+  HIP_OK(hipGetLastError());
+  const size_t rb_bytes = 2 * (nbp + 1) * sizeof(int) + 3 * nbp * sizeof(unsigned long long);
+  char* hp = static_cast<char*>(pinned(c, rb_bytes));
+  HIP_OK(hipMemcpyAsync(hp, d_seg, 2 * (nbp + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(hp + 2 * (nbp + 1) * sizeof(int), d_qstat,
+                        3 * nbp * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  S.seg.assign(reinterpret_cast<int*>(hp), reinterpret_cast<int*>(hp) + 2 * (nbp + 1));
+  const unsigned long long* qs =
+      reinterpret_cast<const unsigned long long*>(hp + 2 * (nbp + 1) * sizeof(int));
+  S.qstat.assign(qs, qs + 3 * nbp);
+  const int nitems = S.seg[2 * nbp + 1];
+  S.items = dev<int4>(c, sItems, std::max(nitems, 1));
+  hipLaunchKernelGGL(expand_kernel, dim3(grid_of(nt, 256)), dim3(256), 0, s, nt, d_bp + 2 * nbp,
+                     nbp, d_cnt, d_off, d_rng, S.items);
+  HIP_OK(hipGetLastError());
+  return S;
+}
+
+int check_opts(const jk_opts* o, jk_opts* out, std::string* msg) {
+  jk_opts_default(out);
+  if (o) *out = *o;
+  if (out->precision != JK_FP64 && out->precision != JK_MIXED) { *msg = "opts.precision"; return JK_EINVAL; }
+  if (!(out->fp32_below >= 0.0) || !std::isfinite(out->fp32_below)) { *msg = "opts.fp32_below"; return JK_EINVAL; }
+  if (!(out->boys_fp64_T > 0.0 && out->boys_fp64_T <= 30.0)) { *msg = "opts.boys_fp64_T must be in (0, 30]"; return JK_EINVAL; }
+  if (out->n_dm < 1 || out->n_dm > JK_MAX_NDM) { *msg = "opts.n_dm must be in 1..16"; return JK_EINVAL; }
+  if (out->deterministic != 0) { *msg = "deterministic mode is not implemented"; return JK_EUNSUPPORTED; }
+  if (out->timing != 0 && out->timing != 1) { *msg = "opts.timing"; return JK_EINVAL; }
+  return JK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int jk_opts_default(jk_opts* o) {
+  if (!o) return JK_EINVAL;
+  o->precision = JK_FP64;
+  o->fp32_below = 1e-4;
+  o->boys_fp64_T = 30.0;
+  o->n_dm = 1;
+  o->deterministic = 0;
+  o->timing = 0;
+  o->max_scratch_bytes = 0;
+  return JK_OK;
+}
+
+int jk_validate_basis(const jk_basis* basis, int32_t* n_bf_out) { return validate(basis, n_bf_out); }
+
+int jk_ctx_create(jk_ctx** out, int device) {
+  if (!out) return JK_EINVAL;
+  *out = nullptr;
+  jk_ctx* c = new (std::nothrow) jk_ctx;
+  if (!c) return JK_ENOMEM;
+  try {
+    int ndev = 0;
+    HIP_OK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) throw Fail{JK_EINVAL, "no such device"};
+    c->device = device;
+    HIP_OK(hipSetDevice(device));
+    std::vector<double> t64;
+    std::vector<float> t32;
+    make_boys_tables(t64, t32);
+    HIP_OK(hipMalloc(&c->boys64, t64.size() * sizeof(double)));
+    HIP_OK(hipMalloc(&c->boys32, t32.size() * sizeof(float)));
+    HIP_OK(hipMemcpy(c->boys64, t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->boys32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
+  } catch (const Fail& f) {
+    g_create_err = f.msg;
+    jk_ctx_destroy(c);
+    return f.code;
+  }
+  *out = c;
+  return JK_OK;
+}
+
+int jk_ctx_destroy(jk_ctx* c) {
+  if (!c) return JK_OK;
+  (void)hipSetDevice(c->device);
+  for (auto& b : c->buf)
+    if (b.p) (void)hipFree(b.p);
+  if (c->boys64) (void)hipFree(c->boys64);
+  if (c->boys32) (void)hipFree(c->boys32);
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+  delete c;
+  return JK_OK;
+}
+
+const char* jk_last_error(const jk_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, double* K, double tol,
+             const jk_opts* opts, void* hip_stream) {
+  if (!c) return JK_EINVAL;
+  c->err.clear();
+  int32_t nbf = 0;
+  int rc = validate(basis, &nbf);
+  if (rc != JK_OK) { c->err = validate_msg(rc); return rc; }
+  if (!D || !J || !K) { c->err = "D, J and K must be device pointers"; return JK_EINVAL; }
+  if (!(tol >= 0.0) || !std::isfinite(tol)) { c->err = "tol must be finite and >= 0"; return JK_EINVAL; }
+  jk_opts o;
+  rc = check_opts(opts, &o, &c->err);
+  if (rc != JK_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  try {
+    HIP_OK(hipSetDevice(c->device));
+    c->scratch_limit = o.max_scratch_bytes;
+    c->timed = o.timing == 1;
+    c->ev_used = 0;
+    c->timed_launches.clear();
+    if (c->timed) c->ev_setup0 = event(c, s);
+    Setup S = setup(c, basis, tol, o, s);
+    const Plan& P = S.P;
+    if (c->timed) c->ev_setup1 = event(c, s);
+    const size_t nn = static_cast<size_t>(nbf) * nbf;
+    hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(nn * o.n_dm, 256)), dim3(256), 0, s, nn * o.n_dm, J);
+    hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(nn * o.n_dm, 256)), dim3(256), 0, s, nn * o.n_dm, K);
+    HIP_OK(hipGetLastError());
+
+    jk_stats st{};
+    for (int q = 0; q < JK_NCLASS; ++q) {
+      int X = 0;
+      while ((X + 1) * (X + 2) / 2 <= q) ++X;
+      const int Y = q - X * (X + 1) / 2;
+      st.class_l[q][0] = kPairL[X][0];
+      st.class_l[q][1] = kPairL[X][1];
+      st.class_l[q][2] = kPairL[Y][0];
+      st.class_l[q][3] = kPairL[Y][1];
+    }
+    st.n_pairs = P.npairs;
+    const int nbp = static_cast<int>(P.bp_x.size());
+    st.work_items = S.seg[2 * nbp + 1];
+    for (int bp = 0; bp < nbp; ++bp) {
+      const int X = P.bp_x[bp], Y = P.bp_y[bp];
+      const int cls = quartet_class(P.bin_cls[X], P.bin_cls[Y]);
+      st.quartets_fp64[cls] += static_cast<int64_t>(S.qstat[3 * bp]);
+      st.quartets_fp32[cls] += static_cast<int64_t>(S.qstat[3 * bp + 1]);
+      st.quartets_skipped += static_cast<int64_t>(S.qstat[3 * bp + 2]);
+      for (int pr = 0; pr < 2; ++pr) {
+        const int i0 = S.seg[pr * (nbp + 1) + bp], i1 = S.seg[pr * (nbp + 1) + bp + 1];
+        if (i1 <= i0) continue;
+        EriLaunch a{};
+        a.bra = bin_view(P, X, S.prim, S.A, S.AB, S.bf, S.atoms, S.fpair, S.Q);
+        a.ket = bin_view(P, Y, S.prim, S.A, S.AB, S.bf, S.atoms, S.fpair, S.Q);
+        a.items = S.items + i0;
+        a.nitems = i1 - i0;
+        a.same_bin = X == Y;
+        a.D = D;
+        a.J = J;
+        a.K = K;
+        a.n = nbf;
+        a.n_dm = o.n_dm;
+        a.boys64 = c->boys64;
+        a.boys32 = c->boys32;
+        a.boys_fp64_T = static_cast<float>(o.boys_fp64_T);
+        size_t e0 = 0;
+        if (c->timed) e0 = event(c, s);
+        launch_eri(cls, pr, a, s);
+        HIP_OK(hipGetLastError());
+        if (c->timed) {
+          event(c, s);
+          c->timed_launches.push_back({cls, pr, e0});
+        }
+        (pr ? st.launches_fp32 : st.launches_fp64)[cls] += 1;
+      }
+    }
+    hipLaunchKernelGGL(finalize_kernel, dim3(grid_of(nn * o.n_dm, 256)), dim3(256), 0, s, nbf,
+                       o.n_dm, J, K);
+    HIP_OK(hipGetLastError());
+    if (c->timed) c->ev_end = event(c, s);
+    c->stats = st;
+  } catch (const Fail& f) {
+    c->err = f.msg;
+    return f.code;
+  }
+  return JK_OK;
+}
+
+int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, double tol,
+            const jk_opts* opts, void* hip_stream) {
+  if (!c) return JK_EINVAL;
+  c->err.clear();
+  int32_t nbf = 0;
+  int rc = validate(basis, &nbf);
+  if (rc != JK_OK) { c->err = validate_msg(rc); return rc; }
+  if (!D || !dEdR) { c->err = "D and dEdR must be device pointers"; return JK_EINVAL; }
+  if (!(tol >= 0.0) || !std::isfinite(tol)) { c->err = "tol must be finite and >= 0"; return JK_EINVAL; }
+  jk_opts o;
+  rc = check_opts(opts, &o, &c->err);
+  if (rc != JK_OK) return rc;
+  (void)hip_stream;
+  c->err = "nuclear gradient kernels are not built in this version";
+  return JK_EUNSUPPORTED;
+}
+
+int jk_get_stats(jk_ctx* c, jk_stats* out) {
+  if (!c || !out) return JK_EINVAL;
+  jk_stats st = c->stats;
+  if (c->timed && c->ev_used > 0) {
+    try {
+      HIP_OK(hipEventSynchronize(c->ev_pool[c->ev_end]));
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, c->ev_pool[c->ev_setup0], c->ev_pool[c->ev_setup1]));
+      st.ms_setup = ms;
+      HIP_OK(hipEventElapsedTime(&ms, c->ev_pool[c->ev_setup0], c->ev_pool[c->ev_end]));
+      st.ms_total = ms;
+      for (auto& t : c->timed_launches) {
+        HIP_OK(hipEventElapsedTime(&ms, c->ev_pool[t.e0], c->ev_pool[t.e0 + 1]));
+        (t.fp32 ? st.ms_kernel_fp32 : st.ms_kernel_fp64)[t.cls] += ms;
+      }
+    } catch (const Fail& f) {
+      c->err = f.msg;
+      return f.code;
+    }
+  }
+  *out = st;
+  return JK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,256 @@
+"""ctypes binding of libjk.so (argument marshalling only).
+
+The names mirror the C ABI in include/jk.h: jk_opts_default, jk_ctx_create,
+jk_ctx_destroy, jk_validate_basis, jk_build, jk_grad, jk_get_stats,
+jk_last_error.  All arithmetic runs in the library's HIP kernels; PyTorch only
+supplies device memory and the current stream.  If libjk.so is missing the
+import fails loudly -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjk.so")
+
+JK_OK, JK_EINVAL, JK_EUNSUPPORTED, JK_ENOMEM, JK_EHIP = 0, 1, 2, 3, 4
+JK_FP64, JK_MIXED = 0, 1
+JK_NCLASS = 21
+JK_MAX_NDM = 16
+ERR_NAMES = {1: "JK_EINVAL", 2: "JK_EUNSUPPORTED", 3: "JK_ENOMEM", 4: "JK_EHIP"}
+
+EXPORTS = ["jk_opts_default", "jk_ctx_create", "jk_ctx_destroy", "jk_validate_basis", "jk_build",
+           "jk_grad", "jk_get_stats", "jk_last_error"]
+
+
+class JkError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class jk_basis(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("xyz", ctypes.POINTER(ctypes.c_double)),
+                ("n_shells", ctypes.c_int32), ("shell_atom", ctypes.POINTER(ctypes.c_int32)),
+                ("shell_l", ctypes.POINTER(ctypes.c_int32)),
+                ("shell_nprim", ctypes.POINTER(ctypes.c_int32)),
+                ("shell_prim0", ctypes.POINTER(ctypes.c_int32)),
+                ("exps", ctypes.POINTER(ctypes.c_double)),
+                ("coefs", ctypes.POINTER(ctypes.c_double))]
+
+
+class jk_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("fp32_below", ctypes.c_double),
+                ("boys_fp64_T", ctypes.c_double), ("n_dm", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("max_scratch_bytes", ctypes.c_uint64)]
+
+
+class jk_stats(ctypes.Structure):
+    _fields_ = [("quartets_fp64", ctypes.c_int64 * JK_NCLASS),
+                ("quartets_fp32", ctypes.c_int64 * JK_NCLASS),
+                ("quartets_skipped", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
+                ("work_items", ctypes.c_int64),
+                ("ms_kernel_fp64", ctypes.c_double * JK_NCLASS),
+                ("ms_kernel_fp32", ctypes.c_double * JK_NCLASS),
+                ("ms_setup", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("launches_fp64", ctypes.c_int32 * JK_NCLASS),
+                ("launches_fp32", ctypes.c_int32 * JK_NCLASS),
+                ("class_l", (ctypes.c_int32 * 4) * JK_NCLASS)]
+
+
+_lib = None
+
+
+def load():
+    """Load libjk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run python -m paper_2406_11185_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.jk_opts_default.argtypes = [ctypes.POINTER(jk_opts)]
+    lib.jk_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+    lib.jk_ctx_destroy.argtypes = [vp]
+    lib.jk_validate_basis.argtypes = [ctypes.POINTER(jk_basis), ctypes.POINTER(ctypes.c_int32)]
+    lib.jk_build.argtypes = [vp, ctypes.POINTER(jk_basis), vp, vp, vp, ctypes.c_double,
+                             ctypes.POINTER(jk_opts), vp]
+    lib.jk_grad.argtypes = [vp, ctypes.POINTER(jk_basis), vp, vp, ctypes.c_double,
+                            ctypes.POINTER(jk_opts), vp]
+    lib.jk_get_stats.argtypes = [vp, ctypes.POINTER(jk_stats)]
+    lib.jk_last_error.argtypes = [vp]
+    lib.jk_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class Basis:
+    """Host arrays of a molecule's basis (fields as in molgen.Molecule) and the C struct."""
+
+    def __init__(self, mol):
+        self.xyz = np.ascontiguousarray(mol.xyz, dtype=np.float64)
+        self.shell_atom = np.ascontiguousarray(mol.shell_atom, dtype=np.int32)
+        self.shell_l = np.ascontiguousarray(mol.shell_l, dtype=np.int32)
+        self.shell_nprim = np.ascontiguousarray(mol.shell_nprim, dtype=np.int32)
+        self.shell_prim0 = np.ascontiguousarray(mol.shell_prim0, dtype=np.int32)
+        self.exps = np.ascontiguousarray(mol.exps, dtype=np.float64)
+        self.coefs = np.ascontiguousarray(mol.coefs, dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        self.c = jk_basis(self.xyz.shape[0], self.xyz.ctypes.data_as(dp),
+                          self.shell_l.shape[0], self.shell_atom.ctypes.data_as(ip),
+                          self.shell_l.ctypes.data_as(ip), self.shell_nprim.ctypes.data_as(ip),
+                          self.shell_prim0.ctypes.data_as(ip), self.exps.ctypes.data_as(dp),
+                          self.coefs.ctypes.data_as(dp))
+
+    @property
+    def n_atoms(self):
+        return int(self.xyz.shape[0])
+
+
+def jk_opts_default() -> jk_opts:
+    o = jk_opts()
+    load().jk_opts_default(ctypes.byref(o))
+    return o
+
+
+def make_opts(precision="fp64", fp32_below=1e-4, n_dm=1, timing=False, boys_fp64_T=30.0,
+              max_scratch_bytes=0, deterministic=0) -> jk_opts:
+    o = jk_opts_default()
+    o.precision = {"fp64": JK_FP64, "mixed": JK_MIXED}[precision] if isinstance(precision, str) \
+        else int(precision)
+    o.fp32_below = float(fp32_below)
+    o.n_dm = int(n_dm)
+    o.timing = 1 if timing else 0
+    o.boys_fp64_T = float(boys_fp64_T)
+    o.max_scratch_bytes = int(max_scratch_bytes)
+    o.deterministic = int(deterministic)
+    return o
+
+
+def jk_validate_basis(basis: Basis) -> int:
+    n = ctypes.c_int32(0)
+    rc = load().jk_validate_basis(ctypes.byref(basis.c), ctypes.byref(n))
+    if rc != JK_OK:
+        raise JkError(rc, "invalid basis")
+    return int(n.value)
+
+
+def jk_last_error(ctx) -> str:
+    h = ctx.h if isinstance(ctx, Context) else ctx
+    return load().jk_last_error(h).decode()
+
+
+class Context:
+    """Owns a jk_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        rc = lib.jk_ctx_create(ctypes.byref(h), int(device))
+        if rc != JK_OK:
+            raise JkError(rc, lib.jk_last_error(None).decode())
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().jk_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != JK_OK:
+            raise JkError(rc, jk_last_error(self))
+
+    def stats(self) -> jk_stats:
+        st = jk_stats()
+        self._check(load().jk_get_stats(self.h, ctypes.byref(st)))
+        return st
+
+
+_default_ctx = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def _stream_ptr(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_dev(t, shape, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+        raise ValueError(f"{name}: expected a contiguous float64 CUDA tensor of shape {shape}")
+
+
+def jk_build(ctx: Context, basis: Basis, D, J, K, tol: float, opts: jk_opts | None = None,
+             stream=None) -> None:
+    """Direct binding: D, J, K are float64 device tensors [n_dm][n][n]."""
+    import torch
+    s = stream if stream is not None else _stream_ptr(torch, D.device)
+    rc = load().jk_build(ctx.h, ctypes.byref(basis.c), ctypes.c_void_p(D.data_ptr()),
+                         ctypes.c_void_p(J.data_ptr()), ctypes.c_void_p(K.data_ptr()),
+                         float(tol), ctypes.byref(opts) if opts is not None else None, s)
+    ctx._check(rc)
+
+
+def jk_grad(ctx: Context, basis: Basis, D, dEdR, tol: float, opts: jk_opts | None = None,
+            stream=None) -> None:
+    import torch
+    s = stream if stream is not None else _stream_ptr(torch, D.device)
+    rc = load().jk_grad(ctx.h, ctypes.byref(basis.c), ctypes.c_void_p(D.data_ptr()),
+                        ctypes.c_void_p(dEdR.data_ptr()), float(tol),
+                        ctypes.byref(opts) if opts is not None else None, s)
+    ctx._check(rc)
+
+
+def jk(mol, D, tol: float, precision: str = "fp64", fp32_below: float = 1e-4,
+       timing: bool = False, ctx: Context | None = None):
+    """J, K for the densities D ([n][n] or [n_dm][n][n] float64 CUDA tensor)."""
+    import torch
+    basis = mol if isinstance(mol, Basis) else Basis(mol)
+    squeeze = D.dim() == 2
+    Dd = D.unsqueeze(0) if squeeze else D
+    Dd = Dd.contiguous()
+    n_dm, n = Dd.shape[0], Dd.shape[1]
+    _check_dev(Dd, (n_dm, n, n), "D")
+    ctx = ctx or default_context(Dd.device.index or 0)
+    J = torch.empty_like(Dd)
+    K = torch.empty_like(Dd)
+    opts = make_opts(precision, fp32_below, n_dm, timing)
+    jk_build(ctx, basis, Dd, J, K, tol, opts)
+    if squeeze:
+        return J[0], K[0]
+    return J, K
+
+
+def grad(mol, D, tol: float, precision: str = "fp64", fp32_below: float = 1e-4,
+         ctx: Context | None = None):
+    """dE/dR ([n_atoms][3] or [n_dm][n_atoms][3]) of E = 1/2 tr(DJ) - 1/4 tr(DK)."""
+    import torch
+    basis = mol if isinstance(mol, Basis) else Basis(mol)
+    squeeze = D.dim() == 2
+    Dd = (D.unsqueeze(0) if squeeze else D).contiguous()
+    n_dm, n = Dd.shape[0], Dd.shape[1]
+    _check_dev(Dd, (n_dm, n, n), "D")
+    ctx = ctx or default_context(Dd.device.index or 0)
+    G = torch.empty((n_dm, basis.n_atoms, 3), dtype=torch.float64, device=Dd.device)
+    opts = make_opts(precision, fp32_below, n_dm)
+    jk_grad(ctx, basis, Dd, G, tol, opts)
+    return G[0] if squeeze else G
