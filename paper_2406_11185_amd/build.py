@@ -11,6 +11,7 @@ from __future__ import annotations
 import argparse
 import concurrent.futures as cf
 import os
+import shutil
 import subprocess
 import sys
 import time
@@ -46,7 +47,8 @@ def _deps_newer(src: str, obj: str) -> bool:
         return True
     t = os.path.getmtime(obj)
     deps = [src, src.replace(".hip", ".inc"), os.path.join(CSRC, "jk_device.hpp"),
-            os.path.join(CSRC, "jk_classes.hpp"), os.path.join(INCLUDE, "jk.h")]
+            os.path.join(CSRC, "jk_grad_device.hpp"), os.path.join(CSRC, "jk_classes.hpp"),
+            os.path.join(INCLUDE, "jk.h")]
     return any(os.path.exists(d) and os.path.getmtime(d) > t for d in deps)
 
 
@@ -70,12 +72,17 @@ def build(jobs: int = 0, verbose: bool = False, incremental: bool = False) -> st
     sys.path.insert(0, CSRC)
     try:
         import gen_hgp  # noqa: E402
+        import gen_grad  # noqa: E402
     finally:
         sys.path.pop(0)
     gen_hgp.main(GEN)
-    sources = [os.path.join(CSRC, "jk_host.hip"), os.path.join(GEN, "jk_classes_table.hip")]
+    gen_grad.main(GEN)
+    shutil.copyfile(os.path.join(GEN, "classes.json"), os.path.join(PKG, "classes.json"))
+    shutil.copyfile(os.path.join(GEN, "grad_classes.json"), os.path.join(PKG, "grad_classes.json"))
+    sources = [os.path.join(CSRC, "jk_host.hip"), os.path.join(GEN, "jk_classes_table.hip"),
+               os.path.join(GEN, "jk_grad_table.hip")]
     sources += sorted(os.path.join(GEN, f) for f in os.listdir(GEN)
-                      if f.startswith("cls_") and f.endswith(".hip"))
+                      if (f.startswith("cls_") or f.startswith("gcls_")) and f.endswith(".hip"))
     # largest classes first so the long compiles start early
     sources.sort(key=lambda p: -os.path.getsize(p.replace(".hip", ".inc"))
                  if os.path.exists(p.replace(".hip", ".inc")) else 0)

@@ -307,7 +307,8 @@ def gen_class(la, lb, lc, ld):
     s.append("};")
     info = dict(name=name, la=la, lb=lb, lc=lc, ld=ld, L=L, nacc=ne * nf,
                 nint=na * nb * nc * nd, vrr_flops=vrr_flops, hrr_flops=hrr_flops,
-                digest_flops=dig_flops, vrr_nodes=vrr.n, hrr_nodes=hrr.n)
+                digest_flops=dig_flops, vrr_nodes=vrr.n, hrr_nodes=hrr.n,
+                vrr_flops_alg=vrr_flops)
     return "\n".join(s) + "\n", info
 
 
@@ -444,9 +445,14 @@ def gen_split_class(la, lb, lc, ld):
     for j, ch in enumerate(chunks):
         s.append(f"template <> struct Cls_{name}::Pass<{j}> {{ static constexpr int F0 = {ch[0]}, "
                  f"NF = {len(ch)}; }};")
+    one = VRR(L)
+    for e in E:
+        for f in Fs:
+            one.node(e, f, 0)
     info = dict(name=name, la=la, lb=lb, lc=lc, ld=ld, L=L, nacc=ne * nf,
                 nint=na * nb * nc * nd, vrr_flops=vrr_flops, hrr_flops=hrr_flops,
-                digest_flops=dig_flops, npass=len(chunks), split=True)
+                digest_flops=dig_flops, npass=len(chunks), split=True,
+                vrr_flops_alg=one.flops + ne * nf)
     return "\n".join(s) + "\n", info
 
 

@@ -1,0 +1,255 @@
+// Nuclear-gradient kernel of the J/K energy E = 1/2 tr(DJ) - 1/4 tr(DK) at
+// fixed D, for gfx950.  Shares the pair data, Boys tables, screening and work
+// items of the J/K build; the per-class code comes from gen_grad.py.
+#pragma once
+#include "jk_device.hpp"
+
+namespace jk {
+
+struct GradLaunch {
+  EriLaunch e;      // pair data, items, D, Boys tables (J, K unused)
+  double* dEdR;     // [n_dm][n_atoms][3]
+  int n_atoms;
+};
+
+// Contraction loop with the exponent weights of the derivative integrals:
+// wA = 2a, wB = 2b (bra primitives), wC = 2c (first ket primitive).
+template <int L, typename T, class V>
+__device__ __forceinline__ void contract_w(const EriLaunch& a, int i, int k, T ACx, T ACy, T ACz,
+                                           V&& vrr) {
+  const int nb = a.bra.n, nk = a.ket.n;
+  const int nppb = a.bra.npp, nppk = a.ket.npp;
+  for (int kl = 0; kl < nppk; ++kl) {
+    const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
+    const T q = T(kp[kP * nk]), oo2q = T(kp[kOo2p * nk]);
+    const T QCx = T(kp[kPAx * nk]), QCy = T(kp[kPAy * nk]), QCz = T(kp[kPAz * nk]);
+    const T Kcd = T(kp[kKt * nk]), wC = T(kp[kTwoA * nk]);
+    for (int ij = 0; ij < nppb; ++ij) {
+      const double* bp = a.bra.prim + static_cast<size_t>(ij) * kPrimFields * nb + i;
+      T F[L + 1];
+      VrrCoef<T> c;
+      prim_setup<L, T>(T(bp[kP * nb]), T(bp[kOo2p * nb]), T(bp[kPAx * nb]), T(bp[kPAy * nb]),
+                       T(bp[kPAz * nb]), T(bp[kKt * nb]), q, oo2q, QCx, QCy, QCz, Kcd, ACx, ACy,
+                       ACz, a, F, c);
+      vrr(F, c, T(bp[kTwoA * nb]), T(bp[kTwoB * nb]), wC);
+    }
+  }
+}
+
+template <class C, typename T, int J>
+__device__ __forceinline__ void grad_pass_body(const EriLaunch& a, int i, int k, T ACx, T ACy,
+                                               T ACz, T* G, int z) {
+  constexpr int N = C::template Pass<J>::N;
+  T acc[N];
+#pragma unroll
+  for (int t = 0; t < N; ++t) acc[t] = T(0);
+  contract_w<C::L, T>(a, i, k, ACx, ACy, ACz,
+                      [&](const T* F, const VrrCoef<T>& c, T wA, T wB, T wC) {
+                        C::template vrr_pass<J, T>(F, c, wA, wB, wC, acc);
+                      });
+  C::template store_pass<J, T>(acc, G, z);
+}
+
+// Classes with many passes call each pass as a separate function, so that the
+// compiler allocates registers pass by pass.
+template <class C, typename T, int J>
+__device__ __attribute__((noinline)) void grad_pass_call(const EriLaunch& a, int i, int k, T ACx,
+                                                          T ACy, T ACz, T* G, int z) {
+  grad_pass_body<C, T, J>(a, i, k, ACx, ACy, ACz, G, z);
+}
+
+template <class C, typename T, int J>
+__device__ __forceinline__ void grad_passes(const EriLaunch& a, int i, int k, T ACx, T ACy, T ACz,
+                                            T* G, int z) {
+  if constexpr (C::NPASS > 4)
+    grad_pass_call<C, T, J>(a, i, k, ACx, ACy, ACz, G, z);
+  else
+    grad_pass_body<C, T, J>(a, i, k, ACx, ACy, ACz, G, z);
+  if constexpr (J + 1 < C::NPASS) grad_passes<C, T, J + 1>(a, i, k, ACx, ACy, ACz, G, z);
+}
+
+constexpr int at_least_1(int v) { return v > 0 ? v : 1; }
+
+// One wavefront per work item; bra pair uniform, one ket pair per lane.
+template <class C, typename T>
+__global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
+  constexpr int NCD = C::NC * C::ND;
+  constexpr int NAB = C::NA * C::NB;
+  const EriLaunch& a = g.e;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (item >= a.nitems) return;
+  const int4 w = a.items[item];
+  const int i = __builtin_amdgcn_readfirstlane(w.x);
+  const int kbeg = __builtin_amdgcn_readfirstlane(w.y);
+  const int kend = __builtin_amdgcn_readfirstlane(w.z);
+  const int nb = a.bra.n, nk = a.ket.n;
+  const size_t n = static_cast<size_t>(a.n);
+  const size_t nn = n * n;
+  const double Ax = a.bra.A[i], Ay = a.bra.A[nb + i], Az = a.bra.A[2 * nb + i];
+  const T ABx = T(a.bra.AB[i]), ABy = T(a.bra.AB[nb + i]), ABz = T(a.bra.AB[2 * nb + i]);
+  const int a0 = a.bra.bf[i], b0 = a.bra.bf[nb + i];
+  const int atA = a.bra.atoms[i], atB = a.bra.atoms[nb + i];
+  const double fbra = a.bra.fpair[i];
+  const int z = opaque_zero();
+
+  for (int kc = kbeg; kc < kend; kc += kWave) {
+    const bool active = kc + lane < kend;
+    const int k = active ? kc + lane : kend - 1;
+    const T ACx = T(Ax - a.ket.A[k]), ACy = T(Ay - a.ket.A[nk + k]),
+            ACz = T(Az - a.ket.A[2 * nk + k]);
+    T G[C::NG];
+    grad_passes<C, T, 0>(a, i, k, ACx, ACy, ACz, G, z);
+    const T CDx = T(a.ket.AB[k]), CDy = T(a.ket.AB[nk + k]), CDz = T(a.ket.AB[2 * nk + k]);
+
+    // ket horizontal recurrences, one bra index e at a time
+    T XA[C::NE_A * NCD], XB[C::NE_B * NCD], XC[C::NE_C * C::NCP];
+    T XU[at_least_1(C::NE_U * NCD)], XV[at_least_1(C::NE_U * C::NCM)];
+#pragma nounroll
+    for (int e = 0; e < C::NE_A; ++e) {
+      T f[C::NF_A], o[NCD];
+#pragma unroll
+      for (int t = 0; t < C::NF_A; ++t) f[t] = G[z + C::OFF_A + e * C::NF_A + t];
+      C::template ket_b<T>(f, CDx, CDy, CDz, o);
+#pragma unroll
+      for (int t = 0; t < NCD; ++t) XA[z + e * NCD + t] = o[t];
+    }
+#pragma nounroll
+    for (int e = 0; e < C::NE_B; ++e) {
+      T f[C::NF_B], o[NCD];
+#pragma unroll
+      for (int t = 0; t < C::NF_B; ++t) f[t] = G[z + C::OFF_B + e * C::NF_B + t];
+      C::template ket_b<T>(f, CDx, CDy, CDz, o);
+#pragma unroll
+      for (int t = 0; t < NCD; ++t) XB[z + e * NCD + t] = o[t];
+    }
+#pragma nounroll
+    for (int e = 0; e < C::NE_C; ++e) {
+      T f[C::NF_C], o[C::NCP];
+#pragma unroll
+      for (int t = 0; t < C::NF_C; ++t) f[t] = G[z + C::OFF_C + e * C::NF_C + t];
+      C::template ket_p<T>(f, CDx, CDy, CDz, o);
+#pragma unroll
+      for (int t = 0; t < C::NCP; ++t) XC[z + e * C::NCP + t] = o[t];
+    }
+    if constexpr (C::USE_U) {
+#pragma nounroll
+      for (int e = 0; e < C::NE_U; ++e) {
+        T f[C::NF_U], o[NCD];
+#pragma unroll
+        for (int t = 0; t < C::NF_U; ++t) f[t] = G[z + C::OFF_U + e * C::NF_U + t];
+        C::template ket_b<T>(f + C::U_FB, CDx, CDy, CDz, o);
+#pragma unroll
+        for (int t = 0; t < NCD; ++t) XU[z + e * NCD + t] = o[t];
+        if constexpr (C::NCM > 0) {
+          T om[at_least_1(C::NCM)];
+          C::template ket_m<T>(f, CDx, CDy, CDz, om);
+#pragma unroll
+          for (int t = 0; t < C::NCM; ++t) XV[z + e * C::NCM + t] = om[t];
+        }
+      }
+    }
+
+    const int c0 = a.ket.bf[k], d0 = a.ket.bf[nk + k];
+    const int atC = a.ket.atoms[k], atD = a.ket.atoms[nk + k];
+    const double fq =
+        active ? 8.0 * fbra * a.ket.fpair[k] * ((a.same_bin && k == i) ? 0.5 : 1.0) : 0.0;
+
+    for (int m = 0; m < a.n_dm; ++m) {
+      const double* Dm = a.D + m * nn;
+      double Dab[NAB];
+#pragma unroll
+      for (int x = 0; x < C::NA; ++x)
+#pragma unroll
+        for (int y = 0; y < C::NB; ++y) Dab[x * C::NB + y] = Dm[(a0 + x) * n + b0 + y];
+      double gA[3] = {0.0, 0.0, 0.0}, gB[3] = {0.0, 0.0, 0.0}, gC[3] = {0.0, 0.0, 0.0};
+#pragma nounroll
+      for (int cd = 0; cd < NCD; ++cd) {
+        const int c = cd / C::ND, d = cd % C::ND;
+        const double Dcd = Dm[(c0 + c) * n + d0 + d];
+        double Dac[C::NA], Dad[C::NA], Dbc[C::NB], Dbd[C::NB];
+#pragma unroll
+        for (int x = 0; x < C::NA; ++x) {
+          Dac[x] = Dm[(a0 + x) * n + c0 + c];
+          Dad[x] = Dm[(a0 + x) * n + d0 + d];
+        }
+#pragma unroll
+        for (int y = 0; y < C::NB; ++y) {
+          Dbc[y] = Dm[(b0 + y) * n + c0 + c];
+          Dbd[y] = Dm[(b0 + y) * n + d0 + d];
+        }
+        double Gam[NAB];
+#pragma unroll
+        for (int x = 0; x < C::NA; ++x)
+#pragma unroll
+          for (int y = 0; y < C::NB; ++y)
+            Gam[x * C::NB + y] = 0.5 * Dab[x * C::NB + y] * Dcd -
+                                 0.125 * (Dac[x] * Dbd[y] + Dad[x] * Dbc[y]);
+        // centres A and B
+        T ea[C::NE_A], eb[C::NE_B];
+#pragma unroll
+        for (int e = 0; e < C::NE_A; ++e) ea[e] = XA[z + e * NCD + cd];
+#pragma unroll
+        for (int e = 0; e < C::NE_B; ++e) eb[e] = XB[z + e * NCD + cd];
+        T xap[(C::NA + C::LA + 2) * C::NB + 8], xbp[C::NA * (C::NB + C::LB + 2) + 8];
+        C::template bra_ap<T>(ea, ABx, ABy, ABz, xap);
+        C::template bra_bp<T>(eb, ABx, ABy, ABz, xbp);
+        T xam[at_least_1(C::LA >= 1 ? C::NA * C::NB : 0)];
+        T xbm[at_least_1(C::LB >= 1 ? C::NA * C::NB : 0)];
+        if constexpr (C::LA >= 1) {
+          T em[at_least_1(C::NE_AM)];
+#pragma unroll
+          for (int e = 0; e < C::NE_AM; ++e) em[e] = XU[z + e * NCD + cd];
+          C::template bra_am<T>(em, ABx, ABy, ABz, xam);
+        }
+        if constexpr (C::LB >= 1) {
+          T em[at_least_1(C::NE_BM)];
+#pragma unroll
+          for (int e = 0; e < C::NE_BM; ++e) em[e] = XU[z + (C::U_EB + e) * NCD + cd];
+          C::template bra_bm<T>(em, ABx, ABy, ABz, xbm);
+        }
+        C::template contract_ab<T>(Gam, xap, xam, xbp, xbm, gA, gB);
+        // centre C
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+          const int cp = C::CPLUS[c][x];
+          T e0[C::NE_0], x0[NAB];
+#pragma unroll
+          for (int e = 0; e < C::NE_0; ++e) e0[e] = XC[z + e * C::NCP + cp * C::ND + d];
+          C::template bra_0<T>(e0, ABx, ABy, ABz, x0);
+          gC[x] += C::template dot0<T>(Gam, x0);
+          if constexpr (C::LC >= 1) {
+            const int pw = C::CPOW[c][x];
+            if (pw > 0) {
+              const int cm = C::CMINUS[c][x];
+#pragma unroll
+              for (int e = 0; e < C::NE_0; ++e)
+                e0[e] = XV[z + (C::U_EB + e) * C::NCM + cm * C::ND + d];
+              C::template bra_0<T>(e0, ABx, ABy, ABz, x0);
+              gC[x] -= pw * C::template dot0<T>(Gam, x0);
+            }
+          }
+        }
+      }
+      double* G3 = g.dEdR + static_cast<size_t>(m) * g.n_atoms * 3;
+#pragma unroll
+      for (int x = 0; x < 3; ++x) {
+        const double ga = fq * gA[x], gb = fq * gB[x], gc = fq * gC[x];
+        const double gd = -(ga + gb + gc);
+        const double sa = wave_sum(ga), sb = wave_sum(gb);
+        if (lane == 0) {
+          atomic_add(&G3[atA * 3 + x], sa);
+          atomic_add(&G3[atB * 3 + x], sb);
+        }
+        if (active) {
+          atomic_add(&G3[atC * 3 + x], gc);
+          atomic_add(&G3[atD * 3 + x], gd);
+        }
+      }
+    }
+  }
+}
+
+void launch_grad(int cls, int fp32, const GradLaunch& a, hipStream_t s);
+
+}  // namespace jk

@@ -35,6 +35,7 @@
 #include "jk.h"
 #include "jk_device.hpp"
 #include "jk_classes.hpp"
+#include "jk_grad_device.hpp"
 
 using namespace jk;
 
@@ -149,7 +150,7 @@ __global__ void pair_data_kernel(int npairs, const int* __restrict__ pair_s1,
   out.atoms[2 * bin_off[b] + t] = sh.atom[s1];
   out.atoms[2 * bin_off[b] + n + t] = sh.atom[s2];
   out.fpair[bin_off[b] + t] = (s1 == s2) ? 0.5 : 1.0;
-  const double kSqrt2Pi54 = 1.4142135623730950488 * 4.1798707165334034;  // sqrt(2) pi^{5/4}
+  const double kSqrt2Pi54 = 5.9149671727956128778;  // sqrt(2) * pi^(5/4)
   const int n1 = sh.nprim[s1], n2 = sh.nprim[s2];
   double* prim = out.prim + bin_prim_off[b];
   for (int u = 0; u < n1; ++u)
@@ -624,6 +625,48 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
   return S;
 }
 
+jk_stats base_stats(const Plan& P, const Setup& S) {
+  jk_stats st{};
+  for (int q = 0; q < JK_NCLASS; ++q) {
+    int X = 0;
+    while ((X + 1) * (X + 2) / 2 <= q) ++X;
+    const int Y = q - X * (X + 1) / 2;
+    st.class_l[q][0] = kPairL[X][0];
+    st.class_l[q][1] = kPairL[X][1];
+    st.class_l[q][2] = kPairL[Y][0];
+    st.class_l[q][3] = kPairL[Y][1];
+  }
+  st.n_pairs = P.npairs;
+  const int nbp = static_cast<int>(P.bp_x.size());
+  st.work_items = S.seg[2 * nbp + 1];
+  for (int bp = 0; bp < nbp; ++bp) {
+    const int cls = quartet_class(P.bin_cls[P.bp_x[bp]], P.bin_cls[P.bp_y[bp]]);
+    st.quartets_fp64[cls] += static_cast<int64_t>(S.qstat[3 * bp]);
+    st.quartets_fp32[cls] += static_cast<int64_t>(S.qstat[3 * bp + 1]);
+    st.quartets_skipped += static_cast<int64_t>(S.qstat[3 * bp + 2]);
+  }
+  return st;
+}
+
+EriLaunch launch_args(jk_ctx* c, const Plan& P, const Setup& S, int X, int Y, int i0, int i1,
+                      const double* D, double* J, double* K, int nbf, const jk_opts& o) {
+  EriLaunch a{};
+  a.bra = bin_view(P, X, S.prim, S.A, S.AB, S.bf, S.atoms, S.fpair, S.Q);
+  a.ket = bin_view(P, Y, S.prim, S.A, S.AB, S.bf, S.atoms, S.fpair, S.Q);
+  a.items = S.items + i0;
+  a.nitems = i1 - i0;
+  a.same_bin = X == Y;
+  a.D = D;
+  a.J = J;
+  a.K = K;
+  a.n = nbf;
+  a.n_dm = o.n_dm;
+  a.boys64 = c->boys64;
+  a.boys32 = c->boys32;
+  a.boys_fp64_T = static_cast<float>(o.boys_fp64_T);
+  return a;
+}
+
 int check_opts(const jk_opts* o, jk_opts* out, std::string* msg) {
   jk_opts_default(out);
   if (o) *out = *o;
@@ -724,42 +767,15 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
     hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(nn * o.n_dm, 256)), dim3(256), 0, s, nn * o.n_dm, K);
     HIP_OK(hipGetLastError());
 
-    jk_stats st{};
-    for (int q = 0; q < JK_NCLASS; ++q) {
-      int X = 0;
-      while ((X + 1) * (X + 2) / 2 <= q) ++X;
-      const int Y = q - X * (X + 1) / 2;
-      st.class_l[q][0] = kPairL[X][0];
-      st.class_l[q][1] = kPairL[X][1];
-      st.class_l[q][2] = kPairL[Y][0];
-      st.class_l[q][3] = kPairL[Y][1];
-    }
-    st.n_pairs = P.npairs;
+    jk_stats st = base_stats(P, S);
     const int nbp = static_cast<int>(P.bp_x.size());
-    st.work_items = S.seg[2 * nbp + 1];
     for (int bp = 0; bp < nbp; ++bp) {
       const int X = P.bp_x[bp], Y = P.bp_y[bp];
       const int cls = quartet_class(P.bin_cls[X], P.bin_cls[Y]);
-      st.quartets_fp64[cls] += static_cast<int64_t>(S.qstat[3 * bp]);
-      st.quartets_fp32[cls] += static_cast<int64_t>(S.qstat[3 * bp + 1]);
-      st.quartets_skipped += static_cast<int64_t>(S.qstat[3 * bp + 2]);
       for (int pr = 0; pr < 2; ++pr) {
         const int i0 = S.seg[pr * (nbp + 1) + bp], i1 = S.seg[pr * (nbp + 1) + bp + 1];
         if (i1 <= i0) continue;
-        EriLaunch a{};
-        a.bra = bin_view(P, X, S.prim, S.A, S.AB, S.bf, S.atoms, S.fpair, S.Q);
-        a.ket = bin_view(P, Y, S.prim, S.A, S.AB, S.bf, S.atoms, S.fpair, S.Q);
-        a.items = S.items + i0;
-        a.nitems = i1 - i0;
-        a.same_bin = X == Y;
-        a.D = D;
-        a.J = J;
-        a.K = K;
-        a.n = nbf;
-        a.n_dm = o.n_dm;
-        a.boys64 = c->boys64;
-        a.boys32 = c->boys32;
-        a.boys_fp64_T = static_cast<float>(o.boys_fp64_T);
+        EriLaunch a = launch_args(c, P, S, X, Y, i0, i1, D, J, K, nbf, o);
         size_t e0 = 0;
         if (c->timed) e0 = event(c, s);
         launch_eri(cls, pr, a, s);
@@ -795,9 +811,50 @@ int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, dou
   jk_opts o;
   rc = check_opts(opts, &o, &c->err);
   if (rc != JK_OK) return rc;
-  (void)hip_stream;
-  c->err = "nuclear gradient kernels are not built in this version";
-  return JK_EUNSUPPORTED;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  try {
+    HIP_OK(hipSetDevice(c->device));
+    c->scratch_limit = o.max_scratch_bytes;
+    c->timed = o.timing == 1;
+    c->ev_used = 0;
+    c->timed_launches.clear();
+    if (c->timed) c->ev_setup0 = event(c, s);
+    Setup S = setup(c, basis, tol, o, s);
+    const Plan& P = S.P;
+    if (c->timed) c->ev_setup1 = event(c, s);
+    const size_t ng = static_cast<size_t>(o.n_dm) * basis->n_atoms * 3;
+    hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(ng, 256)), dim3(256), 0, s, ng, dEdR);
+    HIP_OK(hipGetLastError());
+    jk_stats st = base_stats(P, S);
+    const int nbp = static_cast<int>(P.bp_x.size());
+    for (int bp = 0; bp < nbp; ++bp) {
+      const int X = P.bp_x[bp], Y = P.bp_y[bp];
+      const int cls = quartet_class(P.bin_cls[X], P.bin_cls[Y]);
+      for (int pr = 0; pr < 2; ++pr) {
+        const int i0 = S.seg[pr * (nbp + 1) + bp], i1 = S.seg[pr * (nbp + 1) + bp + 1];
+        if (i1 <= i0) continue;
+        GradLaunch g{};
+        g.e = launch_args(c, P, S, X, Y, i0, i1, D, nullptr, nullptr, nbf, o);
+        g.dEdR = dEdR;
+        g.n_atoms = basis->n_atoms;
+        size_t e0 = 0;
+        if (c->timed) e0 = event(c, s);
+        launch_grad(cls, pr, g, s);
+        HIP_OK(hipGetLastError());
+        if (c->timed) {
+          event(c, s);
+          c->timed_launches.push_back({cls, pr, e0});
+        }
+        (pr ? st.launches_fp32 : st.launches_fp64)[cls] += 1;
+      }
+    }
+    if (c->timed) c->ev_end = event(c, s);
+    c->stats = st;
+  } catch (const Fail& f) {
+    c->err = f.msg;
+    return f.code;
+  }
+  return JK_OK;
 }
 
 int jk_get_stats(jk_ctx* c, jk_stats* out) {

@@ -254,3 +254,54 @@ def grad(mol, D, tol: float, precision: str = "fp64", fp32_below: float = 1e-4,
     opts = make_opts(precision, fp32_below, n_dm)
     jk_grad(ctx, basis, Dd, G, tol, opts)
     return G[0] if squeeze else G
+
+
+class JKEnergy:
+    """E = 1/2 tr(DJ) - 1/4 tr(DK) as a torch.autograd.Function.
+
+    JKEnergy.apply(xyz, D, mol, tol, precision) -> E (0-d tensor, or [n_dm]).
+    The backward pass calls jk_grad (derivative-integral kernels) for dE/dxyz
+    and returns dE/dD = J - K/2 from the forward build.
+    """
+
+    _fn = None
+
+    @classmethod
+    def apply(cls, xyz, D, mol, tol: float, precision: str = "fp64"):
+        if cls._fn is None:
+            cls._fn = _make_jk_energy()
+        return cls._fn.apply(xyz, D, mol, tol, precision)
+
+
+def _make_jk_energy():
+    import torch
+
+    class _JKEnergy(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, xyz, D, mol, tol, precision):
+            moved = mol.with_xyz(xyz.detach().cpu().double().numpy())
+            basis = Basis(moved)
+            J, K = jk(basis, D, tol, precision=precision)
+            E = 0.5 * (D * J).sum(dim=(-1, -2)) - 0.25 * (D * K).sum(dim=(-1, -2))
+            ctx.save_for_backward(D, J, K)
+            ctx.basis = basis
+            ctx.tol = tol
+            ctx.precision = precision
+            ctx.xyz_dev = xyz.device
+            return E
+
+        @staticmethod
+        def backward(ctx, gE):
+            D, J, K = ctx.saved_tensors
+            g_xyz = g_D = None
+            if ctx.needs_input_grad[0]:
+                G = grad(ctx.basis, D, ctx.tol, precision=ctx.precision)
+                scale = gE.reshape(gE.shape + (1, 1)) if gE.dim() else gE
+                g_xyz = (G * scale).sum(dim=0) if G.dim() == 3 else G * scale
+                g_xyz = g_xyz.to(ctx.xyz_dev)
+            if ctx.needs_input_grad[1]:
+                scale = gE.reshape(gE.shape + (1, 1)) if gE.dim() else gE
+                g_D = (J - 0.5 * K) * scale
+            return g_xyz, g_D, None, None, None
+
+    return _JKEnergy

@@ -1,0 +1,98 @@
+"""Nuclear gradient of E = 1/2 tr(DJ) - 1/4 tr(DK) from the derivative-integral
+kernels: parity with the CPU oracle gradient, central finite differences of the
+GPU FP64 energy, translational invariance, and the mixed-precision form."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import gpu_jk, say
+from paper_2406_11185_amd import molgen
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_grad(mol, tol, precision="fp64"):
+    import torch
+    from paper_2406_11185_amd import jk as jkb
+    D = torch.as_tensor(np.ascontiguousarray(mol.D), device="cuda")
+    G = jkb.grad(mol, D, tol, precision=precision)
+    torch.cuda.synchronize()
+    return G.cpu().numpy()
+
+
+def energy(mol, tol, precision="fp64"):
+    J, K = gpu_jk(mol, tol, precision)
+    return 0.5 * np.einsum("mij,mij->m", mol.D, J) - 0.25 * np.einsum("mij,mij->m", mol.D, K)
+
+
+@pytest.mark.parametrize("nh,nH,seed", [(1, 1, 7), (2, 2, 11), (0, 3, 3)])
+def test_gradient_against_oracle(nh, nH, seed):
+    mol = molgen.make_molecule(nh, nH, seed, heavy_z=None if nh else [])
+    say(f"case grad m{nh}_{nH}_{seed} ({mol.n_bf} functions, tol 0)")
+    G = gpu_grad(mol, 0.0)
+    Go = oracle.grad(mol, 0.0)
+    say("  max|dG| =", np.abs(G - Go).max())
+    assert np.abs(G - Go).max() <= 1e-9
+    np.testing.assert_allclose(G.sum(axis=1), 0.0, atol=1e-10)
+
+
+def test_w4_gradient_against_oracle():
+    mol = molgen.workload("w4")
+    say("case grad w4 (40 functions, tol 0)")
+    G = gpu_grad(mol, 0.0)
+    Go = oracle.grad(mol, 0.0)
+    say("  max|dG| =", np.abs(G - Go).max())
+    assert np.abs(G - Go).max() <= 1e-9
+
+
+def test_w30_gradient_finite_differences():
+    """The 30-atom gradient workload against central differences (h = 1e-4 bohr)
+    of the FP64 energy without screening, on a sample of coordinates."""
+    mol = molgen.workload("w30grad")
+    say("case grad w30 vs central differences (tol 0)")
+    G = gpu_grad(mol, 0.0)[0]
+    h = 1e-4
+    rng = np.random.default_rng(0)
+    for a, x in [(int(rng.integers(mol.n_atoms)), int(rng.integers(3))) for _ in range(4)] + [(0, 0)]:
+        xp = mol.xyz.copy(); xp[a, x] += h
+        xm = mol.xyz.copy(); xm[a, x] -= h
+        fd = (energy(mol.with_xyz(xp), 0.0)[0] - energy(mol.with_xyz(xm), 0.0)[0]) / (2 * h)
+        say(f"  atom {a} dir {x}: analytic {G[a, x]:.10f} fd {fd:.10f}")
+        assert abs(G[a, x] - fd) <= 1e-6
+    np.testing.assert_allclose(G.sum(axis=0), 0.0, atol=1e-9)
+
+
+def test_w30_mixed_gradient_against_fp64():
+    mol = molgen.workload("w30grad")
+    say("case grad w30 mixed vs fp64 (tol 1e-10)")
+    G64 = gpu_grad(mol, 1e-10)
+    Gm = gpu_grad(mol, 1e-10, "mixed")
+    say("  max|dG| =", np.abs(Gm - G64).max())
+    assert np.abs(Gm - G64).max() <= 1e-5
+
+
+def test_autograd_function():
+    import torch
+    from paper_2406_11185_amd import jk as jkb
+    mol = molgen.make_molecule(1, 1, 7)
+    say("case autograd JKEnergy")
+    xyz = torch.tensor(mol.xyz, dtype=torch.float64, requires_grad=True)
+    D = torch.tensor(mol.D[0], dtype=torch.float64, device="cuda", requires_grad=True)
+    E = jkb.JKEnergy.apply(xyz, D, mol, 0.0)
+    E.backward()
+    Go = oracle.grad(mol, 0.0)[0]
+    assert np.abs(xyz.grad.numpy() - Go).max() <= 1e-9
+    Jo, Ko, _ = oracle.jk(mol, 0.0)
+    assert np.abs(D.grad.cpu().numpy() - (Jo[0] - 0.5 * Ko[0])).max() <= 1e-10
+    # dE/dD by central differences on a few symmetric perturbations
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        P = rng.normal(size=D.shape)
+        P = torch.tensor(P + P.T, device="cuda")
+        eps = 1e-5
+        with torch.no_grad():
+            Ep = jkb.JKEnergy.apply(xyz, D + eps * P, mol, 0.0)
+            Em = jkb.JKEnergy.apply(xyz, D - eps * P, mol, 0.0)
+        fd = float((Ep - Em) / (2 * eps))
+        an = float((D.grad * P).sum())
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
