@@ -111,6 +111,14 @@ def ket_fn(name, lc, ld):
     return s, h.flops
 
 
+def grad_lanes(ng, npass):
+    """Lanes that share one shell quartet: 1 for the lightest classes, 4 for up to
+    four passes, 16 beyond."""
+    if ng <= 32:
+        return 1
+    return 4 if npass <= 4 else 16
+
+
 def gen_grad_class(la, lb, lc, ld):
     name = g.cls_name(la, lb, lc, ld)
     L1 = la + lb + lc + ld + 1
@@ -150,7 +158,8 @@ def gen_grad_class(la, lb, lc, ld):
          f"struct GCls_{name} {{",
          f"  static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld}, L = {L1};",
          f"  static constexpr int NA = {na}, NB = {nb}, NC = {nc}, ND = {nd}, NG = {NG};",
-         f"  static constexpr int NPASS = {len(passes)}, USE_U = {1 if use_u else 0};"]
+         f"  static constexpr int NPASS = {len(passes)}, USE_U = {1 if use_u else 0};",
+         f"  static constexpr int G = {grad_lanes(NG, len(passes))};  // lanes per shell quartet"]
     # set geometry
     for nm, w, Es, Fs in sets:
         s.append(f"  static constexpr int OFF_{nm} = {off[nm]}, NE_{nm} = {len(Es)}, NF_{nm} = {len(Fs)};")
@@ -179,8 +188,8 @@ def gen_grad_class(la, lb, lc, ld):
         s += ["    " + x for x in g.VRR_PROLOGUE]
         s.append("    (void)wA; (void)wB; (void)wC;")
         s += ["    " + x for x in v.lines] + ["    " + x for x in lines] + ["  }"]
-        s.append("  template <typename T>")
-        s.append(f"  __device__ __forceinline__ static void store_p{j}(const T* __restrict__ acc, T* G, int z) {{")
+        s.append("  template <typename T, class A>")
+        s.append(f"  __device__ __forceinline__ static void store_p{j}(const T* __restrict__ acc, A G, int z) {{")
         s += ["    " + x for x in store] + ["  }"]
     s.append("  template <int J> struct Pass;")
     s.append("  template <int J, typename T>")
@@ -190,11 +199,11 @@ def gen_grad_class(la, lb, lc, ld):
         kw = "if" if j == 0 else "else if"
         s.append(f"    {kw} constexpr (J == {j}) vrr_p{j}<T>(F, c, wA, wB, wC, acc);")
     s.append("  }")
-    s.append("  template <int J, typename T>")
-    s.append("  __device__ __forceinline__ static void store_pass(const T* __restrict__ acc, T* G, int z) {")
+    s.append("  template <int J, typename T, class A>")
+    s.append("  __device__ __forceinline__ static void store_pass(const T* __restrict__ acc, A G, int z) {")
     for j in range(len(passes)):
         kw = "if" if j == 0 else "else if"
-        s.append(f"    {kw} constexpr (J == {j}) store_p{j}<T>(acc, G, z);")
+        s.append(f"    {kw} constexpr (J == {j}) store_p{j}<T, A>(acc, G, z);")
     s.append("  }")
     # ket HRR shapes
     hrr_flops = 0
@@ -281,7 +290,13 @@ def gen_grad_class(la, lb, lc, ld):
     for j, pas in enumerate(passes):
         n = sum(len(nodes[fe]) for fe in pas)
         s.append(f"template <> struct GCls_{name}::Pass<{j}> {{ static constexpr int N = {n}; }};")
-    info = dict(name=name, L=L1, ng=NG, npass=len(passes), vrr_flops=vrr_flops,
+    ncd = nc * nd
+    ws = (NG + len(sets[0][2]) * ncd + len(sets[1][2]) * ncd + len(sets[2][2]) * g.ncart(lc + 1) * nd
+          + (len(sets[3][2]) * ncd + len(sets[3][2]) * (g.ncart(lc - 1) * nd if lc >= 1 else 0)
+             if use_u else 0))
+    s.insert(s.index("};"), f"  static constexpr int WS = {ws};  // workspace values per lane")
+    info = dict(name=name, L=L1, ng=NG, npass=len(passes), vrr_flops=vrr_flops, ws=ws,
+                lanes=grad_lanes(NG, len(passes)),
                 vrr_flops_alg=vrr_flops_alg, hrr_flops=hrr_flops, contract_flops=dig)
     return "\n".join(s) + "\n", info
 
@@ -293,17 +308,25 @@ def wrapper(name):
         "namespace jk {",
         f'#include "gcls_{name}.inc"',
         f"void launch_grad_{name}(const GradLaunch& a, int fp32, hipStream_t s) {{",
-        "  const dim3 grid((a.e.nitems + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);",
+        "  const dim3 grid((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);",
         f"  if (fp32) hipLaunchKernelGGL((grad_kernel<GCls_{name}, float>), grid, block, 0, s, a);",
         f"  else hipLaunchKernelGGL((grad_kernel<GCls_{name}, double>), grid, block, 0, s, a);",
         "}",
         "}  // namespace jk", ""])
 
 
-def table(names):
+def table(names, infos):
     t = ["// generated by gen_grad.py -- do not edit", '#include "jk_grad_device.hpp"', "namespace jk {"]
     for n in names:
         t.append(f"void launch_grad_{n}(const GradLaunch&, int, hipStream_t);")
+    t.append("int grad_ws_elems(int cls) {")
+    t.append("  static const int w[21] = {" + ", ".join(str(i["ws"]) for i in infos) + "};")
+    t.append("  return (cls >= 0 && cls < 21) ? w[cls] : 0;")
+    t.append("}")
+    t.append("int grad_lanes(int cls) {")
+    t.append("  static const int g[21] = {" + ", ".join(str(i["lanes"]) for i in infos) + "};")
+    t.append("  return (cls >= 0 && cls < 21) ? g[cls] : 1;")
+    t.append("}")
     t.append("void launch_grad(int cls, int fp32, const GradLaunch& a, hipStream_t s) {")
     t.append("  switch (cls) {")
     for q, n in enumerate(names):
@@ -322,7 +345,7 @@ def main(outdir):
         g.write_if_changed(os.path.join(outdir, f"gcls_{info['name']}.inc"),
                            "// generated by gen_grad.py -- do not edit\n" + code)
         g.write_if_changed(os.path.join(outdir, f"gcls_{info['name']}.hip"), wrapper(info["name"]))
-    g.write_if_changed(os.path.join(outdir, "jk_grad_table.hip"), table(names))
+    g.write_if_changed(os.path.join(outdir, "jk_grad_table.hip"), table(names, infos))
     g.write_if_changed(os.path.join(outdir, "grad_classes.json"), json.dumps(infos, indent=1))
     return infos
 

@@ -217,6 +217,13 @@ class HRR(Code):
         return name
 
 
+def lanes_for(L, split):
+    """Lanes that share one shell quartet: light classes 1, mid classes 4, heavy 16."""
+    if split:
+        return 16
+    return 1 if L <= 2 else 4
+
+
 def gen_class(la, lb, lc, ld):
     L = la + lb + lc + ld
     name = cls_name(la, lb, lc, ld)
@@ -269,6 +276,7 @@ def gen_class(la, lb, lc, ld):
     s.append(f"  static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld}, L = {L};")
     s.append(f"  static constexpr int NA = {na}, NB = {nb}, NC = {nc}, ND = {nd};")
     s.append(f"  static constexpr int NE = {ne}, NF = {nf}, NACC = {ne * nf};")
+    s.append(f"  static constexpr int G = {lanes_for(L, False)};  // lanes per shell quartet")
     s.append(f"  static constexpr int VRR_FLOPS = {vrr_flops}, HRR_FLOPS = {hrr_flops}, "
              f"DIGEST_FLOPS = {dig_flops};")
     s.append("  template <typename T>")
@@ -307,13 +315,13 @@ def gen_class(la, lb, lc, ld):
     s.append("};")
     info = dict(name=name, la=la, lb=lb, lc=lc, ld=ld, L=L, nacc=ne * nf,
                 nint=na * nb * nc * nd, vrr_flops=vrr_flops, hrr_flops=hrr_flops,
-                digest_flops=dig_flops, vrr_nodes=vrr.n, hrr_nodes=hrr.n,
-                vrr_flops_alg=vrr_flops)
+                digest_flops=dig_flops, vrr_nodes=vrr.n, hrr_nodes=hrr.n, nf=nf,
+                vrr_flops_alg=vrr_flops, lanes=lanes_for(L, False))
     return "\n".join(s) + "\n", info
 
 
 SPLIT_NACC = 160   # classes with more contracted accumulators use the multi-pass form
-PASS_ACC = 128     # accumulators per pass in the multi-pass form
+PASS_ACC = 96      # accumulators per pass in the multi-pass form
 
 
 class KetHRR(Code):
@@ -389,6 +397,7 @@ def gen_split_class(la, lb, lc, ld):
     s.append(f"  static constexpr int NA = {na}, NB = {nb}, NC = {nc}, ND = {nd};")
     s.append(f"  static constexpr int NE = {ne}, NF = {nf}, NACC = {ne * nf};")
     s.append(f"  static constexpr int NPASS = {len(chunks)}, FCHUNK = {chunk};")
+    s.append(f"  static constexpr int G = {lanes_for(L, True)};  // lanes per shell quartet")
     vrr_flops = 0
     for j, ch in enumerate(chunks):
         v = VRR(L)
@@ -451,8 +460,8 @@ def gen_split_class(la, lb, lc, ld):
             one.node(e, f, 0)
     info = dict(name=name, la=la, lb=lb, lc=lc, ld=ld, L=L, nacc=ne * nf,
                 nint=na * nb * nc * nd, vrr_flops=vrr_flops, hrr_flops=hrr_flops,
-                digest_flops=dig_flops, npass=len(chunks), split=True,
-                vrr_flops_alg=one.flops + ne * nf)
+                digest_flops=dig_flops, npass=len(chunks), split=True, nf=nf,
+                vrr_flops_alg=one.flops + ne * nf, lanes=lanes_for(L, True))
     return "\n".join(s) + "\n", info
 
 
@@ -468,14 +477,17 @@ def wrapper(info):
          "namespace jk {",
          f'#include "cls_{n}.inc"',
          f"void launch_eri_{n}(const EriLaunch& a, int fp32, hipStream_t s) {{",
-         "  const dim3 grid((a.nitems + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);",
+         "  const int waves = " + ("a.nwaves" if info["split"] else "a.nitems") + ";",
+         "  const dim3 grid((waves + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);",
          f"  if (fp32) hipLaunchKernelGGL(({kern}<Cls_{n}, float>), grid, block, 0, s, a);",
          f"  else hipLaunchKernelGGL(({kern}<Cls_{n}, double>), grid, block, 0, s, a);",
          "}"]
     if info["bra_class"] == info["ket_class"]:
         w += [f"void launch_schwarz_{n}(const EriLaunch& a, double* Q, hipStream_t s) {{",
-              f"  hipLaunchKernelGGL(({skern}<Cls_{n}>), dim3((a.bra.n + kBlock - 1) / kBlock),"
-              " dim3(kBlock), 0, s, a, Q);",
+              (f"  hipLaunchKernelGGL(({skern}<Cls_{n}>), dim3((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock),"
+               " dim3(kBlock), 0, s, a, Q);") if info["split"] else
+              (f"  hipLaunchKernelGGL(({skern}<Cls_{n}>), dim3((a.bra.n * Cls_{n}::G + kBlock - 1) / kBlock),"
+               " dim3(kBlock), 0, s, a, Q);"),
               "}"]
     w.append("}  // namespace jk")
     return "\n".join(w) + "\n"
@@ -493,6 +505,44 @@ def table(infos):
         t.append(f"    case {q}: launch_eri_{i['name']}(a, fp32, s); break;")
     t.append("    default: break;")
     t.append("  }")
+    t.append("}")
+    t.append("// relative work per primitive quartet of each class (generated operation counts)")
+    t.append("double class_cost(int cls, int grad) {")
+    t.append("  static const double e[21] = {" + ", ".join(
+        f"{i.get('vrr_flops_alg', i['vrr_flops']) + 71 + 4 * i['L'] + (i['hrr_flops'] + i['digest_flops']) / 81.0:.1f}"
+        for i in infos) + "};")
+    t.append("  static const double g[21] = {" + ", ".join(
+        f"{3.0 * (i.get('vrr_flops_alg', i['vrr_flops']) + 71 + 4 * i['L']):.1f}" for i in infos) + "};")
+    t.append("  if (cls < 0 || cls >= 21) return 1.0;")
+    t.append("  return grad ? g[cls] : e[cls];")
+    t.append("}")
+    def wsb(i, tb):
+        if not i["split"]:
+            return 0
+        ncd = (i["lc"] + 1) * (i["lc"] + 2) // 2 * ((i["ld"] + 1) * (i["ld"] + 2) // 2)
+        na = (i["la"] + 1) * (i["la"] + 2) // 2
+        nb = (i["lb"] + 1) * (i["lb"] + 2) // 2
+        nc = (i["lc"] + 1) * (i["lc"] + 2) // 2
+        nd = (i["ld"] + 1) * (i["ld"] + 2) // 2
+        ne = i["nacc"] // i["nf"]
+        return 64 * ((i["nacc"] + ne * ncd) * tb + (na * nc + na * nd + nb * nc + nb * nd) * 8)
+    t.append("// bytes of workspace per wavefront of the multi-pass classes (0: none)")
+    t.append("size_t split_ws_bytes(int cls, int fp32) {")
+    t.append("  static const size_t w64[21] = {" + ", ".join(str(wsb(i, 8)) for i in infos) + "};")
+    t.append("  static const size_t w32[21] = {" + ", ".join(str(wsb(i, 4)) for i in infos) + "};")
+    t.append("  if (cls < 0 || cls >= 21) return 0;")
+    t.append("  return fp32 ? w32[cls] : w64[cls];")
+    t.append("}")
+    t.append("// bytes per wavefront of the multi-pass Schwarz kernel of a diagonal class (FP64)")
+    t.append("size_t split_schwarz_ws_bytes(int cls) {")
+    t.append("  static const size_t w[21] = {" + ", ".join(
+        str(64 * 8 * (i["nacc"] + (i["nacc"] // i["nf"]) * ((i["lc"] + 1) * (i["lc"] + 2) // 2) * ((i["ld"] + 1) * (i["ld"] + 2) // 2)))
+        if i["split"] else "0" for i in infos) + "};")
+    t.append("  return (cls >= 0 && cls < 21) ? w[cls] : 0;")
+    t.append("}")
+    t.append("int class_lanes(int cls) {")
+    t.append("  static const int g[21] = {" + ", ".join(str(i["lanes"]) for i in infos) + "};")
+    t.append("  return (cls >= 0 && cls < 21) ? g[cls] : 1;")
     t.append("}")
     t.append("void launch_schwarz(int pair_class, const EriLaunch& a, double* Q, hipStream_t s) {")
     t.append("  switch (pair_class) {")

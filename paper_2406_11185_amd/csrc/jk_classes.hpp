@@ -6,6 +6,13 @@ namespace jk {
 // Integral + digestion kernel of quartet class `cls` (0..20, bra class X >= ket
 // class Y, index X(X+1)/2 + Y over pair classes ss, ps, pp, ds, dp, dd).
 void launch_eri(int cls, int fp32, const EriLaunch& a, hipStream_t s);
+// Workspace bytes per wavefront of the multi-pass classes (0 for the others).
+size_t split_ws_bytes(int cls, int fp32);
+size_t split_schwarz_ws_bytes(int cls);
+// Lanes that share one shell quartet in the class's kernel.
+int class_lanes(int cls);
+// Relative cost per primitive quartet of class `cls` (energy, or gradient if grad).
+double class_cost(int cls, int grad);
 // Cauchy-Schwarz factors of the pairs of one bin of pair class 0..5.
 void launch_schwarz(int pair_class, const EriLaunch& a, double* Q, hipStream_t s);
 }  // namespace jk

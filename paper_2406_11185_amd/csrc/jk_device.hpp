@@ -17,8 +17,8 @@ namespace jk {
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
-constexpr int kChunksPerItem = 16;          // ket chunks of one wave-width per work item
-constexpr int kItemKets = kWave * kChunksPerItem;
+constexpr int kMaxItemChunks = 16;   // a work item covers 1..16 wave-wide ket chunks
+constexpr int kTargetWaves = 8192;   // aim for this many work items per class launch
 
 // primitive-pair fields
 enum : int { kP = 0, kOo2p = 1, kPAx = 2, kPAy = 3, kPAz = 4, kKt = 5, kTwoA = 6, kTwoB = 7,
@@ -63,6 +63,16 @@ struct EriLaunch {
   const double* boys64;
   const float* boys32;
   float boys_fp64_T;  // FP32 kernels: F_m in FP64 above this T
+  void* ws;           // multi-pass classes: per-wave workspace (see split_ws_bytes)
+  int nwaves;         // multi-pass classes: wavefronts of the launch (item loop stride)
+};
+
+// Per-lane array in a launch workspace, lane-interleaved so that a wavefront
+// touching element i reads 64 consecutive values.
+template <typename T>
+struct LaneArr {
+  T* p;
+  __device__ __forceinline__ T& operator[](int i) const { return p[static_cast<size_t>(i) * kWave]; }
 };
 
 template <typename T>
@@ -78,54 +88,78 @@ __device__ constexpr double kInvOdd[24] = {
 
 constexpr double kPiOver4 = 0.78539816339744830961566084581988;
 
+// 1/sqrt(x) for positive normal FP64 x: hardware estimate refined by two
+// Newton steps y <- y (3/2 - x y^2 / 2) (quadratic convergence, last bit
+// rounding only).
+__device__ __forceinline__ double rsqrt_f64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * (1.5 - h * y * y);
+  y = y * (1.5 - h * y * y);
+  return y;
+}
+
+__device__ __forceinline__ float rsqrt_f32(float x) {
+  float y = __builtin_amdgcn_rsqf(x);
+  y = y * (1.5f - 0.5f * x * y * y);
+  return y;
+}
+
 // F_m(T), m = 0..L, FP64.  T < 64: seven-term Taylor expansion about the nearest
 // table point (|dT| <= 0.025, truncation below 2e-15 relative) for F_L, e^{-T}
 // from the table value times a Taylor series of e^{-dT}, then the stable
 // downward recursion F_m = (2T F_{m+1} + e^{-T}) / (2m+1).  T >= 64: the
 // asymptotic F_0 = sqrt(pi/(4T)) and upward recursion F_{m+1} = (2m+1)/(2T) F_m
 // (the dropped e^{-T} terms are below 1e-15 relative there for m <= 10).
+// Both forms are evaluated and selected per lane, so a wavefront with mixed T
+// does not diverge.
 template <int L>
 __device__ __forceinline__ void boys_f64(double T, const double* __restrict__ tab, double* F) {
-  if (T < kBoysTmax) {
-    const int i = static_cast<int>(T * kBoysInvStep + 0.5);
-    const double x = i * kBoysStep - T;
-    const double* r = tab + i * kBoysStride;
-    double s = r[L + 6];
-    s = r[L + 5] + x * s * (1.0 / 6.0);
-    s = r[L + 4] + x * s * (1.0 / 5.0);
-    s = r[L + 3] + x * s * 0.25;
-    s = r[L + 2] + x * s * (1.0 / 3.0);
-    s = r[L + 1] + x * s * 0.5;
-    s = r[L] + x * s;
-    F[L] = s;
-    if constexpr (L > 0) {
-      double e = 1.0 + x * (1.0 / 6.0);
-      e = 1.0 + x * 0.2 * e;
-      e = 1.0 + x * 0.25 * e;
-      e = 1.0 + x * (1.0 / 3.0) * e;
-      e = 1.0 + x * 0.5 * e;
-      e = 1.0 + x * e;
-      e *= r[kBoysStride - 1];
-      const double T2 = 2.0 * T;
+  const bool near = T < kBoysTmax;
+  const double Tt = near ? T : 0.0;
+  const int i = static_cast<int>(Tt * kBoysInvStep + 0.5);
+  const double x = i * kBoysStep - Tt;
+  const double* r = tab + i * kBoysStride;
+  double s = r[L + 6];
+  s = r[L + 5] + x * s * (1.0 / 6.0);
+  s = r[L + 4] + x * s * (1.0 / 5.0);
+  s = r[L + 3] + x * s * 0.25;
+  s = r[L + 2] + x * s * (1.0 / 3.0);
+  s = r[L + 1] + x * s * 0.5;
+  s = r[L] + x * s;
+  double Ft[L + 1];
+  Ft[L] = s;
+  if constexpr (L > 0) {
+    double e = 1.0 + x * (1.0 / 6.0);
+    e = 1.0 + x * 0.2 * e;
+    e = 1.0 + x * 0.25 * e;
+    e = 1.0 + x * (1.0 / 3.0) * e;
+    e = 1.0 + x * 0.5 * e;
+    e = 1.0 + x * e;
+    e *= r[kBoysStride - 1];
+    const double T2 = 2.0 * Tt;
 #pragma unroll
-      for (int m = L - 1; m >= 0; --m) F[m] = (T2 * F[m + 1] + e) * kInvOdd[m];
-    }
-  } else {
-    const double rT = 1.0 / T;
-    F[0] = sqrt(kPiOver4 * rT);
-    const double h = 0.5 * rT;
+    for (int m = L - 1; m >= 0; --m) Ft[m] = (T2 * Ft[m + 1] + e) * kInvOdd[m];
+  }
+  const double Ta = near ? kBoysTmax : T;
+  const double rs = rsqrt_f64(Ta);
+  double fa = 0.88622692545275801364908374167057 * rs;  // sqrt(pi)/2 / sqrt(T)
+  const double h = 0.5 * rs * rs;
+  F[0] = near ? Ft[0] : fa;
 #pragma unroll
-    for (int m = 0; m < L; ++m) F[m + 1] = F[m] * ((2 * m + 1) * h);
+  for (int m = 0; m < L; ++m) {
+    fa *= (2 * m + 1) * h;
+    F[m + 1] = near ? Ft[m + 1] : fa;
   }
 }
 
 // F_m(T), m = 0..L, for the FP32 kernels.  T <= boys_fp64_T (<= 30): four-term
 // Taylor expansion in FP32 from the FP32 table and downward recursion in FP32.
 // Larger T: evaluated in FP64 (asymptotic F_0, upward recursion with the
-// e^{-T} term) and rounded to FP32.
+// e^{-T} term taken from the FP64 table) and rounded to FP32.
 template <int L>
 __device__ __forceinline__ void boys_f32(float T, float tcut, const float* __restrict__ tab,
-                                         float* F) {
+                                         const double* __restrict__ tab64, float* F) {
   if (T <= tcut) {
     const int i = static_cast<int>(T * kBoys32InvStep + 0.5f);
     const float x = i * kBoys32Step - T;
@@ -147,12 +181,23 @@ __device__ __forceinline__ void boys_f32(float T, float tcut, const float* __res
     }
   } else {
     const double Td = static_cast<double>(T);
-    const double rT = 1.0 / Td;
-    double f = sqrt(kPiOver4 * rT);
+    const double rs = rsqrt_f64(Td);
+    double f = 0.88622692545275801364908374167057 * rs;
     F[0] = static_cast<float>(f);
     if constexpr (L > 0) {
-      const double e = exp(-Td);
-      const double h = 0.5 * rT;
+      double e = 0.0;  // e^{-T}: table row times e^{x}, zero beyond the table
+      if (Td < kBoysTmax) {
+        const int i = static_cast<int>(Td * kBoysInvStep + 0.5);
+        const double x = i * kBoysStep - Td;
+        double ex = 1.0 + x * (1.0 / 6.0);
+        ex = 1.0 + x * 0.2 * ex;
+        ex = 1.0 + x * 0.25 * ex;
+        ex = 1.0 + x * (1.0 / 3.0) * ex;
+        ex = 1.0 + x * 0.5 * ex;
+        ex = 1.0 + x * ex;
+        e = ex * tab64[i * kBoysStride + kBoysStride - 1];
+      }
+      const double h = 0.5 * rs * rs;
 #pragma unroll
       for (int m = 0; m < L; ++m) {
         f = ((2 * m + 1) * f - e) * h;
@@ -173,7 +218,7 @@ struct Boys<L, double> {
 template <int L>
 struct Boys<L, float> {
   __device__ __forceinline__ static void eval(float T, const EriLaunch& a, float* F) {
-    boys_f32<L>(T, a.boys_fp64_T, a.boys32, F);
+    boys_f32<L>(T, a.boys_fp64_T, a.boys32, a.boys64, F);
   }
 };
 
@@ -182,16 +227,23 @@ struct Boys<L, float> {
 //   P - Q = (P - A) - (Q - C) + (A - C)   (keeps FP32 differences small)
 //   W - P = -q/(p+q) (P - Q),  W - Q = p/(p+q) (P - Q),  rho = pq/(p+q)
 //   prefactor = 2 pi^{5/2} K_AB K_CD / (p q sqrt(p+q)) = Kt_AB Kt_CD / sqrt(p+q)
+template <typename T>
+__device__ __forceinline__ T rsqrt_t(T x) {
+  if constexpr (sizeof(T) == 8) return rsqrt_f64(x);
+  else return rsqrt_f32(x);
+}
+
 template <int L, typename T>
 __device__ __forceinline__ void prim_setup(T p, T oo2p, T PAx, T PAy, T PAz, T Kab, T q, T oo2q,
                                            T QCx, T QCy, T QCz, T Kcd, T ACx, T ACy, T ACz,
                                            const EriLaunch& a, T* F, VrrCoef<T>& c) {
-  const T rpq = T(1) / (p + q);
+  const T srpq = rsqrt_t<T>(p + q);   // 1/sqrt(p+q)
+  const T rpq = srpq * srpq;
   const T qr = q * rpq, pr = p * rpq;
   const T PQx = PAx - QCx + ACx, PQy = PAy - QCy + ACy, PQz = PAz - QCz + ACz;
   const T Tb = p * qr * (PQx * PQx + PQy * PQy + PQz * PQz);
   Boys<L, T>::eval(Tb, a, F);
-  const T pref = Kab * Kcd * sqrt(rpq);
+  const T pref = Kab * Kcd * srpq;
 #pragma unroll
   for (int m = 0; m <= L; ++m) F[m] *= pref;
   c.PAx = PAx; c.PAy = PAy; c.PAz = PAz;
@@ -203,28 +255,69 @@ __device__ __forceinline__ void prim_setup(T p, T oo2p, T PAx, T PAy, T PAz, T K
   c.oo2pq = T(0.5) * rpq;
 }
 
-// Contraction loop of one shell quartet: bra pair i (uniform in the ERI
-// kernels), ket pair k (one per lane); `vrr(F, c)` adds one primitive quartet
-// to the caller's accumulators.
-template <int L, typename T, class V>
-__device__ __forceinline__ void contract(const EriLaunch& a, int i, int k, T ACx, T ACy, T ACz,
-                                         V&& vrr) {
+// Contraction loop of one shell quartet: bra pair i, ket pair k.  With G > 1
+// the G lanes of a group share the quartet: lane `sub` takes the primitive
+// quartets sub, sub+G, ...; `vrr(F, c)` adds one primitive quartet to the
+// caller's accumulators, which are summed over the group afterwards.
+template <int L, typename T, int G, class V>
+__device__ __forceinline__ void contract(const EriLaunch& a, int i, int k, int sub, T ACx, T ACy,
+                                         T ACz, V&& vrr) {
   const int nb = a.bra.n, nk = a.ket.n;
   const int nppb = a.bra.npp, nppk = a.ket.npp;
-  for (int kl = 0; kl < nppk; ++kl) {
-    const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
-    const T q = T(kp[kP * nk]), oo2q = T(kp[kOo2p * nk]);
-    const T QCx = T(kp[kPAx * nk]), QCy = T(kp[kPAy * nk]), QCz = T(kp[kPAz * nk]);
-    const T Kcd = T(kp[kKt * nk]);
-    for (int ij = 0; ij < nppb; ++ij) {
+  if constexpr (G == 1) {
+    (void)sub;
+    for (int kl = 0; kl < nppk; ++kl) {
+      const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
+      const T q = T(kp[kP * nk]), oo2q = T(kp[kOo2p * nk]);
+      const T QCx = T(kp[kPAx * nk]), QCy = T(kp[kPAy * nk]), QCz = T(kp[kPAz * nk]);
+      const T Kcd = T(kp[kKt * nk]);
+      // bra primitive pairs are uniform across the wave; the next one is
+      // loaded while the current one is being used
+      const double* bp = a.bra.prim + i;
+      double b0 = bp[kP * nb], b1 = bp[kOo2p * nb], b2 = bp[kPAx * nb], b3 = bp[kPAy * nb],
+             b4 = bp[kPAz * nb], b5 = bp[kKt * nb];
+      for (int ij = 0; ij < nppb; ++ij) {
+        const double* bn = a.bra.prim + static_cast<size_t>(ij + 1 < nppb ? ij + 1 : ij) * kPrimFields * nb + i;
+        const double n0 = bn[kP * nb], n1 = bn[kOo2p * nb], n2 = bn[kPAx * nb],
+                     n3 = bn[kPAy * nb], n4 = bn[kPAz * nb], n5 = bn[kKt * nb];
+        T F[L + 1];
+        VrrCoef<T> c;
+        prim_setup<L, T>(T(b0), T(b1), T(b2), T(b3), T(b4), T(b5), q, oo2q, QCx, QCy, QCz, Kcd,
+                         ACx, ACy, ACz, a, F, c);
+        vrr(F, c);
+        b0 = n0; b1 = n1; b2 = n2; b3 = n3; b4 = n4; b5 = n5;
+      }
+    }
+  } else {
+    const int npq = nppb * nppk;
+    for (int pq = sub; pq < npq; pq += G) {
+      const int kl = pq / nppb, ij = pq - kl * nppb;
+      const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
       const double* bp = a.bra.prim + static_cast<size_t>(ij) * kPrimFields * nb + i;
       T F[L + 1];
       VrrCoef<T> c;
       prim_setup<L, T>(T(bp[kP * nb]), T(bp[kOo2p * nb]), T(bp[kPAx * nb]), T(bp[kPAy * nb]),
-                       T(bp[kPAz * nb]), T(bp[kKt * nb]), q, oo2q, QCx, QCy, QCz, Kcd, ACx, ACy,
-                       ACz, a, F, c);
+                       T(bp[kPAz * nb]), T(bp[kKt * nb]), T(kp[kP * nk]), T(kp[kOo2p * nk]),
+                       T(kp[kPAx * nk]), T(kp[kPAy * nk]), T(kp[kPAz * nk]), T(kp[kKt * nk]),
+                       ACx, ACy, ACz, a, F, c);
       vrr(F, c);
     }
+  }
+}
+
+// Sum over the G lanes of a group (G a power of two dividing 64).
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+template <int G, typename T, int N>
+__device__ __forceinline__ void group_sum_all(T (&acc)[N]) {
+  if constexpr (G > 1) {
+#pragma unroll
+    for (int t = 0; t < N; ++t) acc[t] = group_sum<G>(acc[t]);
   }
 }
 
@@ -251,7 +344,9 @@ __device__ __forceinline__ void atomic_add(double* addr, double v) {
 // takes one ket pair of the current 64-wide chunk of the item's ket range.
 template <class C, typename T>
 __global__ __launch_bounds__(kBlock) void eri_jk_kernel(const EriLaunch a) {
+  constexpr int G = C::G, QPW = kWave / G;
   const int lane = threadIdx.x & (kWave - 1);
+  const int sub = lane & (G - 1), ql = lane / G;
   const int item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (item >= a.nitems) return;
   const int4 w = a.items[item];
@@ -266,16 +361,18 @@ __global__ __launch_bounds__(kBlock) void eri_jk_kernel(const EriLaunch a) {
   const int a0 = a.bra.bf[i], b0 = a.bra.bf[nb + i];
   const double fbra = a.bra.fpair[i];
 
-  for (int kc = kbeg; kc < kend; kc += kWave) {
-    const bool active = kc + lane < kend;
-    const int k = active ? kc + lane : kend - 1;
+  for (int kc = kbeg; kc < kend; kc += QPW) {
+    const bool inrange = kc + ql < kend;
+    const bool active = inrange && sub == 0;   // one lane of the group digests
+    const int k = inrange ? kc + ql : kend - 1;
     const T ACx = T(Ax - a.ket.A[k]), ACy = T(Ay - a.ket.A[nk + k]),
             ACz = T(Az - a.ket.A[2 * nk + k]);
     T acc[C::NACC];
 #pragma unroll
     for (int t = 0; t < C::NACC; ++t) acc[t] = T(0);
-    contract<C::L, T>(a, i, k, ACx, ACy, ACz,
-                      [&](const T* F, const VrrCoef<T>& c) { C::template vrr<T>(F, c, acc); });
+    contract<C::L, T, G>(a, i, k, sub, ACx, ACy, ACz,
+                         [&](const T* F, const VrrCoef<T>& c) { C::template vrr<T>(F, c, acc); });
+    group_sum_all<G>(acc);
 
     const T CDx = T(a.ket.AB[k]), CDy = T(a.ket.AB[nk + k]), CDz = T(a.ket.AB[2 * nk + k]);
     const int c0 = a.ket.bf[k], d0 = a.ket.bf[nk + k];
@@ -358,17 +455,23 @@ __global__ __launch_bounds__(kBlock) void eri_jk_kernel(const EriLaunch a) {
 // One lane per pair; bra and ket are the same pair, so A - C = 0.
 template <class C>
 __global__ __launch_bounds__(kBlock) void schwarz_kernel(const EriLaunch a, double* Qout) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
+  constexpr int G = C::G;
+  const int gt = blockIdx.x * kBlock + threadIdx.x;
   const int n = a.bra.n;
-  if (t >= n) return;
+  if (gt / kWave * (kWave / G) >= n) return;   // whole wave past the end
+  const int sub = gt & (G - 1);
+  const int t0 = gt / G;
+  const int t = t0 < n ? t0 : n - 1;
   double acc[C::NACC];
 #pragma unroll
   for (int s = 0; s < C::NACC; ++s) acc[s] = 0.0;
-  contract<C::L, double>(a, t, t, 0.0, 0.0, 0.0, [&](const double* F, const VrrCoef<double>& c) {
-    C::template vrr<double>(F, c, acc);
-  });
+  contract<C::L, double, G>(a, t, t, sub, 0.0, 0.0, 0.0,
+                            [&](const double* F, const VrrCoef<double>& c) {
+                              C::template vrr<double>(F, c, acc);
+                            });
+  group_sum_all<G>(acc);
   const double mx = C::template diag_max<double>(acc, a.bra.AB[t], a.bra.AB[n + t], a.bra.AB[2 * n + t]);
-  Qout[t] = sqrt(fmax(mx, 0.0));
+  if (t0 < n && sub == 0) Qout[t] = sqrt(fmax(mx, 0.0));
 }
 
 // ---------------------------------------------------------------------------------
@@ -377,25 +480,26 @@ __global__ __launch_bounds__(kBlock) void schwarz_kernel(const EriLaunch a, doub
 // primitive loop and parks the chunk in a private (scratch) array; the
 // horizontal recurrences then run as short loops: the ket step for one e at a
 // time into X[e][cd], the bra step plus digestion for one (c, d) at a time.
-template <class C, typename T, int J>
-__device__ __forceinline__ void split_passes(const EriLaunch& a, int i, int k, T ACx, T ACy,
-                                             T ACz, T* cacc, int z) {
+template <class C, typename T, int J, class A>
+__device__ __forceinline__ void split_passes(const EriLaunch& a, int i, int k, int sub, T ACx,
+                                             T ACy, T ACz, A cacc, int z) {
   constexpr int NFJ = C::template Pass<J>::NF, F0 = C::template Pass<J>::F0;
   T acc[C::NE * NFJ];
 #pragma unroll
   for (int t = 0; t < C::NE * NFJ; ++t) acc[t] = T(0);
-  contract<C::L, T>(a, i, k, ACx, ACy, ACz, [&](const T* F, const VrrCoef<T>& c) {
+  contract<C::L, T, C::G>(a, i, k, sub, ACx, ACy, ACz, [&](const T* F, const VrrCoef<T>& c) {
     C::template vrr_pass<J, T>(F, c, acc);
   });
+  group_sum_all<C::G>(acc);
 #pragma unroll
   for (int e = 0; e < C::NE; ++e)
 #pragma unroll
     for (int f = 0; f < NFJ; ++f) cacc[z + e * C::NF + F0 + f] = acc[e * NFJ + f];
-  if constexpr (J + 1 < C::NPASS) split_passes<C, T, J + 1>(a, i, k, ACx, ACy, ACz, cacc, z);
+  if constexpr (J + 1 < C::NPASS) split_passes<C, T, J + 1, A>(a, i, k, sub, ACx, ACy, ACz, cacc, z);
 }
 
-template <class C, typename T>
-__device__ __forceinline__ void split_ket_hrr(const T* cacc, T* X, int z, T CDx, T CDy, T CDz) {
+template <class C, typename T, class A>
+__device__ __forceinline__ void split_ket_hrr(A cacc, A X, int z, T CDx, T CDy, T CDz) {
   constexpr int NCD = C::NC * C::ND;
 #pragma nounroll
   for (int e = 0; e < C::NE; ++e) {
@@ -412,32 +516,47 @@ __device__ __forceinline__ void split_ket_hrr(const T* cacc, T* X, int z, T CDx,
 template <class C, typename T>
 __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a) {
   constexpr int NCD = C::NC * C::ND;
+  constexpr int G = C::G, QPW = kWave / G;
   const int lane = threadIdx.x & (kWave - 1);
-  const int item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (item >= a.nitems) return;
+  const int sub = lane & (G - 1), ql = lane / G;
+  const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (wave >= a.nwaves) return;
+  // workspace of this wave: T values (contracted [e0|f0], ket-transformed X),
+  // then FP64 exchange accumulators
+  constexpr int NT = C::NACC + C::NE * NCD;
+  constexpr int NK = C::NA * C::NC + C::NA * C::ND + C::NB * C::NC + C::NB * C::ND;
+  char* wbase = static_cast<char*>(a.ws) +
+                static_cast<size_t>(wave) * kWave * (NT * sizeof(T) + NK * sizeof(double));
+  const LaneArr<T> cacc{reinterpret_cast<T*>(wbase) + lane};
+  const LaneArr<T> X{cacc.p + static_cast<size_t>(C::NACC) * kWave};
+  double* kbase = reinterpret_cast<double*>(wbase + static_cast<size_t>(kWave) * NT * sizeof(T)) + lane;
+  const LaneArr<double> kac{kbase};
+  const LaneArr<double> kad{kac.p + static_cast<size_t>(C::NA * C::NC) * kWave};
+  const LaneArr<double> kbc{kad.p + static_cast<size_t>(C::NA * C::ND) * kWave};
+  const LaneArr<double> kbd{kbc.p + static_cast<size_t>(C::NB * C::NC) * kWave};
+  const int z = 0;
+  const int nb = a.bra.n, nk = a.ket.n;
+  const size_t n = static_cast<size_t>(a.n);
+  const size_t nn = n * n;
+  for (int item = wave; item < a.nitems; item += a.nwaves) {
   const int4 w = a.items[item];
   const int i = __builtin_amdgcn_readfirstlane(w.x);
   const int kbeg = __builtin_amdgcn_readfirstlane(w.y);
   const int kend = __builtin_amdgcn_readfirstlane(w.z);
-  const int nb = a.bra.n, nk = a.ket.n;
-  const size_t n = static_cast<size_t>(a.n);
-  const size_t nn = n * n;
   const double Ax = a.bra.A[i], Ay = a.bra.A[nb + i], Az = a.bra.A[2 * nb + i];
   const T ABx = T(a.bra.AB[i]), ABy = T(a.bra.AB[nb + i]), ABz = T(a.bra.AB[2 * nb + i]);
   const int a0 = a.bra.bf[i], b0 = a.bra.bf[nb + i];
   const double fbra = a.bra.fpair[i];
-  const int z = opaque_zero();
 
-  for (int kc = kbeg; kc < kend; kc += kWave) {
-    const bool active = kc + lane < kend;
-    const int k = active ? kc + lane : kend - 1;
+  for (int kc = kbeg; kc < kend; kc += QPW) {
+    const bool inrange = kc + ql < kend;
+    const bool active = inrange && sub == 0;
+    const int k = inrange ? kc + ql : kend - 1;
     const T ACx = T(Ax - a.ket.A[k]), ACy = T(Ay - a.ket.A[nk + k]),
             ACz = T(Az - a.ket.A[2 * nk + k]);
-    T cacc[C::NACC];
-    split_passes<C, T, 0>(a, i, k, ACx, ACy, ACz, cacc, z);
+    split_passes<C, T, 0, LaneArr<T>>(a, i, k, sub, ACx, ACy, ACz, cacc, z);
     const T CDx = T(a.ket.AB[k]), CDy = T(a.ket.AB[nk + k]), CDz = T(a.ket.AB[2 * nk + k]);
-    T X[C::NE * NCD];
-    split_ket_hrr<C, T>(cacc, X, z, CDx, CDy, CDz);
+    split_ket_hrr<C, T, LaneArr<T>>(cacc, X, z, CDx, CDy, CDz);
     const int c0 = a.ket.bf[k], d0 = a.ket.bf[nk + k];
     const double fq =
         active ? fbra * a.ket.fpair[k] * ((a.same_bin && k == i) ? 0.5 : 1.0) : 0.0;
@@ -454,7 +573,6 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
           Dab[x * C::NB + y] = Dm[(a0 + x) * n + b0 + y];
           jab[x * C::NB + y] = 0.0;
         }
-      double kac[C::NA * C::NC], kad[C::NA * C::ND], kbc[C::NB * C::NC], kbd[C::NB * C::ND];
 #pragma unroll
       for (int t = 0; t < C::NA * C::NC; ++t) kac[z + t] = 0.0;
 #pragma unroll
@@ -534,33 +652,43 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
       }
     }
   }
+  }
 }
 
 template <class C>
 __global__ __launch_bounds__(kBlock) void schwarz_split_kernel(const EriLaunch a, double* Qout) {
   constexpr int NCD = C::NC * C::ND;
-  const int t = blockIdx.x * kBlock + threadIdx.x;
+  constexpr int G = C::G, PPW = kWave / G;   // pairs per wave step
+  constexpr int NT = C::NACC + C::NE * NCD;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (wave >= a.nwaves) return;
+  const int sub = lane & (G - 1), ql = lane / G;
   const int n = a.bra.n;
-  if (t >= n) return;
-  const int z = opaque_zero();
-  double cacc[C::NACC];
-  split_passes<C, double, 0>(a, t, t, 0.0, 0.0, 0.0, cacc, z);
-  const double ABx = a.bra.AB[t], ABy = a.bra.AB[n + t], ABz = a.bra.AB[2 * n + t];
-  double X[C::NE * NCD];
-  split_ket_hrr<C, double>(cacc, X, z, ABx, ABy, ABz);
-  double mx = 0.0;
+  double* wl = static_cast<double*>(a.ws) + static_cast<size_t>(wave) * kWave * NT + lane;
+  const LaneArr<double> cacc{wl};
+  const LaneArr<double> X{wl + static_cast<size_t>(C::NACC) * kWave};
+  const int z = 0;
+  for (int p0 = wave * PPW; p0 < n; p0 += a.nwaves * PPW) {
+    const int t0 = p0 + ql;
+    const int t = t0 < n ? t0 : n - 1;
+    split_passes<C, double, 0, LaneArr<double>>(a, t, t, sub, 0.0, 0.0, 0.0, cacc, z);
+    const double ABx = a.bra.AB[t], ABy = a.bra.AB[n + t], ABz = a.bra.AB[2 * n + t];
+    split_ket_hrr<C, double, LaneArr<double>>(cacc, X, z, ABx, ABy, ABz);
+    double mx = 0.0;
 #pragma nounroll
-  for (int cd = 0; cd < NCD; ++cd) {
-    double ev[C::NE];
+    for (int cd = 0; cd < NCD; ++cd) {
+      double ev[C::NE];
 #pragma unroll
-    for (int e = 0; e < C::NE; ++e) ev[e] = X[z + e * NCD + cd];
-    double ab[C::NA * C::NB];
-    C::template bra_hrr<double>(ev, ABx, ABy, ABz, ab);
+      for (int e = 0; e < C::NE; ++e) ev[e] = X[z + e * NCD + cd];
+      double ab[C::NA * C::NB];
+      C::template bra_hrr<double>(ev, ABx, ABy, ABz, ab);
 #pragma unroll
-    for (int s = 0; s < C::NA * C::NB; ++s)
-      if (s == cd) mx = fmax(mx, ab[s]);
+      for (int s = 0; s < C::NA * C::NB; ++s)
+        if (s == cd) mx = fmax(mx, ab[s]);
+    }
+    if (t0 < n && sub == 0) Qout[t] = sqrt(fmax(mx, 0.0));
   }
-  Qout[t] = sqrt(fmax(mx, 0.0));
 }
 
 }  // namespace jk

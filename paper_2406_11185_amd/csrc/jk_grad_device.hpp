@@ -10,62 +10,67 @@ struct GradLaunch {
   EriLaunch e;      // pair data, items, D, Boys tables (J, K unused)
   double* dEdR;     // [n_dm][n_atoms][3]
   int n_atoms;
+  void* ws;         // workspace: nwaves * 64 lanes * C::WS values of type T
+  int nwaves;       // wavefronts of the launch; each loops over items with this stride
 };
+
+
 
 // Contraction loop with the exponent weights of the derivative integrals:
 // wA = 2a, wB = 2b (bra primitives), wC = 2c (first ket primitive).
-template <int L, typename T, class V>
-__device__ __forceinline__ void contract_w(const EriLaunch& a, int i, int k, T ACx, T ACy, T ACz,
-                                           V&& vrr) {
+// The G lanes of a group split the primitive quartets (sub, sub+G, ...).
+template <int L, typename T, int G, class V>
+__device__ __forceinline__ void contract_w(const EriLaunch& a, int i, int k, int sub, T ACx,
+                                           T ACy, T ACz, V&& vrr) {
   const int nb = a.bra.n, nk = a.ket.n;
   const int nppb = a.bra.npp, nppk = a.ket.npp;
-  for (int kl = 0; kl < nppk; ++kl) {
+  const int npq = nppb * nppk;
+  for (int pq = sub; pq < npq; pq += G) {
+    const int kl = pq / nppb, ij = pq - kl * nppb;
     const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
-    const T q = T(kp[kP * nk]), oo2q = T(kp[kOo2p * nk]);
-    const T QCx = T(kp[kPAx * nk]), QCy = T(kp[kPAy * nk]), QCz = T(kp[kPAz * nk]);
-    const T Kcd = T(kp[kKt * nk]), wC = T(kp[kTwoA * nk]);
-    for (int ij = 0; ij < nppb; ++ij) {
-      const double* bp = a.bra.prim + static_cast<size_t>(ij) * kPrimFields * nb + i;
-      T F[L + 1];
-      VrrCoef<T> c;
-      prim_setup<L, T>(T(bp[kP * nb]), T(bp[kOo2p * nb]), T(bp[kPAx * nb]), T(bp[kPAy * nb]),
-                       T(bp[kPAz * nb]), T(bp[kKt * nb]), q, oo2q, QCx, QCy, QCz, Kcd, ACx, ACy,
-                       ACz, a, F, c);
-      vrr(F, c, T(bp[kTwoA * nb]), T(bp[kTwoB * nb]), wC);
-    }
+    const double* bp = a.bra.prim + static_cast<size_t>(ij) * kPrimFields * nb + i;
+    T F[L + 1];
+    VrrCoef<T> c;
+    prim_setup<L, T>(T(bp[kP * nb]), T(bp[kOo2p * nb]), T(bp[kPAx * nb]), T(bp[kPAy * nb]),
+                     T(bp[kPAz * nb]), T(bp[kKt * nb]), T(kp[kP * nk]), T(kp[kOo2p * nk]),
+                     T(kp[kPAx * nk]), T(kp[kPAy * nk]), T(kp[kPAz * nk]), T(kp[kKt * nk]), ACx,
+                     ACy, ACz, a, F, c);
+    vrr(F, c, T(bp[kTwoA * nb]), T(bp[kTwoB * nb]), T(kp[kTwoA * nk]));
   }
 }
 
 template <class C, typename T, int J>
-__device__ __forceinline__ void grad_pass_body(const EriLaunch& a, int i, int k, T ACx, T ACy,
-                                               T ACz, T* G, int z) {
+__device__ __forceinline__ void grad_pass_body(const EriLaunch& a, int i, int k, int sub, T ACx,
+                                               T ACy, T ACz, LaneArr<T> G, int z) {
   constexpr int N = C::template Pass<J>::N;
   T acc[N];
 #pragma unroll
   for (int t = 0; t < N; ++t) acc[t] = T(0);
-  contract_w<C::L, T>(a, i, k, ACx, ACy, ACz,
-                      [&](const T* F, const VrrCoef<T>& c, T wA, T wB, T wC) {
-                        C::template vrr_pass<J, T>(F, c, wA, wB, wC, acc);
-                      });
-  C::template store_pass<J, T>(acc, G, z);
+  contract_w<C::L, T, C::G>(a, i, k, sub, ACx, ACy, ACz,
+                            [&](const T* F, const VrrCoef<T>& c, T wA, T wB, T wC) {
+                              C::template vrr_pass<J, T>(F, c, wA, wB, wC, acc);
+                            });
+  group_sum_all<C::G>(acc);
+  C::template store_pass<J, T, LaneArr<T>>(acc, G, z);
 }
 
 // Classes with many passes call each pass as a separate function, so that the
 // compiler allocates registers pass by pass.
 template <class C, typename T, int J>
-__device__ __attribute__((noinline)) void grad_pass_call(const EriLaunch& a, int i, int k, T ACx,
-                                                          T ACy, T ACz, T* G, int z) {
-  grad_pass_body<C, T, J>(a, i, k, ACx, ACy, ACz, G, z);
+__device__ __attribute__((noinline)) void grad_pass_call(const EriLaunch& a, int i, int k, int sub,
+                                                          T ACx, T ACy, T ACz, LaneArr<T> G,
+                                                          int z) {
+  grad_pass_body<C, T, J>(a, i, k, sub, ACx, ACy, ACz, G, z);
 }
 
 template <class C, typename T, int J>
-__device__ __forceinline__ void grad_passes(const EriLaunch& a, int i, int k, T ACx, T ACy, T ACz,
-                                            T* G, int z) {
+__device__ __forceinline__ void grad_passes(const EriLaunch& a, int i, int k, int sub, T ACx,
+                                            T ACy, T ACz, LaneArr<T> G, int z) {
   if constexpr (C::NPASS > 4)
-    grad_pass_call<C, T, J>(a, i, k, ACx, ACy, ACz, G, z);
+    grad_pass_call<C, T, J>(a, i, k, sub, ACx, ACy, ACz, G, z);
   else
-    grad_pass_body<C, T, J>(a, i, k, ACx, ACy, ACz, G, z);
-  if constexpr (J + 1 < C::NPASS) grad_passes<C, T, J + 1>(a, i, k, ACx, ACy, ACz, G, z);
+    grad_pass_body<C, T, J>(a, i, k, sub, ACx, ACy, ACz, G, z);
+  if constexpr (J + 1 < C::NPASS) grad_passes<C, T, J + 1>(a, i, k, sub, ACx, ACy, ACz, G, z);
 }
 
 constexpr int at_least_1(int v) { return v > 0 ? v : 1; }
@@ -76,9 +81,20 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
   constexpr int NCD = C::NC * C::ND;
   constexpr int NAB = C::NA * C::NB;
   const EriLaunch& a = g.e;
+  constexpr int GL = C::G, QPW = kWave / GL;
   const int lane = threadIdx.x & (kWave - 1);
-  const int item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (item >= a.nitems) return;
+  const int sub = lane & (GL - 1), ql = lane / GL;
+  const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (wave >= g.nwaves) return;
+  T* wsl = static_cast<T*>(g.ws) + static_cast<size_t>(wave) * C::WS * kWave + lane;
+  const LaneArr<T> G{wsl};
+  const LaneArr<T> XA{wsl + static_cast<size_t>(C::NG) * kWave};
+  const LaneArr<T> XB{XA.p + static_cast<size_t>(C::NE_A) * NCD * kWave};
+  const LaneArr<T> XC{XB.p + static_cast<size_t>(C::NE_B) * NCD * kWave};
+  const LaneArr<T> XU{XC.p + static_cast<size_t>(C::NE_C) * C::NCP * kWave};
+  const LaneArr<T> XV{XU.p + static_cast<size_t>(C::NE_U) * NCD * kWave};
+  const int z = 0;
+  for (int item = wave; item < a.nitems; item += g.nwaves) {
   const int4 w = a.items[item];
   const int i = __builtin_amdgcn_readfirstlane(w.x);
   const int kbeg = __builtin_amdgcn_readfirstlane(w.y);
@@ -91,20 +107,17 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
   const int a0 = a.bra.bf[i], b0 = a.bra.bf[nb + i];
   const int atA = a.bra.atoms[i], atB = a.bra.atoms[nb + i];
   const double fbra = a.bra.fpair[i];
-  const int z = opaque_zero();
 
-  for (int kc = kbeg; kc < kend; kc += kWave) {
-    const bool active = kc + lane < kend;
-    const int k = active ? kc + lane : kend - 1;
+  for (int kc = kbeg; kc < kend; kc += QPW) {
+    const bool inrange = kc + ql < kend;
+    const bool active = inrange && sub == 0;
+    const int k = inrange ? kc + ql : kend - 1;
     const T ACx = T(Ax - a.ket.A[k]), ACy = T(Ay - a.ket.A[nk + k]),
             ACz = T(Az - a.ket.A[2 * nk + k]);
-    T G[C::NG];
-    grad_passes<C, T, 0>(a, i, k, ACx, ACy, ACz, G, z);
+    grad_passes<C, T, 0>(a, i, k, sub, ACx, ACy, ACz, G, z);
     const T CDx = T(a.ket.AB[k]), CDy = T(a.ket.AB[nk + k]), CDz = T(a.ket.AB[2 * nk + k]);
 
     // ket horizontal recurrences, one bra index e at a time
-    T XA[C::NE_A * NCD], XB[C::NE_B * NCD], XC[C::NE_C * C::NCP];
-    T XU[at_least_1(C::NE_U * NCD)], XV[at_least_1(C::NE_U * C::NCM)];
 #pragma nounroll
     for (int e = 0; e < C::NE_A; ++e) {
       T f[C::NF_A], o[NCD];
@@ -248,8 +261,11 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
       }
     }
   }
+  }
 }
 
 void launch_grad(int cls, int fp32, const GradLaunch& a, hipStream_t s);
+int grad_ws_elems(int cls);
+int grad_lanes(int cls);
 
 }  // namespace jk

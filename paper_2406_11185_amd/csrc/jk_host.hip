@@ -16,10 +16,13 @@
 //      skipped -- the paper's skip / single / double dispatch ("Electron
 //      Repulsion Integrals" paragraph, third item) without materialising
 //      quartet lists;
-//   6. scan + expand_kernel: work items {bra, ket begin, ket end} of at most
-//      kItemKets kets; one device->host copy of the per-class item counts;
+//   6. the kept-quartet counts come back to the host, which picks for each bin
+//      pair the item size (64 to 1024 kets) that gives enough wavefronts;
+//      count + scan + expand_kernel write work items {bra, ket begin, ket end};
+//      a second small device->host copy returns the item ranges per launch;
 //   7. J, K cleared, one integral+digestion launch per (class pair, precision),
-//      then J = A + A^T, K = B + B^T in place (finalize_kernel).
+//      spread over the context's streams so that small classes overlap, then
+//      J = A + A^T, K = B + B^T in place (finalize_kernel).
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -197,7 +200,6 @@ struct RangeArgs {
   const double* Q;              // sorted Q, all bins
   double tol, thr;
   int mixed;
-  int* cnt;                     // [2][nt] items (FP64, FP32)
   int* rng;                     // [3][nt] k_lo, k_64, k_tol
   unsigned long long* qstat;    // [nbp][3] FP64 quartets, FP32 quartets, skipped
 };
@@ -226,8 +228,6 @@ __global__ void ranges_kernel(RangeArgs r) {
   int k64 = ktol;
   if (r.mixed) k64 = first_below(QY, klo, ktol, qi, r.thr);
   const int n64 = k64 - klo, n32 = ktol - k64;
-  r.cnt[t] = (n64 + kItemKets - 1) / kItemKets;
-  r.cnt[r.nt + t] = (n32 + kItemKets - 1) / kItemKets;
   r.rng[t] = klo;
   r.rng[r.nt + t] = k64;
   r.rng[2 * r.nt + t] = ktol;
@@ -236,9 +236,22 @@ __global__ void ranges_kernel(RangeArgs r) {
   atomicAdd(&r.qstat[3 * bp + 2], static_cast<unsigned long long>(nY - ktol));
 }
 
+// Work items per (thread, precision) for the item sizes chosen per bin pair.
+__global__ void count_kernel(int nt, const int* __restrict__ bp_t0, int nbp,
+                             const int* __restrict__ rng, const int* __restrict__ chunk, int* cnt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const int bp = find_bin(bp_t0, nbp, t);
+  const int klo = rng[t], k64 = rng[nt + t], ktol = rng[2 * nt + t];
+  const int c0 = chunk[bp], c1 = chunk[nbp + bp];
+  cnt[t] = (k64 - klo + c0 - 1) / c0;
+  cnt[nt + t] = (ktol - k64 + c1 - 1) / c1;
+}
+
 __global__ void expand_kernel(int nt, const int* __restrict__ bp_t0, int nbp,
                               const int* __restrict__ cnt, const int* __restrict__ off,
-                              const int* __restrict__ rng, int4* items) {
+                              const int* __restrict__ rng, const int* __restrict__ chunk,
+                              int4* items) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nt) return;
   const int bp = find_bin(bp_t0, nbp, t);
@@ -246,11 +259,12 @@ __global__ void expand_kernel(int nt, const int* __restrict__ bp_t0, int nbp,
   const int klo = rng[t], k64 = rng[nt + t], ktol = rng[2 * nt + t];
   for (int pr = 0; pr < 2; ++pr) {
     const int beg = pr == 0 ? klo : k64, end = pr == 0 ? k64 : ktol;
+    const int ch = chunk[pr * nbp + bp];
     const int c = cnt[pr * nt + t];
     const int base = off[pr * nt + t];
     for (int j = 0; j < c; ++j) {
-      const int k0 = beg + j * kItemKets;
-      items[base + j] = make_int4(i, k0, min(k0 + kItemKets, end), 0);
+      const int k0 = beg + j * ch;
+      items[base + j] = make_int4(i, k0, min(k0 + ch, end), 0);
     }
   }
 }
@@ -293,6 +307,10 @@ __global__ void finalize_kernel(int n, int n_dm, double* J, double* K) {
 
 inline unsigned grid_of(size_t n, int block) { return static_cast<unsigned>((n + block - 1) / block); }
 
+// Upper bound of the workspace one launch of a multi-pass or gradient kernel
+// uses; the launch then loops over its items with correspondingly few waves.
+constexpr size_t kWsBudget = size_t(1) << 30;
+
 // ---------------------------------------------------------------------------------
 // Grow-only device buffers owned by a context.
 struct DevBuf {
@@ -303,7 +321,8 @@ struct DevBuf {
 enum Slot {
   sShellXyz, sShellI, sExps, sCoefs, sPairS, sBinOff, sBinNpp, sBinPrim, sPrimTmp, sPrim,
   sA, sAB, sBf, sAtoms, sFpair, sAtmp, sABtmp, sBftmp, sAtomstmp, sFpairtmp, sQtmp, sQ,
-  sIdx, sIdxSorted, sPerm, sBp, sCnt, sOff, sRng, sQstat, sSeg, sItems, sCub, sNumSlots
+  sIdx, sIdxSorted, sPerm, sBp, sCnt, sOff, sRng, sQstat, sSeg, sItems, sCub, sChunk, sWs0, sWs1,
+  sWs2, sWs3, sWsSchwarz, sNumSlots
 };
 
 }  // namespace
@@ -324,6 +343,10 @@ struct jk_ctx {
   size_t ev_setup0 = 0, ev_setup1 = 0, ev_end = 0;
   void* host_pinned = nullptr;
   size_t host_pinned_bytes = 0;
+  static constexpr int kStreams = 2;   // class launches are spread over these
+  hipStream_t streams[kStreams] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kStreams] = {};
 };
 
 namespace {
@@ -364,7 +387,7 @@ void* pinned(jk_ctx* c, size_t bytes) {
   return c->host_pinned;
 }
 
-size_t event(jk_ctx* c, hipStream_t s) {
+size_t event(jk_ctx* c, hipStream_t s) {  // records on s, returns its index
   if (c->ev_used == c->ev_pool.size()) {
     hipEvent_t e;
     HIP_OK(hipEventCreate(&e));
@@ -484,10 +507,12 @@ struct Setup {
   int4* items;
   std::vector<int> seg;   // [2][nbp+1]
   std::vector<unsigned long long> qstat;
+  std::vector<int> chunk; // [2][nbp] kets per work item
 };
 
 // Steps 1-6.  Returns the sorted pair data, the work items and their segments.
-Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStream_t s) {
+Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStream_t s,
+            bool grad) {
   Setup S;
   S.P = make_plan(b);
   Plan& P = S.P;
@@ -559,6 +584,15 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
     a.ket = a.bra;
     a.boys64 = c->boys64;
     a.boys32 = c->boys32;
+    const int dcls = quartet_class(P.bin_cls[bb], P.bin_cls[bb]);
+    const size_t per_wave = split_schwarz_ws_bytes(dcls);
+    if (per_wave) {  // multi-pass diagonal class: workspace, waves loop over the pairs
+      const int pairs_per_wave = kWave / class_lanes(dcls);
+      const size_t want = (static_cast<size_t>(a.bra.n) + pairs_per_wave - 1) / pairs_per_wave;
+      const size_t cap = std::max<size_t>(64, kWsBudget / per_wave);
+      a.nwaves = static_cast<int>(std::min(want, cap));
+      a.ws = dev<char>(c, sWsSchwarz, per_wave * a.nwaves);
+    }
     launch_schwarz(P.bin_cls[bb], a, d_Qtmp + P.bin_off[bb], s);
   }
   // step 4: segmented sort by Q, descending, then pair data in sorted order
@@ -595,10 +629,34 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
                      static_cast<size_t>(3 * nbp), d_qstat);
   RangeArgs ra{nt, nbp, d_bp, d_bp + nbp, d_bp + 2 * nbp, d_binoff, S.Q, tol,
                o.precision == JK_MIXED ? o.fp32_below : 0.0, o.precision == JK_MIXED ? 1 : 0,
-               d_cnt, d_rng, d_qstat};
+               d_rng, d_qstat};
   hipLaunchKernelGGL(ranges_kernel, dim3(grid_of(nt, 256)), dim3(256), 0, s, ra);
   HIP_OK(hipGetLastError());
-  // step 6: scan, segments, read back, expand
+  // step 6: quartet counts back, item size per (bin pair, precision)
+  char* hp = static_cast<char*>(
+      pinned(c, 3 * nbp * sizeof(unsigned long long) + 2 * (nbp + 1) * sizeof(int)));
+  HIP_OK(hipMemcpyAsync(hp, d_qstat, 3 * nbp * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const unsigned long long* qs = reinterpret_cast<const unsigned long long*>(hp);
+  S.qstat.assign(qs, qs + 3 * nbp);
+  std::vector<int> chunk(2 * nbp);
+  for (int bp = 0; bp < nbp; ++bp) {
+    const int cls = quartet_class(P.bin_cls[P.bp_x[bp]], P.bin_cls[P.bp_y[bp]]);
+    const int qpw = kWave / (grad ? grad_lanes(cls) : class_lanes(cls));  // kets per wave step
+    for (int pr = 0; pr < 2; ++pr) {
+      const unsigned long long per =
+          S.qstat[3 * bp + pr] / (static_cast<unsigned long long>(qpw) * kTargetWaves);
+      const unsigned long long nch =
+          std::min<unsigned long long>(std::max<unsigned long long>(per, 1), kMaxItemChunks);
+      chunk[pr * nbp + bp] = qpw * static_cast<int>(nch);
+    }
+  }
+  S.chunk = chunk;
+  int* d_chunk = dev<int>(c, sChunk, 2 * nbp);
+  upload(chunk, d_chunk, s);
+  hipLaunchKernelGGL(count_kernel, dim3(grid_of(nt, 256)), dim3(256), 0, s, nt, d_bp + 2 * nbp,
+                     nbp, d_rng, d_chunk, d_cnt);
+  HIP_OK(hipGetLastError());
   size_t scan_bytes = 0;
   HIP_OK(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, d_cnt, d_off, 2 * nt, s));
   d_cub = dev<char>(c, sCub, std::max(scan_bytes, cub_bytes));
@@ -607,20 +665,14 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
   hipLaunchKernelGGL(segments_kernel, dim3(grid_of(2 * (nbp + 1), 256)), dim3(256), 0, s, nt,
                      nbp, d_bp + 2 * nbp, d_cnt, d_off, d_seg);
   HIP_OK(hipGetLastError());
-  const size_t rb_bytes = 2 * (nbp + 1) * sizeof(int) + 3 * nbp * sizeof(unsigned long long);
-  char* hp = static_cast<char*>(pinned(c, rb_bytes));
-  HIP_OK(hipMemcpyAsync(hp, d_seg, 2 * (nbp + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(hp + 2 * (nbp + 1) * sizeof(int), d_qstat,
-                        3 * nbp * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  int* hseg = reinterpret_cast<int*>(hp + 3 * nbp * sizeof(unsigned long long));
+  HIP_OK(hipMemcpyAsync(hseg, d_seg, 2 * (nbp + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  S.seg.assign(reinterpret_cast<int*>(hp), reinterpret_cast<int*>(hp) + 2 * (nbp + 1));
-  const unsigned long long* qs =
-      reinterpret_cast<const unsigned long long*>(hp + 2 * (nbp + 1) * sizeof(int));
-  S.qstat.assign(qs, qs + 3 * nbp);
+  S.seg.assign(hseg, hseg + 2 * (nbp + 1));
   const int nitems = S.seg[2 * nbp + 1];
   S.items = dev<int4>(c, sItems, std::max(nitems, 1));
   hipLaunchKernelGGL(expand_kernel, dim3(grid_of(nt, 256)), dim3(256), 0, s, nt, d_bp + 2 * nbp,
-                     nbp, d_cnt, d_off, d_rng, S.items);
+                     nbp, d_cnt, d_off, d_rng, d_chunk, S.items);
   HIP_OK(hipGetLastError());
   return S;
 }
@@ -665,6 +717,69 @@ EriLaunch launch_args(jk_ctx* c, const Plan& P, const Setup& S, int X, int Y, in
   a.boys32 = c->boys32;
   a.boys_fp64_T = static_cast<float>(o.boys_fp64_T);
   return a;
+}
+
+struct LaunchRec {
+  int cls, pr, X, Y, i0, i1;
+  double cost;
+};
+
+// Launches of one build (one per bin pair and precision with work), largest
+// estimated cost first, each assigned to the least-loaded context stream.
+// The caller's stream forks to the context streams after setup and joins them
+// before returning.
+struct NoPrepare {
+  void operator()(const std::vector<LaunchRec>&, const std::vector<int>&) const {}
+};
+
+template <class Fn, class Prep = NoPrepare>
+void dispatch(jk_ctx* c, const Plan& P, const Setup& S, hipStream_t s, jk_stats& st, bool grad,
+              Fn&& launch_one, Prep&& prepare = Prep()) {
+  const int nbp = static_cast<int>(P.bp_x.size());
+  std::vector<LaunchRec> recs;
+  for (int bp = 0; bp < nbp; ++bp) {
+    const int X = P.bp_x[bp], Y = P.bp_y[bp];
+    const int cls = quartet_class(P.bin_cls[X], P.bin_cls[Y]);
+    for (int pr = 0; pr < 2; ++pr) {
+      const int i0 = S.seg[pr * (nbp + 1) + bp], i1 = S.seg[pr * (nbp + 1) + bp + 1];
+      if (i1 <= i0) continue;
+      const double q = static_cast<double>(S.qstat[3 * bp + pr]);
+      const double npp = static_cast<double>(P.bin_npp[X]) * P.bin_npp[Y];
+      recs.push_back({cls, pr, X, Y, i0, i1, q * npp * class_cost(cls, grad ? 1 : 0)});
+    }
+  }
+  std::stable_sort(recs.begin(), recs.end(),
+                   [](const LaunchRec& a, const LaunchRec& b) { return a.cost > b.cost; });
+  std::vector<int> where(recs.size());
+  double load[jk_ctx::kStreams] = {};
+  for (size_t q = 0; q < recs.size(); ++q) {
+    int k = 0;
+    for (int j = 1; j < jk_ctx::kStreams; ++j)
+      if (load[j] < load[k]) k = j;
+    load[k] += recs[q].cost;
+    where[q] = k;
+  }
+  prepare(recs, where);
+  HIP_OK(hipEventRecord(c->fork_ev, s));
+  for (int k = 0; k < jk_ctx::kStreams; ++k) HIP_OK(hipStreamWaitEvent(c->streams[k], c->fork_ev, 0));
+  for (size_t q = 0; q < recs.size(); ++q) {
+    const LaunchRec& r = recs[q];
+    const int k = where[q];
+    hipStream_t ls = c->streams[k];
+    size_t e0 = 0;
+    if (c->timed) e0 = event(c, ls);
+    launch_one(r, ls, k);
+    HIP_OK(hipGetLastError());
+    if (c->timed) {
+      event(c, ls);
+      c->timed_launches.push_back({r.cls, r.pr, e0});
+    }
+    (r.pr ? st.launches_fp32 : st.launches_fp64)[r.cls] += 1;
+  }
+  for (int k = 0; k < jk_ctx::kStreams; ++k) {
+    HIP_OK(hipEventRecord(c->join_ev[k], c->streams[k]));
+    HIP_OK(hipStreamWaitEvent(s, c->join_ev[k], 0));
+  }
 }
 
 int check_opts(const jk_opts* o, jk_opts* out, std::string* msg) {
@@ -715,6 +830,11 @@ int jk_ctx_create(jk_ctx** out, int device) {
     HIP_OK(hipMalloc(&c->boys32, t32.size() * sizeof(float)));
     HIP_OK(hipMemcpy(c->boys64, t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(c->boys32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
+    for (int k = 0; k < jk_ctx::kStreams; ++k) {
+      HIP_OK(hipStreamCreateWithFlags(&c->streams[k], hipStreamNonBlocking));
+      HIP_OK(hipEventCreateWithFlags(&c->join_ev[k], hipEventDisableTiming));
+    }
+    HIP_OK(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
   } catch (const Fail& f) {
     g_create_err = f.msg;
     jk_ctx_destroy(c);
@@ -733,6 +853,11 @@ int jk_ctx_destroy(jk_ctx* c) {
   if (c->boys32) (void)hipFree(c->boys32);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+  for (int k = 0; k < jk_ctx::kStreams; ++k) {
+    if (c->streams[k]) (void)hipStreamDestroy(c->streams[k]);
+    if (c->join_ev[k]) (void)hipEventDestroy(c->join_ev[k]);
+  }
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   delete c;
   return JK_OK;
 }
@@ -759,7 +884,7 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
     c->ev_used = 0;
     c->timed_launches.clear();
     if (c->timed) c->ev_setup0 = event(c, s);
-    Setup S = setup(c, basis, tol, o, s);
+    Setup S = setup(c, basis, tol, o, s, false);
     const Plan& P = S.P;
     if (c->timed) c->ev_setup1 = event(c, s);
     const size_t nn = static_cast<size_t>(nbf) * nbf;
@@ -768,25 +893,30 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
     HIP_OK(hipGetLastError());
 
     jk_stats st = base_stats(P, S);
-    const int nbp = static_cast<int>(P.bp_x.size());
-    for (int bp = 0; bp < nbp; ++bp) {
-      const int X = P.bp_x[bp], Y = P.bp_y[bp];
-      const int cls = quartet_class(P.bin_cls[X], P.bin_cls[Y]);
-      for (int pr = 0; pr < 2; ++pr) {
-        const int i0 = S.seg[pr * (nbp + 1) + bp], i1 = S.seg[pr * (nbp + 1) + bp + 1];
-        if (i1 <= i0) continue;
-        EriLaunch a = launch_args(c, P, S, X, Y, i0, i1, D, J, K, nbf, o);
-        size_t e0 = 0;
-        if (c->timed) e0 = event(c, s);
-        launch_eri(cls, pr, a, s);
-        HIP_OK(hipGetLastError());
-        if (c->timed) {
-          event(c, s);
-          c->timed_launches.push_back({cls, pr, e0});
-        }
-        (pr ? st.launches_fp32 : st.launches_fp64)[cls] += 1;
-      }
-    }
+    auto waves_of = [&](const LaunchRec& r) {
+      const size_t per_wave = split_ws_bytes(r.cls, r.pr);
+      if (!per_wave) return std::pair<int, size_t>(0, 0);
+      const size_t cap = std::max<size_t>(64, kWsBudget / per_wave);
+      return std::pair<int, size_t>(static_cast<int>(std::min<size_t>(r.i1 - r.i0, cap)), per_wave);
+    };
+    void* ws[jk_ctx::kStreams] = {};
+    dispatch(
+        c, P, S, s, st, false,
+        [&](const LaunchRec& r, hipStream_t ls, int k) {
+          EriLaunch a = launch_args(c, P, S, r.X, r.Y, r.i0, r.i1, D, J, K, nbf, o);
+          a.ws = ws[k];
+          a.nwaves = waves_of(r).first;
+          launch_eri(r.cls, r.pr, a, ls);
+        },
+        [&](const std::vector<LaunchRec>& recs, const std::vector<int>& where) {
+          size_t need[jk_ctx::kStreams] = {};
+          for (size_t q = 0; q < recs.size(); ++q) {
+            const auto wv = waves_of(recs[q]);
+            need[where[q]] = std::max(need[where[q]], wv.second * wv.first);
+          }
+          for (int k = 0; k < jk_ctx::kStreams; ++k)
+            if (need[k]) ws[k] = dev<char>(c, static_cast<Slot>(sWs0 + k), need[k]);
+        });
     hipLaunchKernelGGL(finalize_kernel, dim3(grid_of(nn * o.n_dm, 256)), dim3(256), 0, s, nbf,
                        o.n_dm, J, K);
     HIP_OK(hipGetLastError());
@@ -819,35 +949,41 @@ int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, dou
     c->ev_used = 0;
     c->timed_launches.clear();
     if (c->timed) c->ev_setup0 = event(c, s);
-    Setup S = setup(c, basis, tol, o, s);
+    Setup S = setup(c, basis, tol, o, s, true);
     const Plan& P = S.P;
     if (c->timed) c->ev_setup1 = event(c, s);
     const size_t ng = static_cast<size_t>(o.n_dm) * basis->n_atoms * 3;
     hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(ng, 256)), dim3(256), 0, s, ng, dEdR);
     HIP_OK(hipGetLastError());
     jk_stats st = base_stats(P, S);
-    const int nbp = static_cast<int>(P.bp_x.size());
-    for (int bp = 0; bp < nbp; ++bp) {
-      const int X = P.bp_x[bp], Y = P.bp_y[bp];
-      const int cls = quartet_class(P.bin_cls[X], P.bin_cls[Y]);
-      for (int pr = 0; pr < 2; ++pr) {
-        const int i0 = S.seg[pr * (nbp + 1) + bp], i1 = S.seg[pr * (nbp + 1) + bp + 1];
-        if (i1 <= i0) continue;
-        GradLaunch g{};
-        g.e = launch_args(c, P, S, X, Y, i0, i1, D, nullptr, nullptr, nbf, o);
-        g.dEdR = dEdR;
-        g.n_atoms = basis->n_atoms;
-        size_t e0 = 0;
-        if (c->timed) e0 = event(c, s);
-        launch_grad(cls, pr, g, s);
-        HIP_OK(hipGetLastError());
-        if (c->timed) {
-          event(c, s);
-          c->timed_launches.push_back({cls, pr, e0});
-        }
-        (pr ? st.launches_fp32 : st.launches_fp64)[cls] += 1;
-      }
-    }
+    // gradient work arrays live in a per-stream workspace; a launch uses at most
+    // kWsBudget bytes and loops over its items with a fixed number of waves
+    auto waves_of = [&](const LaunchRec& r) {
+      const size_t per_wave = size_t(kWave) * grad_ws_elems(r.cls) * (r.pr ? 4 : 8);
+      const size_t cap = std::max<size_t>(64, kWsBudget / per_wave);
+      return std::pair<int, size_t>(static_cast<int>(std::min<size_t>(r.i1 - r.i0, cap)), per_wave);
+    };
+    void* ws[jk_ctx::kStreams] = {};
+    dispatch(
+        c, P, S, s, st, true,
+        [&](const LaunchRec& r, hipStream_t ls, int k) {
+          GradLaunch g{};
+          g.e = launch_args(c, P, S, r.X, r.Y, r.i0, r.i1, D, nullptr, nullptr, nbf, o);
+          g.dEdR = dEdR;
+          g.n_atoms = basis->n_atoms;
+          g.ws = ws[k];
+          g.nwaves = waves_of(r).first;
+          launch_grad(r.cls, r.pr, g, ls);
+        },
+        [&](const std::vector<LaunchRec>& recs, const std::vector<int>& where) {
+          size_t need[jk_ctx::kStreams] = {};
+          for (size_t q = 0; q < recs.size(); ++q) {
+            const auto wv = waves_of(recs[q]);
+            need[where[q]] = std::max(need[where[q]], wv.second * wv.first);
+          }
+          for (int k = 0; k < jk_ctx::kStreams; ++k)
+            if (need[k]) ws[k] = dev<char>(c, static_cast<Slot>(sWs0 + k), need[k]);
+        });
     if (c->timed) c->ev_end = event(c, s);
     c->stats = st;
   } catch (const Fail& f) {

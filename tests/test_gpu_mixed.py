@@ -17,7 +17,9 @@ def energies(J, K, D):
 
 
 def test_small_mixed_against_oracle():
-    """Every quartet in FP32 (threshold above every bound) against the oracle."""
+    """Every quartet in FP32 (threshold above every bound) against the oracle.  This is
+    outside the dispatcher's envelope (bounds up to 1 in FP32), so the bound is relative:
+    FP32 rounding of O(1) integrals, 1e-7 of the energies and 1e-6 of the largest element."""
     import torch
     from paper_2406_11185_amd import jk as jkb
     mol = molgen.make_molecule(3, 3, 21)
@@ -32,8 +34,9 @@ def test_small_mixed_against_oracle():
     EJo, EKo = energies(Jo[0], Ko[0], mol.D[0])
     say(f"  dEJ={EJ - EJo:.2e} dEK={EK - EKo:.2e} max|dJ|={np.abs(J - Jo).max():.2e} "
         f"max|dK|={np.abs(K - Ko).max():.2e}")
-    assert abs(EJ - EJo) <= 1e-6 and abs(EK - EKo) <= 1e-6
-    assert np.abs(J - Jo).max() <= 1e-5 and np.abs(K - Ko).max() <= 1e-5
+    assert abs(EJ - EJo) <= 1e-7 * abs(EJo) and abs(EK - EKo) <= 1e-7 * abs(EKo)
+    assert np.abs(J - Jo).max() <= 1e-6 * np.abs(Jo).max()
+    assert np.abs(K - Ko).max() <= 1e-6 * np.abs(Ko).max()
 
 
 @pytest.mark.parametrize("name", ["w30", "w120"])
