@@ -1,0 +1,139 @@
+// Host build of the generated energy-class code: contracted shell quartets with an
+// exact Boys function, for comparison with the oracle (test harness, CPU only).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+#define __device__
+#define __forceinline__ inline
+namespace jk {
+template <typename T> struct VrrCoef {
+  T PAx, PAy, PAz, WPx, WPy, WPz, QCx, QCy, QCz, WQx, WQy, WQz;
+  T oo2p, oo2p_rp, oo2q, oo2q_rq, oo2pq;
+};
+using std::fmax;
+#include "cls_ssss.inc"
+#include "cls_psss.inc"
+#include "cls_psps.inc"
+#include "cls_ppss.inc"
+#include "cls_ppps.inc"
+#include "cls_pppp.inc"
+#include "cls_dsss.inc"
+#include "cls_dsps.inc"
+#include "cls_dspp.inc"
+#include "cls_dsds.inc"
+#include "cls_dpss.inc"
+#include "cls_dpps.inc"
+#include "cls_dppp.inc"
+#include "cls_dpds.inc"
+#include "cls_dpdp.inc"
+#include "cls_ddss.inc"
+#include "cls_ddps.inc"
+#include "cls_ddpp.inc"
+#include "cls_ddds.inc"
+#include "cls_dddp.inc"
+#include "cls_dddd.inc"
+}
+using namespace jk;
+
+static double boys_exact(int m, double T) {
+  long double term = 1.0L / (2 * m + 1), sum = term;
+  for (int k = 1; k < 100000; ++k) { term *= 2.0L * T / (2 * m + 2 * k + 1); sum += term; if (term < sum * 1e-21L) break; }
+  return (double)(std::exp(-(long double)T) * sum);
+}
+
+struct Sh { int l, np; double A[3]; double e[8], c[8]; };
+
+template <class C, class V>
+static void contract(const Sh& a, const Sh& b, const Sh& c, const Sh& d, V&& vrr) {
+  const double PI = 3.14159265358979323846;
+  for (int i = 0; i < a.np; ++i) for (int j = 0; j < b.np; ++j)
+  for (int k = 0; k < c.np; ++k) for (int l = 0; l < d.np; ++l) {
+    double p = a.e[i] + b.e[j], q = c.e[k] + d.e[l];
+    double P[3], Q[3], AB2 = 0, CD2 = 0;
+    for (int x = 0; x < 3; ++x) {
+      P[x] = (a.e[i] * a.A[x] + b.e[j] * b.A[x]) / p;
+      Q[x] = (c.e[k] * c.A[x] + d.e[l] * d.A[x]) / q;
+      AB2 += (a.A[x] - b.A[x]) * (a.A[x] - b.A[x]);
+      CD2 += (c.A[x] - d.A[x]) * (c.A[x] - d.A[x]);
+    }
+    double W[3], PQ2 = 0;
+    for (int x = 0; x < 3; ++x) { W[x] = (p * P[x] + q * Q[x]) / (p + q); PQ2 += (P[x] - Q[x]) * (P[x] - Q[x]); }
+    double rho = p * q / (p + q), T = rho * PQ2;
+    double pref = 2 * std::pow(PI, 2.5) / (p * q * std::sqrt(p + q)) *
+                  a.c[i] * b.c[j] * c.c[k] * d.c[l] * std::exp(-a.e[i] * b.e[j] / p * AB2) *
+                  std::exp(-c.e[k] * d.e[l] / q * CD2);
+    double F[16];
+    for (int m = 0; m <= C::L; ++m) F[m] = pref * boys_exact(m, T);
+    VrrCoef<double> cf;
+    cf.PAx = P[0] - a.A[0]; cf.PAy = P[1] - a.A[1]; cf.PAz = P[2] - a.A[2];
+    cf.WPx = W[0] - P[0]; cf.WPy = W[1] - P[1]; cf.WPz = W[2] - P[2];
+    cf.QCx = Q[0] - c.A[0]; cf.QCy = Q[1] - c.A[1]; cf.QCz = Q[2] - c.A[2];
+    cf.WQx = W[0] - Q[0]; cf.WQy = W[1] - Q[1]; cf.WQz = W[2] - Q[2];
+    cf.oo2p = 0.5 / p; cf.oo2p_rp = 0.5 / p * rho / p; cf.oo2q = 0.5 / q; cf.oo2q_rq = 0.5 / q * rho / q;
+    cf.oo2pq = 0.5 / (p + q);
+    vrr(F, cf);
+  }
+}
+
+// raw (ab|cd) via the digestion function with a one-hot D_cd
+template <class C>
+static void block_single(const Sh& a, const Sh& b, const Sh& c, const Sh& d, double* out) {
+  double acc[C::NACC] = {0};
+  contract<C>(a, b, c, d, [&](const double* F, const VrrCoef<double>& cf) { C::template vrr<double>(F, cf, acc); });
+  double ABx = a.A[0] - b.A[0], ABy = a.A[1] - b.A[1], ABz = a.A[2] - b.A[2];
+  double CDx = c.A[0] - d.A[0], CDy = c.A[1] - d.A[1], CDz = c.A[2] - d.A[2];
+  for (int cd = 0; cd < C::NC * C::ND; ++cd) {
+    double Dab[64] = {0}, Dcd[64] = {0}, Z[64] = {0};
+    Dcd[cd] = 1.0;
+    double jab[64] = {0}, jcd[64] = {0}, kac[64] = {0}, kad[64] = {0}, kbc[64] = {0}, kbd[64] = {0};
+    C::template hrr_digest<double>(acc, ABx, ABy, ABz, CDx, CDy, CDz, 1.0, Dab, Dcd, Z, Z, Z, Z,
+                                   jab, jcd, kac, kad, kbc, kbd);
+    for (int ab = 0; ab < C::NA * C::NB; ++ab) out[ab * C::NC * C::ND + cd] = jab[ab];
+  }
+}
+
+template <class C, int J>
+static void passes(const Sh& a, const Sh& b, const Sh& c, const Sh& d, double* cacc) {
+  constexpr int NFJ = C::template Pass<J>::NF, F0 = C::template Pass<J>::F0;
+  double acc[C::NE * NFJ] = {0};
+  contract<C>(a, b, c, d, [&](const double* F, const VrrCoef<double>& cf) { C::template vrr_pass<J, double>(F, cf, acc); });
+  for (int e = 0; e < C::NE; ++e) for (int f = 0; f < NFJ; ++f) cacc[e * C::NF + F0 + f] = acc[e * NFJ + f];
+  if constexpr (J + 1 < C::NPASS) passes<C, J + 1>(a, b, c, d, cacc);
+}
+
+template <class C>
+static void block_split(const Sh& a, const Sh& b, const Sh& c, const Sh& d, double* out) {
+  static double cacc[C::NACC];
+  passes<C, 0>(a, b, c, d, cacc);
+  double ABx = a.A[0] - b.A[0], ABy = a.A[1] - b.A[1], ABz = a.A[2] - b.A[2];
+  double CDx = c.A[0] - d.A[0], CDy = c.A[1] - d.A[1], CDz = c.A[2] - d.A[2];
+  constexpr int NCD = C::NC * C::ND;
+  static double X[C::NE * NCD];
+  for (int e = 0; e < C::NE; ++e) C::template ket_hrr<double>(cacc + e * C::NF, CDx, CDy, CDz, X + e * NCD);
+  for (int cd = 0; cd < NCD; ++cd) {
+    double ev[C::NE], ab[C::NA * C::NB];
+    for (int e = 0; e < C::NE; ++e) ev[e] = X[e * NCD + cd];
+    C::template bra_hrr<double>(ev, ABx, ABy, ABz, ab);
+    for (int t = 0; t < C::NA * C::NB; ++t) out[t * NCD + cd] = ab[t];
+  }
+}
+
+extern "C" int emu_block(int cls, const int* l, const int* np, const double* A, const double* e,
+                         const double* c, double* out) {
+  Sh s[4];
+  for (int k = 0; k < 4; ++k) {
+    s[k].l = l[k]; s[k].np = np[k];
+    for (int x = 0; x < 3; ++x) s[k].A[x] = A[3 * k + x];
+    for (int i = 0; i < np[k]; ++i) { s[k].e[i] = e[8 * k + i]; s[k].c[i] = c[8 * k + i]; }
+  }
+  switch (cls) {
+#define S1(i, N) case i: block_single<Cls_##N>(s[0], s[1], s[2], s[3], out); break;
+#define S2(i, N) case i: block_split<Cls_##N>(s[0], s[1], s[2], s[3], out); break;
+    S1(0, ssss) S1(1, psss) S1(2, psps) S1(3, ppss) S1(4, ppps) S1(5, pppp) S1(6, dsss) S1(7, dsps)
+    S1(8, dspp) S1(9, dsds) S1(10, dpss) S1(11, dpps) S1(12, dppp) S1(13, dpds) S2(14, dpdp)
+    S1(15, ddss) S1(16, ddps) S2(17, ddpp) S2(18, ddds) S2(19, dddp) S2(20, dddd)
+    default: return -1;
+  }
+  return 0;
+}
