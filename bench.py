@@ -102,6 +102,9 @@ def main():
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="before the steps, copy a buffer of this many MiB once (a kernel of "
+                         "known traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -125,6 +128,12 @@ def main():
     ctx = jkb.Context(0)
     opts = jkb.make_opts(precision, n_dm=D.shape[0], timing=True)
 
+    if args.copy_calib_mib:
+        src = torch.ones(args.copy_calib_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         jkb.jk_build(ctx, basis, D, J, K, tol, opts)
     torch.cuda.synchronize()

@@ -159,7 +159,7 @@ def gen_grad_class(la, lb, lc, ld):
          f"  static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld}, L = {L1};",
          f"  static constexpr int NA = {na}, NB = {nb}, NC = {nc}, ND = {nd}, NG = {NG};",
          f"  static constexpr int NPASS = {len(passes)}, USE_U = {1 if use_u else 0};",
-         f"  static constexpr int G = {grad_lanes(NG, len(passes))};  // lanes per shell quartet"]
+         f"  static constexpr int GMAX = {grad_lanes(NG, len(passes))};  // most lanes per shell quartet"]
     # set geometry
     for nm, w, Es, Fs in sets:
         s.append(f"  static constexpr int OFF_{nm} = {off[nm]}, NE_{nm} = {len(Es)}, NF_{nm} = {len(Fs)};")
@@ -309,8 +309,9 @@ def wrapper(name):
         f'#include "gcls_{name}.inc"',
         f"void launch_grad_{name}(const GradLaunch& a, int fp32, hipStream_t s) {{",
         "  const dim3 grid((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);",
-        f"  if (fp32) hipLaunchKernelGGL((grad_kernel<GCls_{name}, float>), grid, block, 0, s, a);",
-        f"  else hipLaunchKernelGGL((grad_kernel<GCls_{name}, double>), grid, block, 0, s, a);",
+        f"  constexpr int GM = GCls_{name}::GMAX;  // gradient launches always use the class maximum",
+        f"  if (fp32) hipLaunchKernelGGL((grad_kernel<GCls_{name}, float, GM>), grid, block, 0, s, a);",
+        f"  else hipLaunchKernelGGL((grad_kernel<GCls_{name}, double, GM>), grid, block, 0, s, a);",
         "}",
         "}  // namespace jk", ""])
 

@@ -276,7 +276,7 @@ def gen_class(la, lb, lc, ld):
     s.append(f"  static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld}, L = {L};")
     s.append(f"  static constexpr int NA = {na}, NB = {nb}, NC = {nc}, ND = {nd};")
     s.append(f"  static constexpr int NE = {ne}, NF = {nf}, NACC = {ne * nf};")
-    s.append(f"  static constexpr int G = {lanes_for(L, False)};  // lanes per shell quartet")
+    s.append(f"  static constexpr int GMAX = {lanes_for(L, False)};  // most lanes per shell quartet")
     s.append(f"  static constexpr int VRR_FLOPS = {vrr_flops}, HRR_FLOPS = {hrr_flops}, "
              f"DIGEST_FLOPS = {dig_flops};")
     s.append("  template <typename T>")
@@ -397,7 +397,7 @@ def gen_split_class(la, lb, lc, ld):
     s.append(f"  static constexpr int NA = {na}, NB = {nb}, NC = {nc}, ND = {nd};")
     s.append(f"  static constexpr int NE = {ne}, NF = {nf}, NACC = {ne * nf};")
     s.append(f"  static constexpr int NPASS = {len(chunks)}, FCHUNK = {chunk};")
-    s.append(f"  static constexpr int G = {lanes_for(L, True)};  // lanes per shell quartet")
+    s.append(f"  static constexpr int GMAX = {lanes_for(L, True)};  // most lanes per shell quartet")
     vrr_flops = 0
     for j, ch in enumerate(chunks):
         v = VRR(L)
@@ -479,14 +479,20 @@ def wrapper(info):
          f"void launch_eri_{n}(const EriLaunch& a, int fp32, hipStream_t s) {{",
          "  const int waves = " + ("a.nwaves" if info["split"] else "a.nitems") + ";",
          "  const dim3 grid((waves + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);",
-         f"  if (fp32) hipLaunchKernelGGL(({kern}<Cls_{n}, float>), grid, block, 0, s, a);",
-         f"  else hipLaunchKernelGGL(({kern}<Cls_{n}, double>), grid, block, 0, s, a);",
+         f"  constexpr int GM = Cls_{n}::GMAX;",
+         f"  if (a.lanes > 1 && GM > 1) {{",
+         f"    if (fp32) hipLaunchKernelGGL(({kern}<Cls_{n}, float, GM>), grid, block, 0, s, a);",
+         f"    else hipLaunchKernelGGL(({kern}<Cls_{n}, double, GM>), grid, block, 0, s, a);",
+         "  } else {",
+         f"    if (fp32) hipLaunchKernelGGL(({kern}<Cls_{n}, float, 1>), grid, block, 0, s, a);",
+         f"    else hipLaunchKernelGGL(({kern}<Cls_{n}, double, 1>), grid, block, 0, s, a);",
+         "  }",
          "}"]
     if info["bra_class"] == info["ket_class"]:
         w += [f"void launch_schwarz_{n}(const EriLaunch& a, double* Q, hipStream_t s) {{",
               (f"  hipLaunchKernelGGL(({skern}<Cls_{n}>), dim3((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock),"
                " dim3(kBlock), 0, s, a, Q);") if info["split"] else
-              (f"  hipLaunchKernelGGL(({skern}<Cls_{n}>), dim3((a.bra.n * Cls_{n}::G + kBlock - 1) / kBlock),"
+              (f"  hipLaunchKernelGGL(({skern}<Cls_{n}>), dim3((a.bra.n * Cls_{n}::GMAX + kBlock - 1) / kBlock),"
                " dim3(kBlock), 0, s, a, Q);"),
               "}"]
     w.append("}  // namespace jk")

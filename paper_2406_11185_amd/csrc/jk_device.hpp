@@ -65,6 +65,7 @@ struct EriLaunch {
   float boys_fp64_T;  // FP32 kernels: F_m in FP64 above this T
   void* ws;           // multi-pass classes: per-wave workspace (see split_ws_bytes)
   int nwaves;         // multi-pass classes: wavefronts of the launch (item loop stride)
+  int lanes;          // lanes sharing one shell quartet in this launch (1 or the class maximum)
 };
 
 // Per-lane array in a launch workspace, lane-interleaved so that a wavefront
@@ -289,9 +290,10 @@ __device__ __forceinline__ void contract(const EriLaunch& a, int i, int k, int s
       }
     }
   } else {
-    const int npq = nppb * nppk;
-    for (int pq = sub; pq < npq; pq += G) {
-      const int kl = pq / nppb, ij = pq - kl * nppb;
+    // primitive quartets sub, sub+G, ... as (kl, ij) with ij running fastest
+    int kl = 0, ij = sub;
+    while (ij >= nppb) { ij -= nppb; ++kl; }
+    for (; kl < nppk;) {
       const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
       const double* bp = a.bra.prim + static_cast<size_t>(ij) * kPrimFields * nb + i;
       T F[L + 1];
@@ -301,6 +303,8 @@ __device__ __forceinline__ void contract(const EriLaunch& a, int i, int k, int s
                        T(kp[kPAx * nk]), T(kp[kPAy * nk]), T(kp[kPAz * nk]), T(kp[kKt * nk]),
                        ACx, ACy, ACz, a, F, c);
       vrr(F, c);
+      ij += G;
+      while (ij >= nppb) { ij -= nppb; ++kl; }
     }
   }
 }
@@ -342,9 +346,9 @@ __device__ __forceinline__ void atomic_add(double* addr, double v) {
 // Integral + digestion kernel of one class and precision.  One wavefront per
 // work item: the bra pair is uniform across the wave (scalar data), each lane
 // takes one ket pair of the current 64-wide chunk of the item's ket range.
-template <class C, typename T>
+template <class C, typename T, int G>
 __global__ __launch_bounds__(kBlock) void eri_jk_kernel(const EriLaunch a) {
-  constexpr int G = C::G, QPW = kWave / G;
+  constexpr int QPW = kWave / G;
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (G - 1), ql = lane / G;
   const int item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
@@ -455,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void eri_jk_kernel(const EriLaunch a) {
 // One lane per pair; bra and ket are the same pair, so A - C = 0.
 template <class C>
 __global__ __launch_bounds__(kBlock) void schwarz_kernel(const EriLaunch a, double* Qout) {
-  constexpr int G = C::G;
+  constexpr int G = C::GMAX;
   const int gt = blockIdx.x * kBlock + threadIdx.x;
   const int n = a.bra.n;
   if (gt / kWave * (kWave / G) >= n) return;   // whole wave past the end
@@ -480,22 +484,24 @@ __global__ __launch_bounds__(kBlock) void schwarz_kernel(const EriLaunch a, doub
 // primitive loop and parks the chunk in a private (scratch) array; the
 // horizontal recurrences then run as short loops: the ket step for one e at a
 // time into X[e][cd], the bra step plus digestion for one (c, d) at a time.
-template <class C, typename T, int J, class A>
+template <class C, typename T, int G, int J, class A>
 __device__ __forceinline__ void split_passes(const EriLaunch& a, int i, int k, int sub, T ACx,
                                              T ACy, T ACz, A cacc, int z) {
   constexpr int NFJ = C::template Pass<J>::NF, F0 = C::template Pass<J>::F0;
   T acc[C::NE * NFJ];
 #pragma unroll
   for (int t = 0; t < C::NE * NFJ; ++t) acc[t] = T(0);
-  contract<C::L, T, C::G>(a, i, k, sub, ACx, ACy, ACz, [&](const T* F, const VrrCoef<T>& c) {
+  contract<C::L, T, G>(a, i, k, sub, ACx, ACy, ACz, [&](const T* F, const VrrCoef<T>& c) {
     C::template vrr_pass<J, T>(F, c, acc);
   });
-  group_sum_all<C::G>(acc);
+  group_sum_all<G>(acc);
+  if (sub == 0) {  // the group's first lane carries the quartet from here on
 #pragma unroll
-  for (int e = 0; e < C::NE; ++e)
+    for (int e = 0; e < C::NE; ++e)
 #pragma unroll
-    for (int f = 0; f < NFJ; ++f) cacc[z + e * C::NF + F0 + f] = acc[e * NFJ + f];
-  if constexpr (J + 1 < C::NPASS) split_passes<C, T, J + 1, A>(a, i, k, sub, ACx, ACy, ACz, cacc, z);
+      for (int f = 0; f < NFJ; ++f) cacc[z + e * C::NF + F0 + f] = acc[e * NFJ + f];
+  }
+  if constexpr (J + 1 < C::NPASS) split_passes<C, T, G, J + 1, A>(a, i, k, sub, ACx, ACy, ACz, cacc, z);
 }
 
 template <class C, typename T, class A>
@@ -513,10 +519,10 @@ __device__ __forceinline__ void split_ket_hrr(A cacc, A X, int z, T CDx, T CDy, 
   }
 }
 
-template <class C, typename T>
+template <class C, typename T, int G>
 __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a) {
   constexpr int NCD = C::NC * C::ND;
-  constexpr int G = C::G, QPW = kWave / G;
+  constexpr int QPW = kWave / G;
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (G - 1), ql = lane / G;
   const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
@@ -554,9 +560,9 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
     const int k = inrange ? kc + ql : kend - 1;
     const T ACx = T(Ax - a.ket.A[k]), ACy = T(Ay - a.ket.A[nk + k]),
             ACz = T(Az - a.ket.A[2 * nk + k]);
-    split_passes<C, T, 0, LaneArr<T>>(a, i, k, sub, ACx, ACy, ACz, cacc, z);
+    split_passes<C, T, G, 0, LaneArr<T>>(a, i, k, sub, ACx, ACy, ACz, cacc, z);
     const T CDx = T(a.ket.AB[k]), CDy = T(a.ket.AB[nk + k]), CDz = T(a.ket.AB[2 * nk + k]);
-    split_ket_hrr<C, T, LaneArr<T>>(cacc, X, z, CDx, CDy, CDz);
+    if (sub == 0) split_ket_hrr<C, T, LaneArr<T>>(cacc, X, z, CDx, CDy, CDz);
     const int c0 = a.ket.bf[k], d0 = a.ket.bf[nk + k];
     const double fq =
         active ? fbra * a.ket.fpair[k] * ((a.same_bin && k == i) ? 0.5 : 1.0) : 0.0;
@@ -583,7 +589,7 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
       for (int t = 0; t < C::NB * C::ND; ++t) kbd[z + t] = 0.0;
 
 #pragma nounroll
-      for (int cd = 0; cd < NCD; ++cd) {
+      for (int cd = 0; cd < (sub == 0 ? NCD : 0); ++cd) {
         const int c = cd / C::ND, d = cd % C::ND;
         T ev[C::NE];
 #pragma unroll
@@ -658,7 +664,7 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
 template <class C>
 __global__ __launch_bounds__(kBlock) void schwarz_split_kernel(const EriLaunch a, double* Qout) {
   constexpr int NCD = C::NC * C::ND;
-  constexpr int G = C::G, PPW = kWave / G;   // pairs per wave step
+  constexpr int G = C::GMAX, PPW = kWave / G;   // pairs per wave step
   constexpr int NT = C::NACC + C::NE * NCD;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
@@ -672,12 +678,12 @@ __global__ __launch_bounds__(kBlock) void schwarz_split_kernel(const EriLaunch a
   for (int p0 = wave * PPW; p0 < n; p0 += a.nwaves * PPW) {
     const int t0 = p0 + ql;
     const int t = t0 < n ? t0 : n - 1;
-    split_passes<C, double, 0, LaneArr<double>>(a, t, t, sub, 0.0, 0.0, 0.0, cacc, z);
+    split_passes<C, double, G, 0, LaneArr<double>>(a, t, t, sub, 0.0, 0.0, 0.0, cacc, z);
     const double ABx = a.bra.AB[t], ABy = a.bra.AB[n + t], ABz = a.bra.AB[2 * n + t];
-    split_ket_hrr<C, double, LaneArr<double>>(cacc, X, z, ABx, ABy, ABz);
+    if (sub == 0) split_ket_hrr<C, double, LaneArr<double>>(cacc, X, z, ABx, ABy, ABz);
     double mx = 0.0;
 #pragma nounroll
-    for (int cd = 0; cd < NCD; ++cd) {
+    for (int cd = 0; cd < (sub == 0 ? NCD : 0); ++cd) {
       double ev[C::NE];
 #pragma unroll
       for (int e = 0; e < C::NE; ++e) ev[e] = X[z + e * NCD + cd];

@@ -39,49 +39,49 @@ __device__ __forceinline__ void contract_w(const EriLaunch& a, int i, int k, int
   }
 }
 
-template <class C, typename T, int J>
+template <class C, typename T, int GL, int J>
 __device__ __forceinline__ void grad_pass_body(const EriLaunch& a, int i, int k, int sub, T ACx,
                                                T ACy, T ACz, LaneArr<T> G, int z) {
   constexpr int N = C::template Pass<J>::N;
   T acc[N];
 #pragma unroll
   for (int t = 0; t < N; ++t) acc[t] = T(0);
-  contract_w<C::L, T, C::G>(a, i, k, sub, ACx, ACy, ACz,
-                            [&](const T* F, const VrrCoef<T>& c, T wA, T wB, T wC) {
-                              C::template vrr_pass<J, T>(F, c, wA, wB, wC, acc);
-                            });
-  group_sum_all<C::G>(acc);
-  C::template store_pass<J, T, LaneArr<T>>(acc, G, z);
+  contract_w<C::L, T, GL>(a, i, k, sub, ACx, ACy, ACz,
+                          [&](const T* F, const VrrCoef<T>& c, T wA, T wB, T wC) {
+                            C::template vrr_pass<J, T>(F, c, wA, wB, wC, acc);
+                          });
+  group_sum_all<GL>(acc);
+  if (sub == 0) C::template store_pass<J, T, LaneArr<T>>(acc, G, z);
 }
 
 // Classes with many passes call each pass as a separate function, so that the
 // compiler allocates registers pass by pass.
-template <class C, typename T, int J>
+template <class C, typename T, int GL, int J>
 __device__ __attribute__((noinline)) void grad_pass_call(const EriLaunch& a, int i, int k, int sub,
                                                           T ACx, T ACy, T ACz, LaneArr<T> G,
                                                           int z) {
-  grad_pass_body<C, T, J>(a, i, k, sub, ACx, ACy, ACz, G, z);
+  grad_pass_body<C, T, GL, J>(a, i, k, sub, ACx, ACy, ACz, G, z);
 }
 
-template <class C, typename T, int J>
+template <class C, typename T, int GL, int J>
 __device__ __forceinline__ void grad_passes(const EriLaunch& a, int i, int k, int sub, T ACx,
                                             T ACy, T ACz, LaneArr<T> G, int z) {
   if constexpr (C::NPASS > 4)
-    grad_pass_call<C, T, J>(a, i, k, sub, ACx, ACy, ACz, G, z);
+    grad_pass_call<C, T, GL, J>(a, i, k, sub, ACx, ACy, ACz, G, z);
   else
-    grad_pass_body<C, T, J>(a, i, k, sub, ACx, ACy, ACz, G, z);
-  if constexpr (J + 1 < C::NPASS) grad_passes<C, T, J + 1>(a, i, k, sub, ACx, ACy, ACz, G, z);
+    grad_pass_body<C, T, GL, J>(a, i, k, sub, ACx, ACy, ACz, G, z);
+  if constexpr (J + 1 < C::NPASS) grad_passes<C, T, GL, J + 1>(a, i, k, sub, ACx, ACy, ACz, G, z);
 }
 
 constexpr int at_least_1(int v) { return v > 0 ? v : 1; }
 
 // One wavefront per work item; bra pair uniform, one ket pair per lane.
-template <class C, typename T>
+template <class C, typename T, int GL>
 __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
   constexpr int NCD = C::NC * C::ND;
   constexpr int NAB = C::NA * C::NB;
   const EriLaunch& a = g.e;
-  constexpr int GL = C::G, QPW = kWave / GL;
+  constexpr int QPW = kWave / GL;
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (GL - 1), ql = lane / GL;
   const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
@@ -114,12 +114,12 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
     const int k = inrange ? kc + ql : kend - 1;
     const T ACx = T(Ax - a.ket.A[k]), ACy = T(Ay - a.ket.A[nk + k]),
             ACz = T(Az - a.ket.A[2 * nk + k]);
-    grad_passes<C, T, 0>(a, i, k, sub, ACx, ACy, ACz, G, z);
+    grad_passes<C, T, GL, 0>(a, i, k, sub, ACx, ACy, ACz, G, z);
     const T CDx = T(a.ket.AB[k]), CDy = T(a.ket.AB[nk + k]), CDz = T(a.ket.AB[2 * nk + k]);
 
     // ket horizontal recurrences, one bra index e at a time
 #pragma nounroll
-    for (int e = 0; e < C::NE_A; ++e) {
+    for (int e = 0; e < (sub == 0 ? C::NE_A : 0); ++e) {
       T f[C::NF_A], o[NCD];
 #pragma unroll
       for (int t = 0; t < C::NF_A; ++t) f[t] = G[z + C::OFF_A + e * C::NF_A + t];
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
       for (int t = 0; t < NCD; ++t) XA[z + e * NCD + t] = o[t];
     }
 #pragma nounroll
-    for (int e = 0; e < C::NE_B; ++e) {
+    for (int e = 0; e < (sub == 0 ? C::NE_B : 0); ++e) {
       T f[C::NF_B], o[NCD];
 #pragma unroll
       for (int t = 0; t < C::NF_B; ++t) f[t] = G[z + C::OFF_B + e * C::NF_B + t];
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
       for (int t = 0; t < NCD; ++t) XB[z + e * NCD + t] = o[t];
     }
 #pragma nounroll
-    for (int e = 0; e < C::NE_C; ++e) {
+    for (int e = 0; e < (sub == 0 ? C::NE_C : 0); ++e) {
       T f[C::NF_C], o[C::NCP];
 #pragma unroll
       for (int t = 0; t < C::NF_C; ++t) f[t] = G[z + C::OFF_C + e * C::NF_C + t];
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
     }
     if constexpr (C::USE_U) {
 #pragma nounroll
-      for (int e = 0; e < C::NE_U; ++e) {
+      for (int e = 0; e < (sub == 0 ? C::NE_U : 0); ++e) {
         T f[C::NF_U], o[NCD];
 #pragma unroll
         for (int t = 0; t < C::NF_U; ++t) f[t] = G[z + C::OFF_U + e * C::NF_U + t];
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
         for (int y = 0; y < C::NB; ++y) Dab[x * C::NB + y] = Dm[(a0 + x) * n + b0 + y];
       double gA[3] = {0.0, 0.0, 0.0}, gB[3] = {0.0, 0.0, 0.0}, gC[3] = {0.0, 0.0, 0.0};
 #pragma nounroll
-      for (int cd = 0; cd < NCD; ++cd) {
+      for (int cd = 0; cd < (sub == 0 ? NCD : 0); ++cd) {
         const int c = cd / C::ND, d = cd % C::ND;
         const double Dcd = Dm[(c0 + c) * n + d0 + d];
         double Dac[C::NA], Dad[C::NA], Dbc[C::NB], Dbd[C::NB];

@@ -508,6 +508,7 @@ struct Setup {
   std::vector<int> seg;   // [2][nbp+1]
   std::vector<unsigned long long> qstat;
   std::vector<int> chunk; // [2][nbp] kets per work item
+  std::vector<int> lanes; // [2][nbp] lanes per shell quartet
 };
 
 // Steps 1-6.  Returns the sorted pair data, the work items and their segments.
@@ -640,10 +641,19 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
   const unsigned long long* qs = reinterpret_cast<const unsigned long long*>(hp);
   S.qstat.assign(qs, qs + 3 * nbp);
   std::vector<int> chunk(2 * nbp);
+  S.lanes.assign(2 * nbp, 1);
   for (int bp = 0; bp < nbp; ++bp) {
     const int cls = quartet_class(P.bin_cls[P.bp_x[bp]], P.bin_cls[P.bp_y[bp]]);
-    const int qpw = kWave / (grad ? grad_lanes(cls) : class_lanes(cls));  // kets per wave step
+    const int gmax = grad ? grad_lanes(cls) : class_lanes(cls);
     for (int pr = 0; pr < 2; ++pr) {
+      // several lanes per quartet only when the launch would otherwise be
+      // short of wavefronts
+      const unsigned long long q = S.qstat[3 * bp + pr];
+      const int lanes =
+          (grad || (gmax > 1 && q < static_cast<unsigned long long>(kWave) * kTargetWaves / 2))
+              ? gmax : 1;
+      S.lanes[pr * nbp + bp] = lanes;
+      const int qpw = kWave / lanes;  // kets per wave step
       const unsigned long long per =
           S.qstat[3 * bp + pr] / (static_cast<unsigned long long>(qpw) * kTargetWaves);
       const unsigned long long nch =
@@ -720,7 +730,7 @@ EriLaunch launch_args(jk_ctx* c, const Plan& P, const Setup& S, int X, int Y, in
 }
 
 struct LaunchRec {
-  int cls, pr, X, Y, i0, i1;
+  int cls, pr, X, Y, i0, i1, lanes;
   double cost;
 };
 
@@ -745,7 +755,8 @@ void dispatch(jk_ctx* c, const Plan& P, const Setup& S, hipStream_t s, jk_stats&
       if (i1 <= i0) continue;
       const double q = static_cast<double>(S.qstat[3 * bp + pr]);
       const double npp = static_cast<double>(P.bin_npp[X]) * P.bin_npp[Y];
-      recs.push_back({cls, pr, X, Y, i0, i1, q * npp * class_cost(cls, grad ? 1 : 0)});
+      recs.push_back({cls, pr, X, Y, i0, i1, S.lanes[pr * nbp + bp],
+                      q * npp * class_cost(cls, grad ? 1 : 0)});
     }
   }
   std::stable_sort(recs.begin(), recs.end(),
@@ -904,6 +915,7 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
         c, P, S, s, st, false,
         [&](const LaunchRec& r, hipStream_t ls, int k) {
           EriLaunch a = launch_args(c, P, S, r.X, r.Y, r.i0, r.i1, D, J, K, nbf, o);
+          a.lanes = r.lanes;
           a.ws = ws[k];
           a.nwaves = waves_of(r).first;
           launch_eri(r.cls, r.pr, a, ls);
@@ -969,6 +981,7 @@ int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, dou
         [&](const LaunchRec& r, hipStream_t ls, int k) {
           GradLaunch g{};
           g.e = launch_args(c, P, S, r.X, r.Y, r.i0, r.i1, D, nullptr, nullptr, nbf, o);
+          g.e.lanes = r.lanes;
           g.dEdR = dEdR;
           g.n_atoms = basis->n_atoms;
           g.ws = ws[k];
