@@ -218,10 +218,17 @@ class HRR(Code):
 
 
 def lanes_for(L, split):
-    """Lanes that share one shell quartet: light classes 1, mid classes 4, heavy 16."""
+    """Most lanes that share one shell quartet: light classes 1, mid classes 4, heavy 16."""
     if split:
         return 16
     return 1 if L <= 2 else 4
+
+
+def lane_options(L, split):
+    """Lane counts a class is compiled for; the host picks one per launch."""
+    if split:
+        return [4, 16]
+    return [1] if L <= 2 else [1, 4]
 
 
 def gen_class(la, lb, lc, ld):
@@ -316,7 +323,8 @@ def gen_class(la, lb, lc, ld):
     info = dict(name=name, la=la, lb=lb, lc=lc, ld=ld, L=L, nacc=ne * nf,
                 nint=na * nb * nc * nd, vrr_flops=vrr_flops, hrr_flops=hrr_flops,
                 digest_flops=dig_flops, vrr_nodes=vrr.n, hrr_nodes=hrr.n, nf=nf,
-                vrr_flops_alg=vrr_flops, lanes=lanes_for(L, False))
+                vrr_flops_alg=vrr_flops, lanes=lanes_for(L, False),
+                lane_options=lane_options(L, False))
     return "\n".join(s) + "\n", info
 
 
@@ -461,7 +469,8 @@ def gen_split_class(la, lb, lc, ld):
     info = dict(name=name, la=la, lb=lb, lc=lc, ld=ld, L=L, nacc=ne * nf,
                 nint=na * nb * nc * nd, vrr_flops=vrr_flops, hrr_flops=hrr_flops,
                 digest_flops=dig_flops, npass=len(chunks), split=True, nf=nf,
-                vrr_flops_alg=one.flops + ne * nf, lanes=lanes_for(L, True))
+                vrr_flops_alg=one.flops + ne * nf, lanes=lanes_for(L, True),
+                lane_options=lane_options(L, True))
     return "\n".join(s) + "\n", info
 
 
@@ -479,14 +488,12 @@ def wrapper(info):
          f"void launch_eri_{n}(const EriLaunch& a, int fp32, hipStream_t s) {{",
          "  const int waves = " + ("a.nwaves" if info["split"] else "a.nitems") + ";",
          "  const dim3 grid((waves + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);",
-         f"  constexpr int GM = Cls_{n}::GMAX;",
-         f"  if (a.lanes > 1 && GM > 1) {{",
-         f"    if (fp32) hipLaunchKernelGGL(({kern}<Cls_{n}, float, GM>), grid, block, 0, s, a);",
-         f"    else hipLaunchKernelGGL(({kern}<Cls_{n}, double, GM>), grid, block, 0, s, a);",
-         "  } else {",
-         f"    if (fp32) hipLaunchKernelGGL(({kern}<Cls_{n}, float, 1>), grid, block, 0, s, a);",
-         f"    else hipLaunchKernelGGL(({kern}<Cls_{n}, double, 1>), grid, block, 0, s, a);",
-         "  }",
+         *[ln for g_ in info["lane_options"] for ln in (
+             f"  {'if' if g_ == info['lane_options'][0] else 'else if'} (a.lanes == {g_} || "
+             f"{'true' if g_ == info['lane_options'][-1] else 'false'}) {{",
+             f"    if (fp32) hipLaunchKernelGGL(({kern}<Cls_{n}, float, {g_}>), grid, block, 0, s, a);",
+             f"    else hipLaunchKernelGGL(({kern}<Cls_{n}, double, {g_}>), grid, block, 0, s, a);",
+             "  }")],
          "}"]
     if info["bra_class"] == info["ket_class"]:
         w += [f"void launch_schwarz_{n}(const EriLaunch& a, double* Q, hipStream_t s) {{",
@@ -545,6 +552,11 @@ def table(infos):
         str(64 * 8 * (i["nacc"] + (i["nacc"] // i["nf"]) * ((i["lc"] + 1) * (i["lc"] + 2) // 2) * ((i["ld"] + 1) * (i["ld"] + 2) // 2)))
         if i["split"] else "0" for i in infos) + "};")
     t.append("  return (cls >= 0 && cls < 21) ? w[cls] : 0;")
+    t.append("}")
+    t.append("// bit g set: the class has a kernel with g lanes per shell quartet")
+    t.append("int class_lane_mask(int cls) {")
+    t.append("  static const int m[21] = {" + ", ".join(str(sum(1 << g_ for g_ in i["lane_options"])) for i in infos) + "};")
+    t.append("  return (cls >= 0 && cls < 21) ? m[cls] : 2;")
     t.append("}")
     t.append("int class_lanes(int cls) {")
     t.append("  static const int g[21] = {" + ", ".join(str(i["lanes"]) for i in infos) + "};")

@@ -24,20 +24,21 @@ constexpr int kTargetWaves = 8192;   // aim for this many work items per class l
 enum : int { kP = 0, kOo2p = 1, kPAx = 2, kPAy = 3, kPAz = 4, kKt = 5, kTwoA = 6, kTwoB = 7,
              kPrimFields = 8 };
 
-// FP64 Boys table: rows T_i = i * 0.05, i = 0..kBoysRows-1 (T < 64); columns
-// F_m(T_i), m = 0..kBoysM-1, then exp(-T_i).
+// FP64 Boys tables, one per order L = 0..kBoysMaxL: rows T_i = i * 0.05,
+// i = 0..kBoysRows-1 (T < 64), each row one 64-byte line
+// [F_L(T_i), ..., F_{L+6}(T_i), exp(-T_i)].
 constexpr double kBoysStep = 0.05;
 constexpr double kBoysInvStep = 20.0;
 constexpr double kBoysTmax = 64.0;
 constexpr int kBoysRows = 1281;
-constexpr int kBoysM = 17;
-constexpr int kBoysStride = 18;
-// FP32 Boys table: rows T_i = i * 0.05 for T <= 30; columns m = 0..14, exp(-T_i).
+constexpr int kBoysMaxL = 10;
+constexpr int kBoysRow = 8;
+// FP32 Boys tables per order L: rows T_i = i * 0.05 for T <= 30, each row 32
+// bytes [F_L, F_{L+1}, F_{L+2}, F_{L+3}, exp(-T_i), 0, 0, 0].
 constexpr float kBoys32Step = 0.05f;
 constexpr float kBoys32InvStep = 20.0f;
 constexpr int kBoys32Rows = 602;
-constexpr int kBoys32M = 15;
-constexpr int kBoys32Stride = 16;
+constexpr int kBoys32Row = 8;
 
 struct BinView {
   int n, npp;
@@ -68,12 +69,13 @@ struct EriLaunch {
   int lanes;          // lanes sharing one shell quartet in this launch (1 or the class maximum)
 };
 
-// Per-lane array in a launch workspace, lane-interleaved so that a wavefront
-// touching element i reads 64 consecutive values.
-template <typename T>
+// Per-quartet array in a launch workspace.  The QPW quartets of a wavefront
+// are interleaved (stride QPW), so the lanes that carry them touch consecutive
+// addresses for the same element.
+template <typename T, int S>
 struct LaneArr {
   T* p;
-  __device__ __forceinline__ T& operator[](int i) const { return p[static_cast<size_t>(i) * kWave]; }
+  __device__ __forceinline__ T& operator[](int i) const { return p[static_cast<size_t>(i) * S]; }
 };
 
 template <typename T>
@@ -116,18 +118,22 @@ __device__ __forceinline__ float rsqrt_f32(float x) {
 // does not diverge.
 template <int L>
 __device__ __forceinline__ void boys_f64(double T, const double* __restrict__ tab, double* F) {
+  static_assert(L <= kBoysMaxL, "Boys table order");
   const bool near = T < kBoysTmax;
   const double Tt = near ? T : 0.0;
   const int i = static_cast<int>(Tt * kBoysInvStep + 0.5);
   const double x = i * kBoysStep - Tt;
-  const double* r = tab + i * kBoysStride;
-  double s = r[L + 6];
-  s = r[L + 5] + x * s * (1.0 / 6.0);
-  s = r[L + 4] + x * s * (1.0 / 5.0);
-  s = r[L + 3] + x * s * 0.25;
-  s = r[L + 2] + x * s * (1.0 / 3.0);
-  s = r[L + 1] + x * s * 0.5;
-  s = r[L] + x * s;
+  const double2* r2 = reinterpret_cast<const double2*>(
+      tab + (static_cast<size_t>(L) * kBoysRows + i) * kBoysRow);
+  const double2 q0 = r2[0], q1 = r2[1], q2 = r2[2], q3 = r2[3];
+  const double r[8] = {q0.x, q0.y, q1.x, q1.y, q2.x, q2.y, q3.x, q3.y};
+  double s = r[6];
+  s = r[5] + x * s * (1.0 / 6.0);
+  s = r[4] + x * s * (1.0 / 5.0);
+  s = r[3] + x * s * 0.25;
+  s = r[2] + x * s * (1.0 / 3.0);
+  s = r[1] + x * s * 0.5;
+  s = r[0] + x * s;
   double Ft[L + 1];
   Ft[L] = s;
   if constexpr (L > 0) {
@@ -137,7 +143,7 @@ __device__ __forceinline__ void boys_f64(double T, const double* __restrict__ ta
     e = 1.0 + x * (1.0 / 3.0) * e;
     e = 1.0 + x * 0.5 * e;
     e = 1.0 + x * e;
-    e *= r[kBoysStride - 1];
+    e *= r[7];
     const double T2 = 2.0 * Tt;
 #pragma unroll
     for (int m = L - 1; m >= 0; --m) Ft[m] = (T2 * Ft[m + 1] + e) * kInvOdd[m];
@@ -164,18 +170,21 @@ __device__ __forceinline__ void boys_f32(float T, float tcut, const float* __res
   if (T <= tcut) {
     const int i = static_cast<int>(T * kBoys32InvStep + 0.5f);
     const float x = i * kBoys32Step - T;
-    const float* r = tab + i * kBoys32Stride;
-    float s = r[L + 3];
-    s = r[L + 2] + x * s * (1.0f / 3.0f);
-    s = r[L + 1] + x * s * 0.5f;
-    s = r[L] + x * s;
+    const float4* r4 = reinterpret_cast<const float4*>(
+        tab + (static_cast<size_t>(L) * kBoys32Rows + i) * kBoys32Row);
+    const float4 q0 = r4[0];
+    const float r[5] = {q0.x, q0.y, q0.z, q0.w, r4[1].x};
+    float s = r[3];
+    s = r[2] + x * s * (1.0f / 3.0f);
+    s = r[1] + x * s * 0.5f;
+    s = r[0] + x * s;
     F[L] = s;
     if constexpr (L > 0) {
       float e = 1.0f + x * 0.25f;
       e = 1.0f + x * (1.0f / 3.0f) * e;
       e = 1.0f + x * 0.5f * e;
       e = 1.0f + x * e;
-      e *= r[kBoys32Stride - 1];
+      e *= r[4];
       const float T2 = 2.0f * T;
 #pragma unroll
       for (int m = L - 1; m >= 0; --m) F[m] = (T2 * F[m + 1] + e) * static_cast<float>(kInvOdd[m]);
@@ -196,7 +205,7 @@ __device__ __forceinline__ void boys_f32(float T, float tcut, const float* __res
         ex = 1.0 + x * (1.0 / 3.0) * ex;
         ex = 1.0 + x * 0.5 * ex;
         ex = 1.0 + x * ex;
-        e = ex * tab64[i * kBoysStride + kBoysStride - 1];
+        e = ex * tab64[(static_cast<size_t>(L) * kBoysRows + i) * kBoysRow + 7];
       }
       const double h = 0.5 * rs * rs;
 #pragma unroll
@@ -528,18 +537,20 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
   const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (wave >= a.nwaves) return;
   // workspace of this wave: T values (contracted [e0|f0], ket-transformed X),
-  // then FP64 exchange accumulators
+  // then FP64 exchange accumulators; one slot per quartet of the wave step
   constexpr int NT = C::NACC + C::NE * NCD;
   constexpr int NK = C::NA * C::NC + C::NA * C::ND + C::NB * C::NC + C::NB * C::ND;
+  using AT = LaneArr<T, QPW>;
+  using AD = LaneArr<double, QPW>;
   char* wbase = static_cast<char*>(a.ws) +
-                static_cast<size_t>(wave) * kWave * (NT * sizeof(T) + NK * sizeof(double));
-  const LaneArr<T> cacc{reinterpret_cast<T*>(wbase) + lane};
-  const LaneArr<T> X{cacc.p + static_cast<size_t>(C::NACC) * kWave};
-  double* kbase = reinterpret_cast<double*>(wbase + static_cast<size_t>(kWave) * NT * sizeof(T)) + lane;
-  const LaneArr<double> kac{kbase};
-  const LaneArr<double> kad{kac.p + static_cast<size_t>(C::NA * C::NC) * kWave};
-  const LaneArr<double> kbc{kad.p + static_cast<size_t>(C::NA * C::ND) * kWave};
-  const LaneArr<double> kbd{kbc.p + static_cast<size_t>(C::NB * C::NC) * kWave};
+                static_cast<size_t>(wave) * QPW * (NT * sizeof(T) + NK * sizeof(double));
+  const AT cacc{reinterpret_cast<T*>(wbase) + ql};
+  const AT X{cacc.p + static_cast<size_t>(C::NACC) * QPW};
+  double* kbase = reinterpret_cast<double*>(wbase + static_cast<size_t>(QPW) * NT * sizeof(T)) + ql;
+  const AD kac{kbase};
+  const AD kad{kac.p + static_cast<size_t>(C::NA * C::NC) * QPW};
+  const AD kbc{kad.p + static_cast<size_t>(C::NA * C::ND) * QPW};
+  const AD kbd{kbc.p + static_cast<size_t>(C::NB * C::NC) * QPW};
   const int z = 0;
   const int nb = a.bra.n, nk = a.ket.n;
   const size_t n = static_cast<size_t>(a.n);
@@ -560,9 +571,9 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
     const int k = inrange ? kc + ql : kend - 1;
     const T ACx = T(Ax - a.ket.A[k]), ACy = T(Ay - a.ket.A[nk + k]),
             ACz = T(Az - a.ket.A[2 * nk + k]);
-    split_passes<C, T, G, 0, LaneArr<T>>(a, i, k, sub, ACx, ACy, ACz, cacc, z);
+    split_passes<C, T, G, 0, AT>(a, i, k, sub, ACx, ACy, ACz, cacc, z);
     const T CDx = T(a.ket.AB[k]), CDy = T(a.ket.AB[nk + k]), CDz = T(a.ket.AB[2 * nk + k]);
-    if (sub == 0) split_ket_hrr<C, T, LaneArr<T>>(cacc, X, z, CDx, CDy, CDz);
+    if (sub == 0) split_ket_hrr<C, T, AT>(cacc, X, z, CDx, CDy, CDz);
     const int c0 = a.ket.bf[k], d0 = a.ket.bf[nk + k];
     const double fq =
         active ? fbra * a.ket.fpair[k] * ((a.same_bin && k == i) ? 0.5 : 1.0) : 0.0;
@@ -579,14 +590,16 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
           Dab[x * C::NB + y] = Dm[(a0 + x) * n + b0 + y];
           jab[x * C::NB + y] = 0.0;
         }
+      if (sub == 0) {
 #pragma unroll
-      for (int t = 0; t < C::NA * C::NC; ++t) kac[z + t] = 0.0;
+        for (int t = 0; t < C::NA * C::NC; ++t) kac[z + t] = 0.0;
 #pragma unroll
-      for (int t = 0; t < C::NA * C::ND; ++t) kad[z + t] = 0.0;
+        for (int t = 0; t < C::NA * C::ND; ++t) kad[z + t] = 0.0;
 #pragma unroll
-      for (int t = 0; t < C::NB * C::NC; ++t) kbc[z + t] = 0.0;
+        for (int t = 0; t < C::NB * C::NC; ++t) kbc[z + t] = 0.0;
 #pragma unroll
-      for (int t = 0; t < C::NB * C::ND; ++t) kbd[z + t] = 0.0;
+        for (int t = 0; t < C::NB * C::ND; ++t) kbd[z + t] = 0.0;
+      }
 
 #pragma nounroll
       for (int cd = 0; cd < (sub == 0 ? NCD : 0); ++cd) {
@@ -671,16 +684,17 @@ __global__ __launch_bounds__(kBlock) void schwarz_split_kernel(const EriLaunch a
   if (wave >= a.nwaves) return;
   const int sub = lane & (G - 1), ql = lane / G;
   const int n = a.bra.n;
-  double* wl = static_cast<double*>(a.ws) + static_cast<size_t>(wave) * kWave * NT + lane;
-  const LaneArr<double> cacc{wl};
-  const LaneArr<double> X{wl + static_cast<size_t>(C::NACC) * kWave};
+  using AD = LaneArr<double, PPW>;
+  double* wl = static_cast<double*>(a.ws) + static_cast<size_t>(wave) * PPW * NT + ql;
+  const AD cacc{wl};
+  const AD X{wl + static_cast<size_t>(C::NACC) * PPW};
   const int z = 0;
   for (int p0 = wave * PPW; p0 < n; p0 += a.nwaves * PPW) {
     const int t0 = p0 + ql;
     const int t = t0 < n ? t0 : n - 1;
-    split_passes<C, double, G, 0, LaneArr<double>>(a, t, t, sub, 0.0, 0.0, 0.0, cacc, z);
+    split_passes<C, double, G, 0, AD>(a, t, t, sub, 0.0, 0.0, 0.0, cacc, z);
     const double ABx = a.bra.AB[t], ABy = a.bra.AB[n + t], ABz = a.bra.AB[2 * n + t];
-    if (sub == 0) split_ket_hrr<C, double, LaneArr<double>>(cacc, X, z, ABx, ABy, ABz);
+    if (sub == 0) split_ket_hrr<C, double, AD>(cacc, X, z, ABx, ABy, ABz);
     double mx = 0.0;
 #pragma nounroll
     for (int cd = 0; cd < (sub == 0 ? NCD : 0); ++cd) {

@@ -41,7 +41,7 @@ __device__ __forceinline__ void contract_w(const EriLaunch& a, int i, int k, int
 
 template <class C, typename T, int GL, int J>
 __device__ __forceinline__ void grad_pass_body(const EriLaunch& a, int i, int k, int sub, T ACx,
-                                               T ACy, T ACz, LaneArr<T> G, int z) {
+                                               T ACy, T ACz, LaneArr<T, kWave / GL> G, int z) {
   constexpr int N = C::template Pass<J>::N;
   T acc[N];
 #pragma unroll
@@ -51,21 +51,21 @@ __device__ __forceinline__ void grad_pass_body(const EriLaunch& a, int i, int k,
                             C::template vrr_pass<J, T>(F, c, wA, wB, wC, acc);
                           });
   group_sum_all<GL>(acc);
-  if (sub == 0) C::template store_pass<J, T, LaneArr<T>>(acc, G, z);
+  if (sub == 0) C::template store_pass<J, T, LaneArr<T, kWave / GL>>(acc, G, z);
 }
 
 // Classes with many passes call each pass as a separate function, so that the
 // compiler allocates registers pass by pass.
 template <class C, typename T, int GL, int J>
 __device__ __attribute__((noinline)) void grad_pass_call(const EriLaunch& a, int i, int k, int sub,
-                                                          T ACx, T ACy, T ACz, LaneArr<T> G,
-                                                          int z) {
+                                                          T ACx, T ACy, T ACz,
+                                                          LaneArr<T, kWave / GL> G, int z) {
   grad_pass_body<C, T, GL, J>(a, i, k, sub, ACx, ACy, ACz, G, z);
 }
 
 template <class C, typename T, int GL, int J>
 __device__ __forceinline__ void grad_passes(const EriLaunch& a, int i, int k, int sub, T ACx,
-                                            T ACy, T ACz, LaneArr<T> G, int z) {
+                                            T ACy, T ACz, LaneArr<T, kWave / GL> G, int z) {
   if constexpr (C::NPASS > 4)
     grad_pass_call<C, T, GL, J>(a, i, k, sub, ACx, ACy, ACz, G, z);
   else
@@ -86,13 +86,14 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
   const int sub = lane & (GL - 1), ql = lane / GL;
   const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (wave >= g.nwaves) return;
-  T* wsl = static_cast<T*>(g.ws) + static_cast<size_t>(wave) * C::WS * kWave + lane;
-  const LaneArr<T> G{wsl};
-  const LaneArr<T> XA{wsl + static_cast<size_t>(C::NG) * kWave};
-  const LaneArr<T> XB{XA.p + static_cast<size_t>(C::NE_A) * NCD * kWave};
-  const LaneArr<T> XC{XB.p + static_cast<size_t>(C::NE_B) * NCD * kWave};
-  const LaneArr<T> XU{XC.p + static_cast<size_t>(C::NE_C) * C::NCP * kWave};
-  const LaneArr<T> XV{XU.p + static_cast<size_t>(C::NE_U) * NCD * kWave};
+  using AT = LaneArr<T, QPW>;
+  T* wsl = static_cast<T*>(g.ws) + static_cast<size_t>(wave) * C::WS * QPW + ql;
+  const AT G{wsl};
+  const AT XA{wsl + static_cast<size_t>(C::NG) * QPW};
+  const AT XB{XA.p + static_cast<size_t>(C::NE_A) * NCD * QPW};
+  const AT XC{XB.p + static_cast<size_t>(C::NE_B) * NCD * QPW};
+  const AT XU{XC.p + static_cast<size_t>(C::NE_C) * C::NCP * QPW};
+  const AT XV{XU.p + static_cast<size_t>(C::NE_U) * NCD * QPW};
   const int z = 0;
   for (int item = wave; item < a.nitems; item += g.nwaves) {
   const int4 w = a.items[item];

@@ -77,17 +77,24 @@ long double boys_series(int m, long double T) {
 }
 
 void make_boys_tables(std::vector<double>& t64, std::vector<float>& t32) {
-  t64.assign(static_cast<size_t>(kBoysRows) * kBoysStride, 0.0);
+  const int nL = kBoysMaxL + 1;
+  t64.assign(static_cast<size_t>(nL) * kBoysRows * kBoysRow, 0.0);
+  t32.assign(static_cast<size_t>(nL) * kBoys32Rows * kBoys32Row, 0.0f);
+  std::vector<long double> F(kBoysMaxL + 7);
   for (int i = 0; i < kBoysRows; ++i) {
     const long double T = static_cast<long double>(i) * 0.05L;
-    for (int m = 0; m < kBoysM; ++m) t64[i * kBoysStride + m] = static_cast<double>(boys_series(m, T));
-    t64[i * kBoysStride + kBoysStride - 1] = static_cast<double>(std::exp(-T));
-  }
-  t32.assign(static_cast<size_t>(kBoys32Rows) * kBoys32Stride, 0.0f);
-  for (int i = 0; i < kBoys32Rows; ++i) {
-    const long double T = static_cast<long double>(i) * 0.05L;
-    for (int m = 0; m < kBoys32M; ++m) t32[i * kBoys32Stride + m] = static_cast<float>(boys_series(m, T));
-    t32[i * kBoys32Stride + kBoys32Stride - 1] = static_cast<float>(std::exp(-T));
+    for (int m = 0; m < kBoysMaxL + 7; ++m) F[m] = boys_series(m, T);
+    const long double eT = std::exp(-T);
+    for (int L = 0; L < nL; ++L) {
+      double* row = &t64[(static_cast<size_t>(L) * kBoysRows + i) * kBoysRow];
+      for (int k = 0; k < 7; ++k) row[k] = static_cast<double>(F[L + k]);
+      row[7] = static_cast<double>(eT);
+      if (i < kBoys32Rows) {
+        float* r32 = &t32[(static_cast<size_t>(L) * kBoys32Rows + i) * kBoys32Row];
+        for (int k = 0; k < 4; ++k) r32[k] = static_cast<float>(F[L + k]);
+        r32[4] = static_cast<float>(eT);
+      }
+    }
   }
 }
 
@@ -586,7 +593,7 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
     a.boys64 = c->boys64;
     a.boys32 = c->boys32;
     const int dcls = quartet_class(P.bin_cls[bb], P.bin_cls[bb]);
-    const size_t per_wave = split_schwarz_ws_bytes(dcls);
+    const size_t per_wave = split_schwarz_ws_bytes(dcls) / class_lanes(dcls);
     if (per_wave) {  // multi-pass diagonal class: workspace, waves loop over the pairs
       const int pairs_per_wave = kWave / class_lanes(dcls);
       const size_t want = (static_cast<size_t>(a.bra.n) + pairs_per_wave - 1) / pairs_per_wave;
@@ -648,10 +655,17 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
     for (int pr = 0; pr < 2; ++pr) {
       // several lanes per quartet only when the launch would otherwise be
       // short of wavefronts
+      // the fewest lanes per quartet that still give kTargetWaves/2 wavefronts
       const unsigned long long q = S.qstat[3 * bp + pr];
-      const int lanes =
-          (grad || (gmax > 1 && q < static_cast<unsigned long long>(kWave) * kTargetWaves / 2))
-              ? gmax : 1;
+      int lanes = gmax;
+      if (!grad) {
+        const int mask = class_lane_mask(cls);
+        for (int g = 1; g <= gmax; g *= 2) {
+          if (!(mask & (1 << g))) continue;
+          lanes = g;
+          if (q * g >= static_cast<unsigned long long>(kWave) * (kTargetWaves / 2)) break;
+        }
+      }
       S.lanes[pr * nbp + bp] = lanes;
       const int qpw = kWave / lanes;  // kets per wave step
       const unsigned long long per =
@@ -905,7 +919,7 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
 
     jk_stats st = base_stats(P, S);
     auto waves_of = [&](const LaunchRec& r) {
-      const size_t per_wave = split_ws_bytes(r.cls, r.pr);
+      const size_t per_wave = split_ws_bytes(r.cls, r.pr) / r.lanes;  // one slot per quartet
       if (!per_wave) return std::pair<int, size_t>(0, 0);
       const size_t cap = std::max<size_t>(64, kWsBudget / per_wave);
       return std::pair<int, size_t>(static_cast<int>(std::min<size_t>(r.i1 - r.i0, cap)), per_wave);
@@ -971,7 +985,7 @@ int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, dou
     // gradient work arrays live in a per-stream workspace; a launch uses at most
     // kWsBudget bytes and loops over its items with a fixed number of waves
     auto waves_of = [&](const LaunchRec& r) {
-      const size_t per_wave = size_t(kWave) * grad_ws_elems(r.cls) * (r.pr ? 4 : 8);
+      const size_t per_wave = size_t(kWave / r.lanes) * grad_ws_elems(r.cls) * (r.pr ? 4 : 8);
       const size_t cap = std::max<size_t>(64, kWsBudget / per_wave);
       return std::pair<int, size_t>(static_cast<int>(std::min<size_t>(r.i1 - r.i0, cap)), per_wave);
     };
