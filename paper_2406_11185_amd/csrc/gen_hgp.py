@@ -117,6 +117,40 @@ class VRR(Code):
         self.memo[key] = name
         return name
 
+    def _missing(self, key, seen):
+        """Nodes that computing `key` would add (upper bound, no emission)."""
+        if key in self.memo or key in seen:
+            return 0
+        e, f, m = key
+        if any(x < 0 for x in e) or any(x < 0 for x in f) or (sum(e) == 0 and sum(f) == 0):
+            return 0
+        seen.add(key)
+        if sum(f) == 0:
+            i = next(k for k in range(3) if e[k] > 0)
+            e1 = sub(e, i)
+            ks = [(e1, f, m), (e1, f, m + 1), (sub(e1, i), f, m), (sub(e1, i), f, m + 1)]
+        else:
+            i = next(k for k in range(3) if f[k] > 0)
+            f1 = sub(f, i)
+            ks = [(e, f1, m), (e, f1, m + 1), (e, sub(f1, i), m), (e, sub(f1, i), m + 1),
+                  (sub(e, i), f1, m + 1)]
+        return 1 + sum(self._missing(k, seen) for k in ks)
+
+    def accumulate(self, outputs, greedy=False):
+        """Emit acc[t] += [e0|f0]^(0) for outputs [(t, e, f)], each add right after
+        its value is available; with `greedy` the next output is the one that
+        needs the fewest new nodes."""
+        todo = list(outputs)
+        while todo:
+            j = 0
+            if greedy:
+                j = min(range(len(todo)),
+                        key=lambda u: (self._missing((todo[u][1], todo[u][2], 0), set()), u))
+            t, e, f = todo.pop(j)
+            v = self.node(e, f, 0)
+            self.lines.append(f"acc[{t}] += {v};")
+        return len(outputs)
+
     def _pick(self, cands, children):
         best, best_cost = None, None
         for i in cands:
@@ -184,6 +218,44 @@ class VRR(Code):
         return self.emit(" + ".join(terms), fl)
 
 
+def max_live(lines):
+    """Largest number of recurrence temporaries alive at once in emitted order."""
+    import re
+    defs, last = {}, {}
+    for n, ln in enumerate(lines):
+        m = re.match(r"const T (\w+) = (.*);", ln)
+        rhs = m.group(2) if m else ln
+        for u in re.findall(r"\bv\d+\b", rhs):
+            last[u] = n
+        if m:
+            defs[m.group(1)] = n
+    ev = [0] * (len(lines) + 2)
+    for v, d in defs.items():
+        ev[d] += 1
+        ev[last.get(v, d) + 1] -= 1
+    cur = best = 0
+    for x in ev:
+        cur += x
+        best = max(best, cur)
+    return best
+
+
+def build_vrr(L, outputs):
+    """Straight-line recurrence code for the accumulator outputs [(t, e, f)]:
+    of a few output orders, the one with the fewest live temporaries (register
+    pressure of FP64 values on a 512-register file decides occupancy)."""
+    orders = [list(outputs), sorted(outputs, key=lambda o: (o[2], o[1]))]
+    best = None
+    for greedy in (False, True):
+        for order in orders:
+            v = VRR(L)
+            v.accumulate(order, greedy)
+            score = (max_live(v.lines), v.flops)
+            if best is None or score < best[0]:
+                best = (score, v)
+    return best[1]
+
+
 def e_set(la, lb):
     return [c for l in range(la, la + lb + 1) for c in cart(l)]
 
@@ -227,7 +299,7 @@ def lanes_for(L, split):
 def lane_options(L, split):
     """Lane counts a class is compiled for; the host picks one per launch."""
     if split:
-        return [4, 16]
+        return [1, 4, 16] if L <= 6 else [4, 16]
     return [1] if L <= 2 else [1, 4]
 
 
@@ -239,23 +311,21 @@ def gen_class(la, lb, lc, ld):
     ne, nf = len(E), len(Fs)
     na, nb, nc, nd = ncart(la), ncart(lb), ncart(lc), ncart(ld)
 
-    vrr = VRR(L)
-    acc_lines = []
-    for ie, e in enumerate(E):
-        for jf, f in enumerate(Fs):
-            v = vrr.node(e, f, 0)
-            acc_lines.append(f"acc[{ie * nf + jf}] += {v};")
-    vrr_flops = vrr.flops + len(acc_lines)
+    outs = [(ie * nf + jf, e, f) for ie, e in enumerate(E) for jf, f in enumerate(Fs)]
+    vrr = build_vrr(L, outs)
+    vrr_flops = vrr.flops + len(outs)
 
     hrr = HRR(la, lb, lc, ld)
-    dig = []
+    n_int = 0
     A, B, C, D = cart(la), cart(lb), cart(lc), cart(ld)
     for ia, a in enumerate(A):
         for ib, b in enumerate(B):
             for ic, c in enumerate(C):
                 for id_, d in enumerate(D):
                     h = hrr.node(a, b, c, d)
-                    dig.append(
+                    n_int += 1
+                    # digest each integral right after it is formed: few live values
+                    hrr.lines.append(
                         f"{{ const double v = double({h}) * fq;"
                         f" jab[{ia * nb + ib}] += Dcd[{ic * nd + id_}] * v;"
                         f" jcd[{ic * nd + id_}] += Dab[{ia * nb + ib}] * v;"
@@ -264,7 +334,7 @@ def gen_class(la, lb, lc, ld):
                         f" kbc[{ib * nc + ic}] += Dad[{ia * nd + id_}] * v;"
                         f" kbd[{ib * nd + id_}] += Dac[{ia * nc + ic}] * v; }}")
     hrr_flops = hrr.flops
-    dig_flops = 13 * len(dig)
+    dig_flops = 13 * n_int
 
     diag_code = None
     if (la, lb) == (lc, ld):
@@ -297,7 +367,6 @@ def gen_class(la, lb, lc, ld):
              " (void)QCz; (void)WQx; (void)WQy; (void)WQz; (void)oo2p; (void)oo2p_rp; (void)oo2q;"
              " (void)oo2q_rq; (void)oo2pq;")
     s += ["    " + x for x in vrr.lines]
-    s += ["    " + x for x in acc_lines]
     s.append("  }")
     s.append("  template <typename T>")
     s.append("  __device__ __forceinline__ static void hrr_digest(const T* __restrict__ acc, T ABx, T ABy, T ABz,"
@@ -306,7 +375,6 @@ def gen_class(la, lb, lc, ld):
              " double* jab, double* jcd, double* kac, double* kad, double* kbc, double* kbd) {")
     s.append("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz;")
     s += ["    " + x for x in hrr.lines]
-    s += ["    " + x for x in dig]
     s.append("  }")
     if diag_code is not None:
         s.append("  template <typename T>")
@@ -328,8 +396,20 @@ def gen_class(la, lb, lc, ld):
     return "\n".join(s) + "\n", info
 
 
-SPLIT_NACC = 160   # classes with more contracted accumulators use the multi-pass form
-PASS_ACC = 96      # accumulators per pass in the multi-pass form
+# Classes with more contracted accumulators than SPLIT_NACC use the multi-pass
+# form; a pass holds at most PASS_ACC accumulators, and the f components are
+# spread evenly over the fewest passes that respect that bound.  (Measured on
+# gfx950: single-pass classes up to about 100 FP64 accumulators beat their
+# multi-pass form; above, passes of <= 64 beat both fewer, larger passes, which
+# spill, and more, smaller ones, which repeat more of the recurrence.)
+SPLIT_NACC = 100
+PASS_ACC = 64
+
+
+def pass_chunks(ne, nf):
+    npass = -(-ne * nf // PASS_ACC)
+    chunk = max(1, min(nf, -(-nf // npass), PASS_ACC // ne))
+    return [list(range(i, min(i + chunk, nf))) for i in range(0, nf, chunk)]
 
 
 class KetHRR(Code):
@@ -394,8 +474,8 @@ def gen_split_class(la, lb, lc, ld):
     Fs = e_set(lc, ld)
     ne, nf = len(E), len(Fs)
     na, nb, nc, nd = ncart(la), ncart(lb), ncart(lc), ncart(ld)
-    chunk = max(1, PASS_ACC // ne)
-    chunks = [list(range(i, min(i + chunk, nf))) for i in range(0, nf, chunk)]
+    chunks = pass_chunks(ne, nf)
+    chunk = len(chunks[0])
     s = []
     s.append(f"// class ({LNAME[la]}{LNAME[lb]}|{LNAME[lc]}{LNAME[ld]}): L = {L}, "
              f"{ne}x{nf} contracted [e0|f0] built in {len(chunks)} passes, "
@@ -408,12 +488,10 @@ def gen_split_class(la, lb, lc, ld):
     s.append(f"  static constexpr int GMAX = {lanes_for(L, True)};  // most lanes per shell quartet")
     vrr_flops = 0
     for j, ch in enumerate(chunks):
-        v = VRR(L)
+        outs = [(ie * len(ch) + jj, e, Fs[jf]) for ie, e in enumerate(E) for jj, jf in enumerate(ch)]
+        v = build_vrr(L, outs)
         lines = []
-        for ie, e in enumerate(E):
-            for jj, jf in enumerate(ch):
-                lines.append(f"acc[{ie * len(ch) + jj}] += {v.node(e, Fs[jf], 0)};")
-        vrr_flops += v.flops + len(lines)
+        vrr_flops += v.flops + len(outs)
         s.append(f"  static constexpr int PASS{j}_F0 = {ch[0]}, PASS{j}_NF = {len(ch)};")
         s.append("  template <typename T>")
         s.append(f"  __device__ __forceinline__ static void vrr_p{j}(const T* __restrict__ F, "

@@ -4,6 +4,8 @@
 // one primitive-pair count, sorted by Schwarz bound Q, descending):
 //   prim  [npp][kPrimFields][n]  per primitive pair (SoA over pairs, so lanes
 //                                that hold consecutive ket pairs load coalesced)
+//   primT [n][npp][kPrimFields]  the same, pair-major (one bra pair's primitive
+//                                pairs are contiguous: scalar loads)
 //   A     [3][n]   centre of the first shell        AB [3][n]  A - B
 //   bf    [2][n]   first basis function of each shell
 //   atoms [2][n]   atom of each shell               fpair [n]  1/2 if both shells coincide
@@ -18,7 +20,10 @@ constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kMaxItemChunks = 16;   // a work item covers 1..16 wave-wide ket chunks
-constexpr int kTargetWaves = 8192;   // aim for this many work items per class launch
+#ifndef JK_TARGET_WAVES
+#define JK_TARGET_WAVES 8192
+#endif
+constexpr int kTargetWaves = JK_TARGET_WAVES;   // aim for this many work items per class launch
 
 // primitive-pair fields
 enum : int { kP = 0, kOo2p = 1, kPAx = 2, kPAy = 3, kPAz = 4, kKt = 5, kTwoA = 6, kTwoB = 7,
@@ -43,6 +48,7 @@ constexpr int kBoys32Row = 8;
 struct BinView {
   int n, npp;
   const double* prim;
+  const double* primT;   // the same primitive-pair fields pair-major: [n][npp][kPrimFields]
   const double* A;
   const double* AB;
   const int* bf;
@@ -115,18 +121,30 @@ __device__ __forceinline__ float rsqrt_f32(float x) {
 // asymptotic F_0 = sqrt(pi/(4T)) and upward recursion F_{m+1} = (2m+1)/(2T) F_m
 // (the dropped e^{-T} terms are below 1e-15 relative there for m <= 10).
 // Both forms are evaluated and selected per lane, so a wavefront with mixed T
-// does not diverge.
+// does not diverge.  The table row is fetched by a separate call so that the
+// load can be issued one primitive quartet ahead of its use.
+struct BoysRow64 {
+  double2 q0, q1, q2, q3;   // F_L(T_i) ... F_{L+6}(T_i), exp(-T_i)
+  double x;                 // T_i - T
+};
+
 template <int L>
-__device__ __forceinline__ void boys_f64(double T, const double* __restrict__ tab, double* F) {
+__device__ __forceinline__ BoysRow64 boys64_fetch(double T, const double* __restrict__ tab) {
   static_assert(L <= kBoysMaxL, "Boys table order");
-  const bool near = T < kBoysTmax;
-  const double Tt = near ? T : 0.0;
+  const double Tt = T < kBoysTmax ? T : 0.0;
   const int i = static_cast<int>(Tt * kBoysInvStep + 0.5);
-  const double x = i * kBoysStep - Tt;
   const double2* r2 = reinterpret_cast<const double2*>(
       tab + (static_cast<size_t>(L) * kBoysRows + i) * kBoysRow);
-  const double2 q0 = r2[0], q1 = r2[1], q2 = r2[2], q3 = r2[3];
-  const double r[8] = {q0.x, q0.y, q1.x, q1.y, q2.x, q2.y, q3.x, q3.y};
+  return BoysRow64{r2[0], r2[1], r2[2], r2[3], i * kBoysStep - Tt};
+}
+
+template <int L>
+__device__ __forceinline__ void boys64_eval(double T, const BoysRow64& row, double* F) {
+  const bool near = T < kBoysTmax;
+  const double Tt = near ? T : 0.0;
+  const double x = row.x;
+  const double r[8] = {row.q0.x, row.q0.y, row.q1.x, row.q1.y,
+                       row.q2.x, row.q2.y, row.q3.x, row.q3.y};
   double s = r[6];
   s = r[5] + x * s * (1.0 / 6.0);
   s = r[4] + x * s * (1.0 / 5.0);
@@ -164,27 +182,54 @@ __device__ __forceinline__ void boys_f64(double T, const double* __restrict__ ta
 // Taylor expansion in FP32 from the FP32 table and downward recursion in FP32.
 // Larger T: evaluated in FP64 (asymptotic F_0, upward recursion with the
 // e^{-T} term taken from the FP64 table) and rounded to FP32.
+struct BoysRow32 {
+  float4 q0;    // F_L(T_i) ... F_{L+3}(T_i)
+  float e;      // exp(-T_i)
+  float x;      // T_i - T
+  double e64;   // FP64 branch: exp(-T_j) of the FP64 table (0 beyond it)
+  double x64;   // FP64 branch: T_j - T
+};
+
 template <int L>
-__device__ __forceinline__ void boys_f32(float T, float tcut, const float* __restrict__ tab,
-                                         const double* __restrict__ tab64, float* F) {
+__device__ __forceinline__ BoysRow32 boys32_fetch(float T, float tcut, const float* __restrict__ tab,
+                                                  const double* __restrict__ tab64) {
+  BoysRow32 r;
+  const bool lo = T <= tcut;
+  const float Tl = lo ? T : 0.0f;
+  const int i = static_cast<int>(Tl * kBoys32InvStep + 0.5f);
+  const float4* r4 = reinterpret_cast<const float4*>(
+      tab + (static_cast<size_t>(L) * kBoys32Rows + i) * kBoys32Row);
+  r.q0 = r4[0];
+  r.e = r4[1].x;
+  r.x = i * kBoys32Step - Tl;
+  r.e64 = 0.0;
+  r.x64 = 0.0;
+  if constexpr (L > 0) {
+    const double Td = static_cast<double>(T);
+    if (!lo && Td < kBoysTmax) {
+      const int j = static_cast<int>(Td * kBoysInvStep + 0.5);
+      r.x64 = j * kBoysStep - Td;
+      r.e64 = tab64[(static_cast<size_t>(L) * kBoysRows + j) * kBoysRow + 7];
+    }
+  }
+  return r;
+}
+
+template <int L>
+__device__ __forceinline__ void boys32_eval(float T, float tcut, const BoysRow32& row, float* F) {
   if (T <= tcut) {
-    const int i = static_cast<int>(T * kBoys32InvStep + 0.5f);
-    const float x = i * kBoys32Step - T;
-    const float4* r4 = reinterpret_cast<const float4*>(
-        tab + (static_cast<size_t>(L) * kBoys32Rows + i) * kBoys32Row);
-    const float4 q0 = r4[0];
-    const float r[5] = {q0.x, q0.y, q0.z, q0.w, r4[1].x};
-    float s = r[3];
-    s = r[2] + x * s * (1.0f / 3.0f);
-    s = r[1] + x * s * 0.5f;
-    s = r[0] + x * s;
+    const float x = row.x;
+    float s = row.q0.w;
+    s = row.q0.z + x * s * (1.0f / 3.0f);
+    s = row.q0.y + x * s * 0.5f;
+    s = row.q0.x + x * s;
     F[L] = s;
     if constexpr (L > 0) {
       float e = 1.0f + x * 0.25f;
       e = 1.0f + x * (1.0f / 3.0f) * e;
       e = 1.0f + x * 0.5f * e;
       e = 1.0f + x * e;
-      e *= r[4];
+      e *= row.e;
       const float T2 = 2.0f * T;
 #pragma unroll
       for (int m = L - 1; m >= 0; --m) F[m] = (T2 * F[m + 1] + e) * static_cast<float>(kInvOdd[m]);
@@ -195,18 +240,15 @@ __device__ __forceinline__ void boys_f32(float T, float tcut, const float* __res
     double f = 0.88622692545275801364908374167057 * rs;
     F[0] = static_cast<float>(f);
     if constexpr (L > 0) {
-      double e = 0.0;  // e^{-T}: table row times e^{x}, zero beyond the table
-      if (Td < kBoysTmax) {
-        const int i = static_cast<int>(Td * kBoysInvStep + 0.5);
-        const double x = i * kBoysStep - Td;
-        double ex = 1.0 + x * (1.0 / 6.0);
-        ex = 1.0 + x * 0.2 * ex;
-        ex = 1.0 + x * 0.25 * ex;
-        ex = 1.0 + x * (1.0 / 3.0) * ex;
-        ex = 1.0 + x * 0.5 * ex;
-        ex = 1.0 + x * ex;
-        e = ex * tab64[(static_cast<size_t>(L) * kBoysRows + i) * kBoysRow + 7];
-      }
+      // e^{-T}: table value times e^{x}, zero beyond the table
+      const double x = row.x64;
+      double ex = 1.0 + x * (1.0 / 6.0);
+      ex = 1.0 + x * 0.2 * ex;
+      ex = 1.0 + x * 0.25 * ex;
+      ex = 1.0 + x * (1.0 / 3.0) * ex;
+      ex = 1.0 + x * 0.5 * ex;
+      ex = 1.0 + x * ex;
+      const double e = ex * row.e64;
       const double h = 0.5 * rs * rs;
 #pragma unroll
       for (int m = 0; m < L; ++m) {
@@ -221,108 +263,257 @@ template <int L, typename T>
 struct Boys;
 template <int L>
 struct Boys<L, double> {
-  __device__ __forceinline__ static void eval(double T, const EriLaunch& a, double* F) {
-    boys_f64<L>(T, a.boys64, F);
+  using Row = BoysRow64;
+  __device__ __forceinline__ static Row fetch(double T, const EriLaunch& a) {
+    return boys64_fetch<L>(T, a.boys64);
+  }
+  __device__ __forceinline__ static void eval(double T, const Row& r, const EriLaunch& a, double* F) {
+    (void)a;
+    boys64_eval<L>(T, r, F);
   }
 };
 template <int L>
 struct Boys<L, float> {
-  __device__ __forceinline__ static void eval(float T, const EriLaunch& a, float* F) {
-    boys_f32<L>(T, a.boys_fp64_T, a.boys32, a.boys64, F);
+  using Row = BoysRow32;
+  __device__ __forceinline__ static Row fetch(float T, const EriLaunch& a) {
+    return boys32_fetch<L>(T, a.boys_fp64_T, a.boys32, a.boys64);
+  }
+  __device__ __forceinline__ static void eval(float T, const Row& r, const EriLaunch& a, float* F) {
+    boys32_eval<L>(T, a.boys_fp64_T, r, F);
   }
 };
 
-// One primitive quartet: Boys values scaled by the prefactor and the
-// recurrence coefficients.
-//   P - Q = (P - A) - (Q - C) + (A - C)   (keeps FP32 differences small)
-//   W - P = -q/(p+q) (P - Q),  W - Q = p/(p+q) (P - Q),  rho = pq/(p+q)
-//   prefactor = 2 pi^{5/2} K_AB K_CD / (p q sqrt(p+q)) = Kt_AB Kt_CD / sqrt(p+q)
 template <typename T>
 __device__ __forceinline__ T rsqrt_t(T x) {
   if constexpr (sizeof(T) == 8) return rsqrt_f64(x);
   else return rsqrt_f32(x);
 }
 
+// One primitive quartet in two steps.  prim_geo: Gaussian-product geometry,
+// the Boys argument and the fetch of its table row; prim_finish: Boys values
+// scaled by the prefactor and the recurrence coefficients.
+//   P - Q = (P - A) - (Q - C) + (A - C)   (keeps FP32 differences small)
+//   W - P = -q/(p+q) (P - Q),  W - Q = p/(p+q) (P - Q),  rho = pq/(p+q)
+//   prefactor = 2 pi^{5/2} K_AB K_CD / (p q sqrt(p+q)) = Kt_AB Kt_CD / sqrt(p+q)
 template <int L, typename T>
-__device__ __forceinline__ void prim_setup(T p, T oo2p, T PAx, T PAy, T PAz, T Kab, T q, T oo2q,
-                                           T QCx, T QCy, T QCz, T Kcd, T ACx, T ACy, T ACz,
-                                           const EriLaunch& a, T* F, VrrCoef<T>& c) {
-  const T srpq = rsqrt_t<T>(p + q);   // 1/sqrt(p+q)
-  const T rpq = srpq * srpq;
+struct PrimGeo {
+  T srpq, PQx, PQy, PQz, Tb;
+  typename Boys<L, T>::Row row;
+};
+
+template <int L, typename T>
+__device__ __forceinline__ void prim_geo(T p, T PAx, T PAy, T PAz, T q, T QCx, T QCy, T QCz,
+                                         T ACx, T ACy, T ACz, const EriLaunch& a,
+                                         PrimGeo<L, T>& g) {
+  g.srpq = rsqrt_t<T>(p + q);   // 1/sqrt(p+q)
+  const T rpq = g.srpq * g.srpq;
+  g.PQx = PAx - QCx + ACx;
+  g.PQy = PAy - QCy + ACy;
+  g.PQz = PAz - QCz + ACz;
+  g.Tb = p * (q * rpq) * (g.PQx * g.PQx + g.PQy * g.PQy + g.PQz * g.PQz);
+  g.row = Boys<L, T>::fetch(g.Tb, a);
+}
+
+template <int L, typename T>
+__device__ __forceinline__ void prim_finish(const PrimGeo<L, T>& g, T p, T oo2p, T PAx, T PAy,
+                                            T PAz, T Kab, T q, T oo2q, T QCx, T QCy, T QCz,
+                                            T Kcd, const EriLaunch& a, T* F, VrrCoef<T>& c) {
+  const T rpq = g.srpq * g.srpq;
   const T qr = q * rpq, pr = p * rpq;
-  const T PQx = PAx - QCx + ACx, PQy = PAy - QCy + ACy, PQz = PAz - QCz + ACz;
-  const T Tb = p * qr * (PQx * PQx + PQy * PQy + PQz * PQz);
-  Boys<L, T>::eval(Tb, a, F);
-  const T pref = Kab * Kcd * srpq;
+  Boys<L, T>::eval(g.Tb, g.row, a, F);
+  const T pref = Kab * Kcd * g.srpq;
 #pragma unroll
   for (int m = 0; m <= L; ++m) F[m] *= pref;
   c.PAx = PAx; c.PAy = PAy; c.PAz = PAz;
   c.QCx = QCx; c.QCy = QCy; c.QCz = QCz;
-  c.WPx = -qr * PQx; c.WPy = -qr * PQy; c.WPz = -qr * PQz;
-  c.WQx = pr * PQx; c.WQy = pr * PQy; c.WQz = pr * PQz;
+  c.WPx = -qr * g.PQx; c.WPy = -qr * g.PQy; c.WPz = -qr * g.PQz;
+  c.WQx = pr * g.PQx; c.WQy = pr * g.PQy; c.WQz = pr * g.PQz;
   c.oo2p = oo2p; c.oo2p_rp = oo2p * qr;
   c.oo2q = oo2q; c.oo2q_rq = oo2q * pr;
   c.oo2pq = T(0.5) * rpq;
 }
 
-// Contraction loop of one shell quartet: bra pair i, ket pair k.  With G > 1
-// the G lanes of a group share the quartet: lane `sub` takes the primitive
-// quartets sub, sub+G, ...; `vrr(F, c)` adds one primitive quartet to the
-// caller's accumulators, which are summed over the group afterwards.
-template <int L, typename T, int G, class V>
+template <int L, typename T>
+__device__ __forceinline__ void prim_setup(T p, T oo2p, T PAx, T PAy, T PAz, T Kab, T q, T oo2q,
+                                           T QCx, T QCy, T QCz, T Kcd, T ACx, T ACy, T ACz,
+                                           const EriLaunch& a, T* F, VrrCoef<T>& c) {
+  PrimGeo<L, T> g;
+  prim_geo<L, T>(p, PAx, PAy, PAz, q, QCx, QCy, QCz, ACx, ACy, ACz, a, g);
+  prim_finish<L, T>(g, p, oo2p, PAx, PAy, PAz, Kab, q, oo2q, QCx, QCy, QCz, Kcd, a, F, c);
+}
+
+// Read-only global data that the kernels never write: the constant address
+// space lets the compiler use scalar loads where the address is uniform.
+using CDouble = const __attribute__((address_space(4))) double*;
+
+// Keeps the compiler from moving instructions across this point: the Boys
+// row of the next primitive quartet is requested before the current one is
+// used, so that its latency overlaps the current recurrences.
+__device__ __forceinline__ void pipeline_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+// Classes with at most this many contracted intermediates software-pipeline
+// their primitive loop (two Boys rows in flight need about 40 more VGPRs).
+#ifndef JK_PIPE_MAX_NACC
+#define JK_PIPE_MAX_NACC 0
+#endif
+template <class C>
+constexpr bool kPipelined = C::NACC <= JK_PIPE_MAX_NACC;
+
+// Contraction loop of one shell quartet: bra pair i, ket pair k.  `vrr(F, c)`
+// adds one primitive quartet to the caller's accumulators.
+//
+// G == 1: the bra pair is uniform across the wavefront; its primitive pairs
+// come from the pair-major copy through scalar loads, the ket primitive pair
+// of the lane is loaded once per ket primitive.
+//
+// G > 1: the G lanes of a group share the quartet; lane `sub` takes the
+// primitive quartets sub, sub+G, ... as (kl, ij) with ij running fastest; the
+// group's accumulators are summed by the caller.
+//
+// PIPE: the loop is software-pipelined by one step (two alternating stages):
+// the Boys row of the next primitive quartet is requested before the current
+// one is finished.
+template <int L, typename T, int G, bool PIPE, class V>
 __device__ __forceinline__ void contract(const EriLaunch& a, int i, int k, int sub, T ACx, T ACy,
                                          T ACz, V&& vrr) {
-  const int nb = a.bra.n, nk = a.ket.n;
+  const int nk = a.ket.n;
   const int nppb = a.bra.npp, nppk = a.ket.npp;
   if constexpr (G == 1) {
     (void)sub;
+    const CDouble bt = (CDouble)(a.bra.primT) + static_cast<size_t>(i) * nppb * kPrimFields;
     for (int kl = 0; kl < nppk; ++kl) {
       const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
       const T q = T(kp[kP * nk]), oo2q = T(kp[kOo2p * nk]);
       const T QCx = T(kp[kPAx * nk]), QCy = T(kp[kPAy * nk]), QCz = T(kp[kPAz * nk]);
       const T Kcd = T(kp[kKt * nk]);
-      // bra primitive pairs are uniform across the wave; the next one is
-      // loaded while the current one is being used
-      const double* bp = a.bra.prim + i;
-      double b0 = bp[kP * nb], b1 = bp[kOo2p * nb], b2 = bp[kPAx * nb], b3 = bp[kPAy * nb],
-             b4 = bp[kPAz * nb], b5 = bp[kKt * nb];
-      for (int ij = 0; ij < nppb; ++ij) {
-        const double* bn = a.bra.prim + static_cast<size_t>(ij + 1 < nppb ? ij + 1 : ij) * kPrimFields * nb + i;
-        const double n0 = bn[kP * nb], n1 = bn[kOo2p * nb], n2 = bn[kPAx * nb],
-                     n3 = bn[kPAy * nb], n4 = bn[kPAz * nb], n5 = bn[kKt * nb];
+      auto geo = [&](int ij, PrimGeo<L, T>& g) {
+        const CDouble b = bt + ij * kPrimFields;
+        prim_geo<L, T>(T(b[kP]), T(b[kPAx]), T(b[kPAy]), T(b[kPAz]), q, QCx, QCy, QCz, ACx, ACy,
+                       ACz, a, g);
+      };
+      auto finish = [&](int ij, const PrimGeo<L, T>& g) {
+        const CDouble b = bt + ij * kPrimFields;
         T F[L + 1];
         VrrCoef<T> c;
-        prim_setup<L, T>(T(b0), T(b1), T(b2), T(b3), T(b4), T(b5), q, oo2q, QCx, QCy, QCz, Kcd,
-                         ACx, ACy, ACz, a, F, c);
+        prim_finish<L, T>(g, T(b[kP]), T(b[kOo2p]), T(b[kPAx]), T(b[kPAy]), T(b[kPAz]),
+                          T(b[kKt]), q, oo2q, QCx, QCy, QCz, Kcd, a, F, c);
         vrr(F, c);
-        b0 = n0; b1 = n1; b2 = n2; b3 = n3; b4 = n4; b5 = n5;
+      };
+      if constexpr (PIPE) {
+        PrimGeo<L, T> g0, g1;
+        geo(0, g0);
+        for (int ij = 0;;) {
+          if (ij + 1 < nppb) geo(ij + 1, g1);
+          pipeline_fence();
+          finish(ij, g0);
+          if (++ij == nppb) break;
+          if (ij + 1 < nppb) geo(ij + 1, g0);
+          pipeline_fence();
+          finish(ij, g1);
+          if (++ij == nppb) break;
+        }
+      } else {
+        for (int ij = 0; ij < nppb; ++ij) {
+          PrimGeo<L, T> g;
+          geo(ij, g);
+          finish(ij, g);
+        }
       }
     }
   } else {
-    // primitive quartets sub, sub+G, ... as (kl, ij) with ij running fastest
-    int kl = 0, ij = sub;
-    while (ij >= nppb) { ij -= nppb; ++kl; }
-    for (; kl < nppk;) {
+    const double* bt = a.bra.primT + static_cast<size_t>(i) * nppb * kPrimFields;
+    const int npq = nppb * nppk;
+    auto geo = [&](int kl, int ij, PrimGeo<L, T>& g) {
+      const double* b = bt + ij * kPrimFields;
       const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
-      const double* bp = a.bra.prim + static_cast<size_t>(ij) * kPrimFields * nb + i;
+      prim_geo<L, T>(T(b[kP]), T(b[kPAx]), T(b[kPAy]), T(b[kPAz]), T(kp[kP * nk]),
+                     T(kp[kPAx * nk]), T(kp[kPAy * nk]), T(kp[kPAz * nk]), ACx, ACy, ACz, a, g);
+    };
+    auto finish = [&](int kl, int ij, const PrimGeo<L, T>& g) {
+      const double* b = bt + ij * kPrimFields;
+      const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
       T F[L + 1];
       VrrCoef<T> c;
-      prim_setup<L, T>(T(bp[kP * nb]), T(bp[kOo2p * nb]), T(bp[kPAx * nb]), T(bp[kPAy * nb]),
-                       T(bp[kPAz * nb]), T(bp[kKt * nb]), T(kp[kP * nk]), T(kp[kOo2p * nk]),
-                       T(kp[kPAx * nk]), T(kp[kPAy * nk]), T(kp[kPAz * nk]), T(kp[kKt * nk]),
-                       ACx, ACy, ACz, a, F, c);
+      prim_finish<L, T>(g, T(b[kP]), T(b[kOo2p]), T(b[kPAx]), T(b[kPAy]), T(b[kPAz]), T(b[kKt]),
+                        T(kp[kP * nk]), T(kp[kOo2p * nk]), T(kp[kPAx * nk]), T(kp[kPAy * nk]),
+                        T(kp[kPAz * nk]), T(kp[kKt * nk]), a, F, c);
       vrr(F, c);
+    };
+    auto step = [&](int& kl, int& ij) {
       ij += G;
       while (ij >= nppb) { ij -= nppb; ++kl; }
+    };
+    int kl0 = 0, ij0 = sub;
+    while (ij0 >= nppb) { ij0 -= nppb; ++kl0; }
+    if constexpr (PIPE) {
+      // (kl0, ij0): quartet t held by the stage about to be finished
+      int t = sub;
+      PrimGeo<L, T> g0, g1;
+      if (t < npq) geo(kl0, ij0, g0);
+      while (t < npq) {
+        int kl1 = kl0, ij1 = ij0;
+        step(kl1, ij1);
+        if (t + G < npq) geo(kl1, ij1, g1);
+        pipeline_fence();
+        finish(kl0, ij0, g0);
+        t += G;
+        if (t >= npq) break;
+        kl0 = kl1; ij0 = ij1;
+        step(kl1, ij1);
+        if (t + G < npq) geo(kl1, ij1, g0);
+        pipeline_fence();
+        finish(kl0, ij0, g1);
+        t += G;
+        kl0 = kl1; ij0 = ij1;
+      }
+    } else {
+      for (int t = sub; t < npq; t += G) {
+        PrimGeo<L, T> g;
+        geo(kl0, ij0, g);
+        finish(kl0, ij0, g);
+        step(kl0, ij0);
+      }
     }
   }
 }
 
-// Sum over the G lanes of a group (G a power of two dividing 64).
+// Cross-lane moves of an FP64 value within rows of 16 lanes (DPP on the two
+// 32-bit halves; no LDS traffic).
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_f64(double v, double old) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const long long o = __builtin_bit_cast(long long, old);
+  const int lo = __builtin_amdgcn_update_dpp(static_cast<int>(o), static_cast<int>(b), CTRL,
+                                             ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(static_cast<int>(o >> 32), static_cast<int>(b >> 32),
+                                             CTRL, ROW_MASK, 0xF, false);
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) |
+                                        static_cast<unsigned long long>(static_cast<unsigned>(lo)));
+}
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp_f32(float v, float old) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v),
+                                         CTRL, ROW_MASK, 0xF, false));
+}
+
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_t(T v) {
+  if constexpr (sizeof(T) == 8) return dpp_f64<CTRL>(v, v);
+  else return dpp_f32<CTRL>(v, v);
+}
+
+// Sum over the G lanes of a group (G = 1, 2, 4, 8 or 16 consecutive lanes);
+// every lane of the group ends with the sum.  Steps: swap neighbours, swap
+// pairs within a quad, mirror within half-rows, mirror within rows.
 template <int G, typename T>
 __device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-  for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off, kWave);
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group size");
+  if constexpr (G >= 2) v += dpp_t<0xB1>(v);    // quad_perm [1,0,3,2]
+  if constexpr (G >= 4) v += dpp_t<0x4E>(v);    // quad_perm [2,3,0,1]
+  if constexpr (G >= 8) v += dpp_t<0x141>(v);   // row_half_mirror
+  if constexpr (G >= 16) v += dpp_t<0x140>(v);  // row_mirror
   return v;
 }
 
@@ -342,9 +533,14 @@ __device__ __forceinline__ int opaque_zero() {
   return z;
 }
 
+// Sum over the wavefront; the result is complete in lane kWaveSumLane only.
+// Row sums by DPP, then row 0 is added into row 1 and rows 0-1 into rows 2-3
+// (row broadcasts of lanes 15 and 31).
+constexpr int kWaveSumLane = kWave - 1;
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  v = group_sum<16>(v);
+  v += dpp_f64<0x142, 0xA>(v, 0.0);   // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v, 0.0);   // row_bcast:31 into rows 2 and 3
   return v;
 }
 
@@ -383,7 +579,7 @@ __global__ __launch_bounds__(kBlock) void eri_jk_kernel(const EriLaunch a) {
     T acc[C::NACC];
 #pragma unroll
     for (int t = 0; t < C::NACC; ++t) acc[t] = T(0);
-    contract<C::L, T, G>(a, i, k, sub, ACx, ACy, ACz,
+    contract<C::L, T, G, kPipelined<C>>(a, i, k, sub, ACx, ACy, ACz,
                          [&](const T* F, const VrrCoef<T>& c) { C::template vrr<T>(F, c, acc); });
     group_sum_all<G>(acc);
 
@@ -440,7 +636,7 @@ __global__ __launch_bounds__(kBlock) void eri_jk_kernel(const EriLaunch a) {
 #pragma unroll
       for (int t = 0; t < C::NA * C::NB; ++t) {
         const double s = wave_sum(jab[t]);
-        if (lane == 0)
+        if (lane == kWaveSumLane)
           atomic_add(&Jm[(a0 + t / C::NB) * static_cast<size_t>(a.n) + b0 + t % C::NB], 2.0 * s);
       }
       if (active) {
@@ -478,7 +674,7 @@ __global__ __launch_bounds__(kBlock) void schwarz_kernel(const EriLaunch a, doub
   double acc[C::NACC];
 #pragma unroll
   for (int s = 0; s < C::NACC; ++s) acc[s] = 0.0;
-  contract<C::L, double, G>(a, t, t, sub, 0.0, 0.0, 0.0,
+  contract<C::L, double, G, false>(a, t, t, sub, 0.0, 0.0, 0.0,
                             [&](const double* F, const VrrCoef<double>& c) {
                               C::template vrr<double>(F, c, acc);
                             });
@@ -500,7 +696,7 @@ __device__ __forceinline__ void split_passes(const EriLaunch& a, int i, int k, i
   T acc[C::NE * NFJ];
 #pragma unroll
   for (int t = 0; t < C::NE * NFJ; ++t) acc[t] = T(0);
-  contract<C::L, T, G>(a, i, k, sub, ACx, ACy, ACz, [&](const T* F, const VrrCoef<T>& c) {
+  contract<C::L, T, G, kPipelined<C>>(a, i, k, sub, ACx, ACy, ACz, [&](const T* F, const VrrCoef<T>& c) {
     C::template vrr_pass<J, T>(F, c, acc);
   });
   group_sum_all<G>(acc);
@@ -653,7 +849,7 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
 #pragma unroll
       for (int t = 0; t < C::NA * C::NB; ++t) {
         const double s = wave_sum(jab[t]);
-        if (lane == 0) atomic_add(&Jm[(a0 + t / C::NB) * n + b0 + t % C::NB], 2.0 * s);
+        if (lane == kWaveSumLane) atomic_add(&Jm[(a0 + t / C::NB) * n + b0 + t % C::NB], 2.0 * s);
       }
       if (active) {
 #pragma unroll

@@ -251,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
         const double ga = fq * gA[x], gb = fq * gB[x], gc = fq * gC[x];
         const double gd = -(ga + gb + gc);
         const double sa = wave_sum(ga), sb = wave_sum(gb);
-        if (lane == 0) {
+        if (lane == kWaveSumLane) {
           atomic_add(&G3[atA * 3 + x], sa);
           atomic_add(&G3[atB * 3 + x], sb);
         }

@@ -113,6 +113,7 @@ struct ShellDev {
 
 struct PairOut {
   double* prim;        // all bins, bin b at prim_off[b]
+  double* primT;       // pair-major copy, same offsets
   double* A;           // bin b at 3*pair_off[b], [3][n_b]
   double* AB;
   int* bf;             // bin b at 2*pair_off[b]
@@ -163,6 +164,7 @@ __global__ void pair_data_kernel(int npairs, const int* __restrict__ pair_s1,
   const double kSqrt2Pi54 = 5.9149671727956128778;  // sqrt(2) * pi^(5/4)
   const int n1 = sh.nprim[s1], n2 = sh.nprim[s2];
   double* prim = out.prim + bin_prim_off[b];
+  double* primT = out.primT + bin_prim_off[b] + static_cast<size_t>(t) * n1 * n2 * kPrimFields;
   for (int u = 0; u < n1; ++u)
     for (int v = 0; v < n2; ++v) {
       const int pp = u * n2 + v;
@@ -179,6 +181,8 @@ __global__ void pair_data_kernel(int npairs, const int* __restrict__ pair_s1,
       f[kKt * n] = kSqrt2Pi54 * Kab * rp;
       f[kTwoA * n] = 2.0 * ea;
       f[kTwoB * n] = 2.0 * eb;
+      double* h = primT + static_cast<size_t>(pp) * kPrimFields;
+      for (int x = 0; x < kPrimFields; ++x) h[x] = f[x * n];
     }
   (void)bin_npp;
 }
@@ -326,7 +330,7 @@ struct DevBuf {
 };
 
 enum Slot {
-  sShellXyz, sShellI, sExps, sCoefs, sPairS, sBinOff, sBinNpp, sBinPrim, sPrimTmp, sPrim,
+  sShellXyz, sShellI, sExps, sCoefs, sPairS, sBinOff, sBinNpp, sBinPrim, sPrimTmp, sPrim, sPrimTmpT, sPrimT,
   sA, sAB, sBf, sAtoms, sFpair, sAtmp, sABtmp, sBftmp, sAtomstmp, sFpairtmp, sQtmp, sQ,
   sIdx, sIdxSorted, sPerm, sBp, sCnt, sOff, sRng, sQstat, sSeg, sItems, sCub, sChunk, sWs0, sWs1,
   sWs2, sWs3, sWsSchwarz, sNumSlots
@@ -350,7 +354,10 @@ struct jk_ctx {
   size_t ev_setup0 = 0, ev_setup1 = 0, ev_end = 0;
   void* host_pinned = nullptr;
   size_t host_pinned_bytes = 0;
-  static constexpr int kStreams = 2;   // class launches are spread over these
+#ifndef JK_STREAMS
+#define JK_STREAMS 2
+#endif
+  static constexpr int kStreams = JK_STREAMS;   // class launches are spread over these
   hipStream_t streams[kStreams] = {};
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kStreams] = {};
@@ -491,13 +498,14 @@ void upload(const std::vector<T>& v, T* d, hipStream_t s) {
   if (!v.empty()) HIP_OK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
-BinView bin_view(const Plan& P, int b, double* prim, double* A, double* AB, int* bf, int* atoms,
-                 double* fpair, double* Q) {
+BinView bin_view(const Plan& P, int b, double* prim, double* primT, double* A, double* AB, int* bf,
+                 int* atoms, double* fpair, double* Q) {
   BinView v;
   const int o = P.bin_off[b];
   v.n = P.bin_off[b + 1] - o;
   v.npp = P.bin_npp[b];
   v.prim = prim + P.bin_prim[b];
+  v.primT = primT + P.bin_prim[b];
   v.A = A + 3 * o;
   v.AB = AB + 3 * o;
   v.bf = bf + 2 * o;
@@ -509,7 +517,7 @@ BinView bin_view(const Plan& P, int b, double* prim, double* A, double* AB, int*
 
 struct Setup {
   Plan P;
-  double *prim, *A, *AB, *fpair, *Q;
+  double *prim, *primT, *A, *AB, *fpair, *Q;
   int *bf, *atoms;
   int4* items;
   std::vector<int> seg;   // [2][nbp+1]
@@ -551,6 +559,8 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
   const size_t nprimd = static_cast<size_t>(P.bin_prim.back());
   double* d_primtmp = dev<double>(c, sPrimTmp, nprimd);
   S.prim = dev<double>(c, sPrim, nprimd);
+  S.primT = dev<double>(c, sPrimT, nprimd);
+  double* d_primtmpT = dev<double>(c, sPrimTmpT, nprimd);
   S.A = dev<double>(c, sA, 3 * static_cast<size_t>(np));
   S.AB = dev<double>(c, sAB, 3 * static_cast<size_t>(np));
   S.bf = dev<int>(c, sBf, 2 * static_cast<size_t>(np));
@@ -581,14 +591,14 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
 
   ShellDev sd{d_sxyz, d_si, d_si + ns, d_si + 2 * ns, d_si + 3 * ns, d_si + 4 * ns, d_exps, d_coefs};
   // step 2 (unsorted), step 3
-  PairOut tmp{d_primtmp, d_Atmp, d_ABtmp, d_bftmp, d_atomstmp, d_fpairtmp};
+  PairOut tmp{d_primtmp, d_primtmpT, d_Atmp, d_ABtmp, d_bftmp, d_atomstmp, d_fpairtmp};
   hipLaunchKernelGGL(pair_data_kernel, dim3(grid_of(np, 256)), dim3(256), 0, s, np, d_pairs,
                      d_pairs + np, static_cast<const int*>(nullptr), d_binoff, d_binnpp,
                      d_binprim, P.nbins, sd, tmp);
   HIP_OK(hipGetLastError());
   for (int bb = 0; bb < P.nbins; ++bb) {
     EriLaunch a{};
-    a.bra = bin_view(P, bb, d_primtmp, d_Atmp, d_ABtmp, d_bftmp, d_atomstmp, d_fpairtmp, d_Qtmp);
+    a.bra = bin_view(P, bb, d_primtmp, d_primtmpT, d_Atmp, d_ABtmp, d_bftmp, d_atomstmp, d_fpairtmp, d_Qtmp);
     a.ket = a.bra;
     a.boys64 = c->boys64;
     a.boys32 = c->boys32;
@@ -615,7 +625,7 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
       64, s));
   hipLaunchKernelGGL(local_to_global_kernel, dim3(grid_of(np, 256)), dim3(256), 0, s, np,
                      d_binoff, P.nbins, d_idxs, d_perm);
-  PairOut fin{S.prim, S.A, S.AB, S.bf, S.atoms, S.fpair};
+  PairOut fin{S.prim, S.primT, S.A, S.AB, S.bf, S.atoms, S.fpair};
   hipLaunchKernelGGL(pair_data_kernel, dim3(grid_of(np, 256)), dim3(256), 0, s, np, d_pairs,
                      d_pairs + np, d_perm, d_binoff, d_binnpp, d_binprim, P.nbins, sd, fin);
   HIP_OK(hipGetLastError());
@@ -727,8 +737,8 @@ jk_stats base_stats(const Plan& P, const Setup& S) {
 EriLaunch launch_args(jk_ctx* c, const Plan& P, const Setup& S, int X, int Y, int i0, int i1,
                       const double* D, double* J, double* K, int nbf, const jk_opts& o) {
   EriLaunch a{};
-  a.bra = bin_view(P, X, S.prim, S.A, S.AB, S.bf, S.atoms, S.fpair, S.Q);
-  a.ket = bin_view(P, Y, S.prim, S.A, S.AB, S.bf, S.atoms, S.fpair, S.Q);
+  a.bra = bin_view(P, X, S.prim, S.primT, S.A, S.AB, S.bf, S.atoms, S.fpair, S.Q);
+  a.ket = bin_view(P, Y, S.prim, S.primT, S.A, S.AB, S.bf, S.atoms, S.fpair, S.Q);
   a.items = S.items + i0;
   a.nitems = i1 - i0;
   a.same_bin = X == Y;

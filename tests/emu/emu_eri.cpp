@@ -1,5 +1,6 @@
 // Host build of the generated energy-class code: contracted shell quartets with an
 // exact Boys function, for comparison with the oracle (test harness, CPU only).
+#include <type_traits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -119,6 +120,18 @@ static void block_split(const Sh& a, const Sh& b, const Sh& c, const Sh& d, doub
   }
 }
 
+// single-pass classes have no NPASS member; multi-pass classes do
+template <class C, class = void>
+struct is_split : std::false_type {};
+template <class C>
+struct is_split<C, std::void_t<decltype(C::NPASS)>> : std::true_type {};
+
+template <class C>
+static void block(const Sh& a, const Sh& b, const Sh& c, const Sh& d, double* out) {
+  if constexpr (is_split<C>::value) block_split<C>(a, b, c, d, out);
+  else block_single<C>(a, b, c, d, out);
+}
+
 extern "C" int emu_block(int cls, const int* l, const int* np, const double* A, const double* e,
                          const double* c, double* out) {
   Sh s[4];
@@ -128,11 +141,10 @@ extern "C" int emu_block(int cls, const int* l, const int* np, const double* A, 
     for (int i = 0; i < np[k]; ++i) { s[k].e[i] = e[8 * k + i]; s[k].c[i] = c[8 * k + i]; }
   }
   switch (cls) {
-#define S1(i, N) case i: block_single<Cls_##N>(s[0], s[1], s[2], s[3], out); break;
-#define S2(i, N) case i: block_split<Cls_##N>(s[0], s[1], s[2], s[3], out); break;
+#define S1(i, N) case i: block<Cls_##N>(s[0], s[1], s[2], s[3], out); break;
     S1(0, ssss) S1(1, psss) S1(2, psps) S1(3, ppss) S1(4, ppps) S1(5, pppp) S1(6, dsss) S1(7, dsps)
-    S1(8, dspp) S1(9, dsds) S1(10, dpss) S1(11, dpps) S1(12, dppp) S1(13, dpds) S2(14, dpdp)
-    S1(15, ddss) S1(16, ddps) S2(17, ddpp) S2(18, ddds) S2(19, dddp) S2(20, dddd)
+    S1(8, dspp) S1(9, dsds) S1(10, dpss) S1(11, dpps) S1(12, dppp) S1(13, dpds) S1(14, dpdp)
+    S1(15, ddss) S1(16, ddps) S1(17, ddpp) S1(18, ddds) S1(19, dddp) S1(20, dddd)
     default: return -1;
   }
   return 0;
