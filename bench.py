@@ -53,6 +53,98 @@ def flops_per_quartet(info, npp_b=9, npp_k=9, n_dm=1):
             + info["hrr_flops"] + n_dm * info["digest_flops"])
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_w30_fp64.md")
+FINGERPRINT_SOURCES = ["paper_2406_11185_amd/csrc/gen_hgp.py", "paper_2406_11185_amd/csrc/jk_device.hpp",
+                       "paper_2406_11185_amd/csrc/jk_host.hip", "paper_2406_11185_amd/csrc/jk_classes.hpp"]
+
+
+def source_fingerprint() -> str:
+    """Hash of the sources that decide the J/K kernels' code: counter data taken
+    with another fingerprint describe other kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in FINGERPRINT_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_key(name: str):
+    """'eri_jk <class> fp64|fp32' for a J/K class kernel name, else None."""
+    import re
+    m = re.search(r"jk::eri_jk(?:_lds|_split)?_kernel<jk::Cls_(\w+), (double|float)", name)
+    if not m:
+        return None
+    return f"eri_jk {m.group(1)} {'fp64' if m.group(2) == 'double' else 'fp32'}"
+
+
+def pmc_summary(fetch_csv: str, write_csv: str, out: str, calib_mib: int, command: str) -> None:
+    """Per-dispatch HBM bytes of every J/K class kernel from two rocprofv3 --pmc
+    runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), scaled by what the same
+    counters read for the copy of calib_mib MiB made before the steps."""
+    import csv
+    from collections import defaultdict
+
+    def load(path, counter):
+        per = defaultdict(list)
+        copy = []
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"])
+                if "copyBuffer" in r["Kernel_Name"]:
+                    copy.append(v)
+                k = kernel_key(r["Kernel_Name"])
+                if k:
+                    per[k].append(v)
+        return per, max(copy) if copy else None
+
+    fetch, fcopy = load(fetch_csv, "FETCH_SIZE")
+    write, wcopy = load(write_csv, "WRITE_SIZE")
+    known = calib_mib * 1024.0
+    fs, ws = known / fcopy, known / wcopy
+    lines = ["# HBM traffic per dispatch: J/K build, 30 atoms / 270 functions, tol 1e-10, FP64", "",
+             "Two rocprofv3 counter runs of the benchmark (kernels are serialised while counters "
+             "are collected), from the repository root on the GPU box:", "", "```",
+             command.replace("PMC", "FETCH_SIZE"), command.replace("PMC", "WRITE_SIZE"), "```", "",
+             f"Calibration: the {calib_mib} MiB device-to-device copy made before the steps reads "
+             f"FETCH_SIZE = {fcopy:.1f} KiB and WRITE_SIZE = {wcopy:.1f} KiB for {known:.0f} KiB "
+             f"moved each way, so read bytes = FETCH_SIZE x {fs:.3f} and written bytes = "
+             f"WRITE_SIZE x {ws:.3f}.", "",
+             f"source fingerprint: `{source_fingerprint()}`", "",
+             "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read MB | written MB | traffic MB |",
+             "|---|---|---|---|---|---|---|"]
+    rows = []
+    for k in sorted(set(fetch) & set(write)):
+        f = sum(fetch[k]) / len(fetch[k])
+        w = sum(write[k]) / len(write[k])
+        rd, wr = f * fs * 1024 / 1e6, w * ws * 1024 / 1e6
+        rows.append((rd + wr, f"| {k} | {len(fetch[k])} | {f:.1f} | {w:.1f} | {rd:.3f} | {wr:.3f} | "
+                              f"{rd + wr:.3f} |"))
+    lines += [r for _, r in sorted(rows, reverse=True)]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def traffic_of(kernel: str):
+    """HBM bytes per dispatch of `kernel` from the committed counter summary, or
+    None if there is none or the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    if f"source fingerprint: `{source_fingerprint()}`" not in text:
+        return None
+    for ln in text.splitlines():
+        cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+        if len(cells) == 7 and cells[0] == kernel:
+            return float(cells[6]) * 1e6
+    return None
+
+
 def cpu_baseline(mol, tol, seconds_target=15.0):
     """Oracle timed on a growing sample of unique bra pairs (all their kets)."""
     import numpy as np
@@ -105,7 +197,16 @@ def main():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB once (a kernel of "
                          "known traffic for scaling hardware byte counters)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the per-dispatch HBM traffic summary from two rocprofv3 "
+                         "counter_collection.csv files and exit (no GPU use)")
+    ap.add_argument("--pmc-command", default="",
+                    help="with --pmc-summary: the profiled command, PMC standing for the counter")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], TRAFFIC_FILE,
+                    args.copy_calib_mib or 256, args.pmc_command)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -160,6 +261,7 @@ def main():
     mean_s = ms_sum / nlaunch / 1e3
     achieved = flops_launch / mean_s / 1e12
     peak = FP64_PEAK_TFLOPS if prd == 0 else FP32_PEAK_TFLOPS
+    kname = f"eri_jk {info['name']} {'fp32' if prd else 'fp64'}"
     total_kernel_ms = sum(a[0] for a in agg.values()) / len(stats)
     total_flops = 0.0
     for (q, pr), a in agg.items():
@@ -182,8 +284,10 @@ def main():
                    "n_dm": int(D.shape[0]), "screened_quartets": int(quartets),
                    "skipped_quartets": int(st.quartets_skipped)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": f"eri_jk {info['name']} {'fp32' if prd else 'fp64'}",
+                     "frac": achieved / peak,
+                     "traffic": traffic_of(kname) if args.workload == "w30" and precision == "fp64"
+                     else None,
+                     "kernel": kname,
                      "flops_per_launch": flops_launch, "mean_launch_ms": mean_s * 1e3,
                      "launches": nlaunch},
         "build_kernel_ms": total_kernel_ms,
@@ -213,6 +317,16 @@ def main():
         EJ = {p: 0.5 * float(np.sum(mol2.D[0] * res[p][0][0])) for p in res}
         EK = {p: 0.25 * float(np.sum(mol2.D[0] * res[p][1][0])) for p in res}
         ex["w120_mixed_speedup"] = ex["w120_fp64_ms"] / ex["w120_mixed_ms"]
+        # nuclear gradient of the 30-atom molecule (same geometry and density)
+        G = torch.empty((D.shape[0], mol.n_atoms, 3), dtype=torch.float64, device=dev)
+        og = jkb.make_opts("fp64", n_dm=D.shape[0])
+        jkb.jk_grad(ctx, basis, D, G, tol, og)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(2):
+            jkb.jk_grad(ctx, basis, D, G, tol, og)
+        torch.cuda.synchronize()
+        ex["w30_grad_ms"] = 1e3 * (time.perf_counter() - tg) / 2
         ex["w120_dEJ"] = EJ["mixed"] - EJ["fp64"]
         ex["w120_dEK"] = EK["mixed"] - EK["fp64"]
         result["extra"] = ex

@@ -296,11 +296,18 @@ def lanes_for(L, split):
     return 1 if L <= 2 else 4
 
 
+LDS_MAX_L = 3   # single-pass classes up to this order read the Boys rows from LDS
+
+
+def uses_lds(L, split):
+    return not split and L <= LDS_MAX_L
+
+
 def lane_options(L, split):
     """Lane counts a class is compiled for; the host picks one per launch."""
     if split:
         return [1, 4, 16] if L <= 6 else [4, 16]
-    return [1] if L <= 2 else [1, 4]
+    return [1] if uses_lds(L, split) else [1, 4]
 
 
 def gen_class(la, lb, lc, ld):
@@ -392,7 +399,8 @@ def gen_class(la, lb, lc, ld):
                 nint=na * nb * nc * nd, vrr_flops=vrr_flops, hrr_flops=hrr_flops,
                 digest_flops=dig_flops, vrr_nodes=vrr.n, hrr_nodes=hrr.n, nf=nf,
                 vrr_flops_alg=vrr_flops, lanes=lanes_for(L, False),
-                lane_options=lane_options(L, False))
+                lane_options=lane_options(L, False), lds=uses_lds(L, False),
+                lds_block=1024 if L <= 2 else 512)
     return "\n".join(s) + "\n", info
 
 
@@ -564,6 +572,13 @@ def wrapper(info):
          "namespace jk {",
          f'#include "cls_{n}.inc"',
          f"void launch_eri_{n}(const EriLaunch& a, int fp32, hipStream_t s) {{",
+         *([f"  // Boys rows staged in LDS; the workgroups loop over the items",
+            f"  constexpr int NT = {info.get('lds_block', 0)};",
+            f"  const dim3 lgrid(std::min((a.nitems + NT / kWave - 1) / (NT / kWave), kLdsMaxBlocks));",
+            f"  if (fp32) hipLaunchKernelGGL((eri_jk_lds_kernel<Cls_{n}, float, NT>), lgrid, dim3(NT), 0, s, a);",
+            f"  else hipLaunchKernelGGL((eri_jk_lds_kernel<Cls_{n}, double, NT>), lgrid, dim3(NT), 0, s, a);",
+            "}"] if info.get("lds") else []),
+         *([] if info.get("lds") else [
          "  const int waves = " + ("a.nwaves" if info["split"] else "a.nitems") + ";",
          "  const dim3 grid((waves + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);",
          *[ln for g_ in info["lane_options"] for ln in (
@@ -572,7 +587,7 @@ def wrapper(info):
              f"    if (fp32) hipLaunchKernelGGL(({kern}<Cls_{n}, float, {g_}>), grid, block, 0, s, a);",
              f"    else hipLaunchKernelGGL(({kern}<Cls_{n}, double, {g_}>), grid, block, 0, s, a);",
              "  }")],
-         "}"]
+         "}"])]
     if info["bra_class"] == info["ket_class"]:
         w += [f"void launch_schwarz_{n}(const EriLaunch& a, double* Q, hipStream_t s) {{",
               (f"  hipLaunchKernelGGL(({skern}<Cls_{n}>), dim3((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock),"

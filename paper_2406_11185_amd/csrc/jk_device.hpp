@@ -12,6 +12,7 @@
 //   Q     [n]      Cauchy-Schwarz factor sqrt(max (ab|ab))
 #pragma once
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cstdint>
 
 namespace jk {
@@ -128,19 +129,20 @@ struct BoysRow64 {
   double x;                 // T_i - T
 };
 
-template <int L>
-__device__ __forceinline__ BoysRow64 boys64_fetch(double T, const double* __restrict__ tab) {
-  static_assert(L <= kBoysMaxL, "Boys table order");
-  const double Tt = T < kBoysTmax ? T : 0.0;
+// rows: the table of order L (global memory, or a copy staged in LDS that
+// covers T < tmax only).
+__device__ __forceinline__ BoysRow64 boys64_fetch(double T, const double* __restrict__ rows,
+                                                  double tmax) {
+  const double Tt = T < tmax ? T : 0.0;
   const int i = static_cast<int>(Tt * kBoysInvStep + 0.5);
-  const double2* r2 = reinterpret_cast<const double2*>(
-      tab + (static_cast<size_t>(L) * kBoysRows + i) * kBoysRow);
+  const double2* r2 = reinterpret_cast<const double2*>(rows + i * kBoysRow);
   return BoysRow64{r2[0], r2[1], r2[2], r2[3], i * kBoysStep - Tt};
 }
 
 template <int L>
-__device__ __forceinline__ void boys64_eval(double T, const BoysRow64& row, double* F) {
-  const bool near = T < kBoysTmax;
+__device__ __forceinline__ void boys64_eval(double T, const BoysRow64& row, double tmax, double* F) {
+  static_assert(L <= kBoysMaxL, "Boys table order");
+  const bool near = T < tmax;
   const double Tt = near ? T : 0.0;
   const double x = row.x;
   const double r[8] = {row.q0.x, row.q0.y, row.q1.x, row.q1.y,
@@ -166,7 +168,7 @@ __device__ __forceinline__ void boys64_eval(double T, const BoysRow64& row, doub
 #pragma unroll
     for (int m = L - 1; m >= 0; --m) Ft[m] = (T2 * Ft[m + 1] + e) * kInvOdd[m];
   }
-  const double Ta = near ? kBoysTmax : T;
+  const double Ta = near ? tmax : T;
   const double rs = rsqrt_f64(Ta);
   double fa = 0.88622692545275801364908374167057 * rs;  // sqrt(pi)/2 / sqrt(T)
   const double h = 0.5 * rs * rs;
@@ -190,15 +192,15 @@ struct BoysRow32 {
   double x64;   // FP64 branch: T_j - T
 };
 
+// rows: FP32 table of order L; rows64: FP64 table of order L (global).
 template <int L>
-__device__ __forceinline__ BoysRow32 boys32_fetch(float T, float tcut, const float* __restrict__ tab,
-                                                  const double* __restrict__ tab64) {
+__device__ __forceinline__ BoysRow32 boys32_fetch(float T, float tcut, const float* __restrict__ rows,
+                                                  const double* __restrict__ rows64) {
   BoysRow32 r;
   const bool lo = T <= tcut;
   const float Tl = lo ? T : 0.0f;
   const int i = static_cast<int>(Tl * kBoys32InvStep + 0.5f);
-  const float4* r4 = reinterpret_cast<const float4*>(
-      tab + (static_cast<size_t>(L) * kBoys32Rows + i) * kBoys32Row);
+  const float4* r4 = reinterpret_cast<const float4*>(rows + i * kBoys32Row);
   r.q0 = r4[0];
   r.e = r4[1].x;
   r.x = i * kBoys32Step - Tl;
@@ -209,7 +211,7 @@ __device__ __forceinline__ BoysRow32 boys32_fetch(float T, float tcut, const flo
     if (!lo && Td < kBoysTmax) {
       const int j = static_cast<int>(Td * kBoysInvStep + 0.5);
       r.x64 = j * kBoysStep - Td;
-      r.e64 = tab64[(static_cast<size_t>(L) * kBoysRows + j) * kBoysRow + 7];
+      r.e64 = rows64[j * kBoysRow + 7];
     }
   }
   return r;
@@ -259,27 +261,56 @@ __device__ __forceinline__ void boys32_eval(float T, float tcut, const BoysRow32
   }
 }
 
+// Where a kernel reads the Boys rows of its order L from.
+template <typename T>
+struct BoysTab;
+template <>
+struct BoysTab<double> {
+  const double* rows;   // order-L FP64 rows
+  double tmax;          // tabulated range T < tmax; asymptotic form beyond
+};
+template <>
+struct BoysTab<float> {
+  const float* rows;     // order-L FP32 rows (T <= tcut)
+  float tcut;            // FP64 evaluation above
+  const double* rows64;  // order-L FP64 rows, for e^{-T} above tcut
+};
+
+// The tables in global memory.
+template <int L, typename T>
+__device__ __forceinline__ BoysTab<T> global_boys(const EriLaunch& a) {
+  static_assert(L <= kBoysMaxL, "Boys table order");
+  const double* r64 = a.boys64 + static_cast<size_t>(L) * kBoysRows * kBoysRow;
+  if constexpr (sizeof(T) == 8) {
+    return BoysTab<double>{r64, kBoysTmax};
+  } else {
+    return BoysTab<float>{a.boys32 + static_cast<size_t>(L) * kBoys32Rows * kBoys32Row,
+                          a.boys_fp64_T, r64};
+  }
+}
+
 template <int L, typename T>
 struct Boys;
 template <int L>
 struct Boys<L, double> {
   using Row = BoysRow64;
-  __device__ __forceinline__ static Row fetch(double T, const EriLaunch& a) {
-    return boys64_fetch<L>(T, a.boys64);
+  __device__ __forceinline__ static Row fetch(double T, const BoysTab<double>& t) {
+    return boys64_fetch(T, t.rows, t.tmax);
   }
-  __device__ __forceinline__ static void eval(double T, const Row& r, const EriLaunch& a, double* F) {
-    (void)a;
-    boys64_eval<L>(T, r, F);
+  __device__ __forceinline__ static void eval(double T, const Row& r, const BoysTab<double>& t,
+                                              double* F) {
+    boys64_eval<L>(T, r, t.tmax, F);
   }
 };
 template <int L>
 struct Boys<L, float> {
   using Row = BoysRow32;
-  __device__ __forceinline__ static Row fetch(float T, const EriLaunch& a) {
-    return boys32_fetch<L>(T, a.boys_fp64_T, a.boys32, a.boys64);
+  __device__ __forceinline__ static Row fetch(float T, const BoysTab<float>& t) {
+    return boys32_fetch<L>(T, t.tcut, t.rows, t.rows64);
   }
-  __device__ __forceinline__ static void eval(float T, const Row& r, const EriLaunch& a, float* F) {
-    boys32_eval<L>(T, a.boys_fp64_T, r, F);
+  __device__ __forceinline__ static void eval(float T, const Row& r, const BoysTab<float>& t,
+                                              float* F) {
+    boys32_eval<L>(T, t.tcut, r, F);
   }
 };
 
@@ -303,7 +334,7 @@ struct PrimGeo {
 
 template <int L, typename T>
 __device__ __forceinline__ void prim_geo(T p, T PAx, T PAy, T PAz, T q, T QCx, T QCy, T QCz,
-                                         T ACx, T ACy, T ACz, const EriLaunch& a,
+                                         T ACx, T ACy, T ACz, const BoysTab<T>& bt,
                                          PrimGeo<L, T>& g) {
   g.srpq = rsqrt_t<T>(p + q);   // 1/sqrt(p+q)
   const T rpq = g.srpq * g.srpq;
@@ -311,16 +342,16 @@ __device__ __forceinline__ void prim_geo(T p, T PAx, T PAy, T PAz, T q, T QCx, T
   g.PQy = PAy - QCy + ACy;
   g.PQz = PAz - QCz + ACz;
   g.Tb = p * (q * rpq) * (g.PQx * g.PQx + g.PQy * g.PQy + g.PQz * g.PQz);
-  g.row = Boys<L, T>::fetch(g.Tb, a);
+  g.row = Boys<L, T>::fetch(g.Tb, bt);
 }
 
 template <int L, typename T>
 __device__ __forceinline__ void prim_finish(const PrimGeo<L, T>& g, T p, T oo2p, T PAx, T PAy,
                                             T PAz, T Kab, T q, T oo2q, T QCx, T QCy, T QCz,
-                                            T Kcd, const EriLaunch& a, T* F, VrrCoef<T>& c) {
+                                            T Kcd, const BoysTab<T>& bt, T* F, VrrCoef<T>& c) {
   const T rpq = g.srpq * g.srpq;
   const T qr = q * rpq, pr = p * rpq;
-  Boys<L, T>::eval(g.Tb, g.row, a, F);
+  Boys<L, T>::eval(g.Tb, g.row, bt, F);
   const T pref = Kab * Kcd * g.srpq;
 #pragma unroll
   for (int m = 0; m <= L; ++m) F[m] *= pref;
@@ -337,9 +368,10 @@ template <int L, typename T>
 __device__ __forceinline__ void prim_setup(T p, T oo2p, T PAx, T PAy, T PAz, T Kab, T q, T oo2q,
                                            T QCx, T QCy, T QCz, T Kcd, T ACx, T ACy, T ACz,
                                            const EriLaunch& a, T* F, VrrCoef<T>& c) {
+  const BoysTab<T> bt = global_boys<L, T>(a);
   PrimGeo<L, T> g;
-  prim_geo<L, T>(p, PAx, PAy, PAz, q, QCx, QCy, QCz, ACx, ACy, ACz, a, g);
-  prim_finish<L, T>(g, p, oo2p, PAx, PAy, PAz, Kab, q, oo2q, QCx, QCy, QCz, Kcd, a, F, c);
+  prim_geo<L, T>(p, PAx, PAy, PAz, q, QCx, QCy, QCz, ACx, ACy, ACz, bt, g);
+  prim_finish<L, T>(g, p, oo2p, PAx, PAy, PAz, Kab, q, oo2q, QCx, QCy, QCz, Kcd, bt, F, c);
 }
 
 // Read-only global data that the kernels never write: the constant address
@@ -374,29 +406,29 @@ constexpr bool kPipelined = C::NACC <= JK_PIPE_MAX_NACC;
 // the Boys row of the next primitive quartet is requested before the current
 // one is finished.
 template <int L, typename T, int G, bool PIPE, class V>
-__device__ __forceinline__ void contract(const EriLaunch& a, int i, int k, int sub, T ACx, T ACy,
-                                         T ACz, V&& vrr) {
+__device__ __forceinline__ void contract(const EriLaunch& a, const BoysTab<T>& bt, int i, int k,
+                                         int sub, T ACx, T ACy, T ACz, V&& vrr) {
   const int nk = a.ket.n;
   const int nppb = a.bra.npp, nppk = a.ket.npp;
   if constexpr (G == 1) {
     (void)sub;
-    const CDouble bt = (CDouble)(a.bra.primT) + static_cast<size_t>(i) * nppb * kPrimFields;
+    const CDouble bra = (CDouble)(a.bra.primT) + static_cast<size_t>(i) * nppb * kPrimFields;
     for (int kl = 0; kl < nppk; ++kl) {
       const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
       const T q = T(kp[kP * nk]), oo2q = T(kp[kOo2p * nk]);
       const T QCx = T(kp[kPAx * nk]), QCy = T(kp[kPAy * nk]), QCz = T(kp[kPAz * nk]);
       const T Kcd = T(kp[kKt * nk]);
       auto geo = [&](int ij, PrimGeo<L, T>& g) {
-        const CDouble b = bt + ij * kPrimFields;
+        const CDouble b = bra + ij * kPrimFields;
         prim_geo<L, T>(T(b[kP]), T(b[kPAx]), T(b[kPAy]), T(b[kPAz]), q, QCx, QCy, QCz, ACx, ACy,
-                       ACz, a, g);
+                       ACz, bt, g);
       };
       auto finish = [&](int ij, const PrimGeo<L, T>& g) {
-        const CDouble b = bt + ij * kPrimFields;
+        const CDouble b = bra + ij * kPrimFields;
         T F[L + 1];
         VrrCoef<T> c;
         prim_finish<L, T>(g, T(b[kP]), T(b[kOo2p]), T(b[kPAx]), T(b[kPAy]), T(b[kPAz]),
-                          T(b[kKt]), q, oo2q, QCx, QCy, QCz, Kcd, a, F, c);
+                          T(b[kKt]), q, oo2q, QCx, QCy, QCz, Kcd, bt, F, c);
         vrr(F, c);
       };
       if constexpr (PIPE) {
@@ -421,22 +453,22 @@ __device__ __forceinline__ void contract(const EriLaunch& a, int i, int k, int s
       }
     }
   } else {
-    const double* bt = a.bra.primT + static_cast<size_t>(i) * nppb * kPrimFields;
+    const double* bra = a.bra.primT + static_cast<size_t>(i) * nppb * kPrimFields;
     const int npq = nppb * nppk;
     auto geo = [&](int kl, int ij, PrimGeo<L, T>& g) {
-      const double* b = bt + ij * kPrimFields;
+      const double* b = bra + ij * kPrimFields;
       const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
       prim_geo<L, T>(T(b[kP]), T(b[kPAx]), T(b[kPAy]), T(b[kPAz]), T(kp[kP * nk]),
-                     T(kp[kPAx * nk]), T(kp[kPAy * nk]), T(kp[kPAz * nk]), ACx, ACy, ACz, a, g);
+                     T(kp[kPAx * nk]), T(kp[kPAy * nk]), T(kp[kPAz * nk]), ACx, ACy, ACz, bt, g);
     };
     auto finish = [&](int kl, int ij, const PrimGeo<L, T>& g) {
-      const double* b = bt + ij * kPrimFields;
+      const double* b = bra + ij * kPrimFields;
       const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
       T F[L + 1];
       VrrCoef<T> c;
       prim_finish<L, T>(g, T(b[kP]), T(b[kOo2p]), T(b[kPAx]), T(b[kPAy]), T(b[kPAz]), T(b[kKt]),
                         T(kp[kP * nk]), T(kp[kOo2p * nk]), T(kp[kPAx * nk]), T(kp[kPAy * nk]),
-                        T(kp[kPAz * nk]), T(kp[kKt * nk]), a, F, c);
+                        T(kp[kPAz * nk]), T(kp[kKt * nk]), bt, F, c);
       vrr(F, c);
     };
     auto step = [&](int& kl, int& ij) {
@@ -548,16 +580,15 @@ __device__ __forceinline__ void atomic_add(double* addr, double v) {
   unsafeAtomicAdd(addr, v);
 }
 
-// Integral + digestion kernel of one class and precision.  One wavefront per
-// work item: the bra pair is uniform across the wave (scalar data), each lane
-// takes one ket pair of the current 64-wide chunk of the item's ket range.
+// Integral + digestion of one work item {bra pair, ket range} of one class and
+// precision by one wavefront: the bra pair is uniform across the wave (scalar
+// data), each lane (each group of G lanes) takes one ket pair of the current
+// chunk of the item's ket range.
 template <class C, typename T, int G>
-__global__ __launch_bounds__(kBlock) void eri_jk_kernel(const EriLaunch a) {
+__device__ __forceinline__ void eri_item(const EriLaunch& a, const BoysTab<T>& bt, int item) {
   constexpr int QPW = kWave / G;
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (G - 1), ql = lane / G;
-  const int item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (item >= a.nitems) return;
   const int4 w = a.items[item];
   const int i = __builtin_amdgcn_readfirstlane(w.x);
   const int kbeg = __builtin_amdgcn_readfirstlane(w.y);
@@ -579,7 +610,7 @@ __global__ __launch_bounds__(kBlock) void eri_jk_kernel(const EriLaunch a) {
     T acc[C::NACC];
 #pragma unroll
     for (int t = 0; t < C::NACC; ++t) acc[t] = T(0);
-    contract<C::L, T, G, kPipelined<C>>(a, i, k, sub, ACx, ACy, ACz,
+    contract<C::L, T, G, kPipelined<C>>(a, bt, i, k, sub, ACx, ACy, ACz,
                          [&](const T* F, const VrrCoef<T>& c) { C::template vrr<T>(F, c, acc); });
     group_sum_all<G>(acc);
 
@@ -660,6 +691,48 @@ __global__ __launch_bounds__(kBlock) void eri_jk_kernel(const EriLaunch a) {
   }
 }
 
+template <class C, typename T, int G>
+__global__ __launch_bounds__(kBlock) void eri_jk_kernel(const EriLaunch a) {
+  const int item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (item >= a.nitems) return;
+  eri_item<C, T, G>(a, global_boys<C::L, T>(a), item);
+}
+
+// Light classes (L <= 3, one lane per quartet): the Boys-table gathers, one
+// 64-byte row per primitive quartet and lane, would otherwise saturate the
+// vector-memory path.  Each workgroup of NT threads stages the rows of its
+// order in LDS once (FP64: T < 45, beyond which the asymptotic form is exact to
+// 2e-16 relative for orders <= 3; FP32: the whole FP32 table) and its
+// wavefronts then loop over work items.  NT = 1024 where the class fits in 128
+// VGPRs, else 512 (256 VGPRs).
+constexpr int kLdsMaxL = 3;
+constexpr double kLdsTmax = 45.0;
+constexpr int kLdsRows64 = 901;   // T_i = 0.05 i <= 45
+constexpr int kLdsMaxBlocks = 512;
+
+template <class C, typename T, int NT>
+__global__ __launch_bounds__(NT) void eri_jk_lds_kernel(const EriLaunch a) {
+  static_assert(C::L <= kLdsMaxL, "LDS Boys table: orders <= 3");
+  constexpr int W = NT / kWave;
+  const BoysTab<T> g = global_boys<C::L, T>(a);
+  BoysTab<T> bt = g;
+  if constexpr (sizeof(T) == 8) {
+    __shared__ double2 rows[kLdsRows64 * kBoysRow / 2];
+    const double2* src = reinterpret_cast<const double2*>(g.rows);
+    for (int t = threadIdx.x; t < kLdsRows64 * kBoysRow / 2; t += NT) rows[t] = src[t];
+    bt.rows = reinterpret_cast<const double*>(rows);
+    bt.tmax = kLdsTmax;
+  } else {
+    __shared__ float4 rows[kBoys32Rows * kBoys32Row / 4];
+    const float4* src = reinterpret_cast<const float4*>(g.rows);
+    for (int t = threadIdx.x; t < kBoys32Rows * kBoys32Row / 4; t += NT) rows[t] = src[t];
+    bt.rows = reinterpret_cast<const float*>(rows);
+  }
+  __syncthreads();
+  for (int item = blockIdx.x * W + (threadIdx.x >> 6); item < a.nitems; item += gridDim.x * W)
+    eri_item<C, T, 1>(a, bt, item);
+}
+
 // Cauchy-Schwarz factor of every pair of a bin: Q = sqrt(max_ab (ab|ab)).
 // One lane per pair; bra and ket are the same pair, so A - C = 0.
 template <class C>
@@ -674,7 +747,7 @@ __global__ __launch_bounds__(kBlock) void schwarz_kernel(const EriLaunch a, doub
   double acc[C::NACC];
 #pragma unroll
   for (int s = 0; s < C::NACC; ++s) acc[s] = 0.0;
-  contract<C::L, double, G, false>(a, t, t, sub, 0.0, 0.0, 0.0,
+  contract<C::L, double, G, false>(a, global_boys<C::L, double>(a), t, t, sub, 0.0, 0.0, 0.0,
                             [&](const double* F, const VrrCoef<double>& c) {
                               C::template vrr<double>(F, c, acc);
                             });
@@ -696,7 +769,8 @@ __device__ __forceinline__ void split_passes(const EriLaunch& a, int i, int k, i
   T acc[C::NE * NFJ];
 #pragma unroll
   for (int t = 0; t < C::NE * NFJ; ++t) acc[t] = T(0);
-  contract<C::L, T, G, kPipelined<C>>(a, i, k, sub, ACx, ACy, ACz, [&](const T* F, const VrrCoef<T>& c) {
+  contract<C::L, T, G, kPipelined<C>>(a, global_boys<C::L, T>(a), i, k, sub, ACx, ACy, ACz,
+                                      [&](const T* F, const VrrCoef<T>& c) {
     C::template vrr_pass<J, T>(F, c, acc);
   });
   group_sum_all<G>(acc);
