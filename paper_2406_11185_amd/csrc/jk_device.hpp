@@ -580,12 +580,85 @@ __device__ __forceinline__ void atomic_add(double* addr, double v) {
   unsafeAtomicAdd(addr, v);
 }
 
+// Scatter of per-quartet integral blocks into J or K with few memory-side
+// atomic requests.  FP64 atomic adds are executed past the L2, one request per
+// 64-byte line and wavefront instruction, whatever the number of lanes that hit
+// the line.  A block of NX x NY values per quartet (row-major, rows rx + x,
+// columns cy + y of an n x n matrix) is therefore staged in LDS and re-read so
+// that groups of P lanes add the S contiguous elements of one row segment
+// together.  When NX > NY the block goes in transposed (rows cy + y, columns
+// rx + x): the build returns M + M^T, so either orientation gives the same
+// result.  Q quartets per wavefront; `writer` marks the lane that holds a
+// quartet's block (the first lane of its group), slot = lane / (64 / Q).
+template <int NX, int NY, int Q>
+struct Scatter {
+  static constexpr bool TR = NX > NY;
+  static constexpr int S = TR ? NX : NY;   // contiguous segment
+  static constexpr int R = TR ? NY : NX;   // segments per quartet
+  static constexpr int P = S <= 1 ? 1 : S <= 2 ? 2 : S <= 4 ? 4 : 8;
+  static constexpr int GW = kWave / P;     // segments per round
+  static constexpr int STAGE = S > 1 ? Q * (S + 1) : 0;   // doubles of LDS per wavefront
+};
+
+template <int NX, int NY, int Q>
+__device__ __forceinline__ void scatter_block(double* M, size_t n, int rx, int cy,
+                                              const double* blk, bool writer, double* stage) {
+  using Sc = Scatter<NX, NY, Q>;
+  if constexpr (Sc::S == 1) {
+    if (writer && blk[0] != 0.0) atomic_add(&M[static_cast<size_t>(rx) * n + cy], blk[0]);
+  } else {
+    constexpr int S = Sc::S, R = Sc::R, P = Sc::P, GW = Sc::GW;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int slot = lane / (kWave / Q);
+    const int g = lane / P, e = lane % P;
+    double* vals = stage;             // [Q][S] one segment per quartet
+    double* base = stage + Q * S;     // [Q] its first element, as a bit pattern
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (writer) {
+        const long long b = Sc::TR ? static_cast<long long>(cy + r) * static_cast<long long>(n) + rx
+                                   : static_cast<long long>(rx + r) * static_cast<long long>(n) + cy;
+        base[slot] = __builtin_bit_cast(double, b);
+#pragma unroll
+        for (int x = 0; x < S; ++x) vals[slot * S + x] = Sc::TR ? blk[x * NY + r] : blk[r * NY + x];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int q0 = 0; q0 < Q; q0 += GW) {
+        const int q = q0 + g;
+        if (e < S && q < Q) {
+          const double v = vals[q * S + e];
+          if (v != 0.0) atomic_add(&M[__builtin_bit_cast(long long, base[q]) + e], v);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+}
+
+// LDS staging doubles per wavefront for the scatters of class C with Q quartets
+// per wavefront.
+template <class C, int Q>
+constexpr int stage_doubles() {
+  int m = Scatter<C::NC, C::ND, Q>::STAGE;
+  m = m > Scatter<C::NA, C::NC, Q>::STAGE ? m : Scatter<C::NA, C::NC, Q>::STAGE;
+  m = m > Scatter<C::NA, C::ND, Q>::STAGE ? m : Scatter<C::NA, C::ND, Q>::STAGE;
+  m = m > Scatter<C::NB, C::NC, Q>::STAGE ? m : Scatter<C::NB, C::NC, Q>::STAGE;
+  m = m > Scatter<C::NB, C::ND, Q>::STAGE ? m : Scatter<C::NB, C::ND, Q>::STAGE;
+  return m > 0 ? m : 1;
+}
+
 // Integral + digestion of one work item {bra pair, ket range} of one class and
 // precision by one wavefront: the bra pair is uniform across the wave (scalar
 // data), each lane (each group of G lanes) takes one ket pair of the current
 // chunk of the item's ket range.
 template <class C, typename T, int G>
-__device__ __forceinline__ void eri_item(const EriLaunch& a, const BoysTab<T>& bt, int item) {
+__device__ __forceinline__ void eri_item(const EriLaunch& a, const BoysTab<T>& bt, int item,
+                                         double* stage) {
   constexpr int QPW = kWave / G;
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (G - 1), ql = lane / G;
@@ -670,32 +743,27 @@ __device__ __forceinline__ void eri_item(const EriLaunch& a, const BoysTab<T>& b
         if (lane == kWaveSumLane)
           atomic_add(&Jm[(a0 + t / C::NB) * static_cast<size_t>(a.n) + b0 + t % C::NB], 2.0 * s);
       }
-      if (active) {
 #pragma unroll
-        for (int t = 0; t < C::NC * C::ND; ++t)
-          atomic_add(&Jm[(c0 + t / C::ND) * static_cast<size_t>(a.n) + d0 + t % C::ND], 2.0 * jcd[t]);
-#pragma unroll
-        for (int t = 0; t < C::NA * C::NC; ++t)
-          atomic_add(&Km[(a0 + t / C::NC) * static_cast<size_t>(a.n) + c0 + t % C::NC], kac[t]);
-#pragma unroll
-        for (int t = 0; t < C::NA * C::ND; ++t)
-          atomic_add(&Km[(a0 + t / C::ND) * static_cast<size_t>(a.n) + d0 + t % C::ND], kad[t]);
-#pragma unroll
-        for (int t = 0; t < C::NB * C::NC; ++t)
-          atomic_add(&Km[(b0 + t / C::NC) * static_cast<size_t>(a.n) + c0 + t % C::NC], kbc[t]);
-#pragma unroll
-        for (int t = 0; t < C::NB * C::ND; ++t)
-          atomic_add(&Km[(b0 + t / C::ND) * static_cast<size_t>(a.n) + d0 + t % C::ND], kbd[t]);
-      }
+      for (int t = 0; t < C::NC * C::ND; ++t) jcd[t] *= 2.0;
+      const size_t n = static_cast<size_t>(a.n);
+      // every quartet slot is written (out-of-range ones hold zeros, fq = 0)
+      const bool writer = sub == 0;
+      scatter_block<C::NC, C::ND, QPW>(Jm, n, c0, d0, jcd, writer, stage);
+      scatter_block<C::NA, C::NC, QPW>(Km, n, a0, c0, kac, writer, stage);
+      scatter_block<C::NA, C::ND, QPW>(Km, n, a0, d0, kad, writer, stage);
+      scatter_block<C::NB, C::NC, QPW>(Km, n, b0, c0, kbc, writer, stage);
+      scatter_block<C::NB, C::ND, QPW>(Km, n, b0, d0, kbd, writer, stage);
     }
   }
 }
 
 template <class C, typename T, int G>
 __global__ __launch_bounds__(kBlock) void eri_jk_kernel(const EriLaunch a) {
+  constexpr int ST = stage_doubles<C, kWave / G>();
+  __shared__ double stage[kWavesPerBlock * ST];
   const int item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (item >= a.nitems) return;
-  eri_item<C, T, G>(a, global_boys<C::L, T>(a), item);
+  eri_item<C, T, G>(a, global_boys<C::L, T>(a), item, stage + (threadIdx.x >> 6) * ST);
 }
 
 // Light classes (L <= 3, one lane per quartet): the Boys-table gathers, one
@@ -728,9 +796,11 @@ __global__ __launch_bounds__(NT) void eri_jk_lds_kernel(const EriLaunch a) {
     for (int t = threadIdx.x; t < kBoys32Rows * kBoys32Row / 4; t += NT) rows[t] = src[t];
     bt.rows = reinterpret_cast<const float*>(rows);
   }
+  constexpr int ST = stage_doubles<C, kWave>();
+  __shared__ double stage[W * ST];
   __syncthreads();
   for (int item = blockIdx.x * W + (threadIdx.x >> 6); item < a.nitems; item += gridDim.x * W)
-    eri_item<C, T, 1>(a, bt, item);
+    eri_item<C, T, 1>(a, bt, item, stage + (threadIdx.x >> 6) * ST);
 }
 
 // Cauchy-Schwarz factor of every pair of a bin: Q = sqrt(max_ab (ab|ab)).
