@@ -631,7 +631,7 @@ def table(infos):
         nc = (i["lc"] + 1) * (i["lc"] + 2) // 2
         nd = (i["ld"] + 1) * (i["ld"] + 2) // 2
         ne = i["nacc"] // i["nf"]
-        return 64 * ((i["nacc"] + ne * ncd) * tb + (na * nc + na * nd + nb * nc + nb * nd) * 8)
+        return 64 * ((i["nacc"] + ne * ncd) * tb + (na * nc + na * nd + nb * nc + nb * nd + ncd) * 8)
     t.append("// bytes of workspace per wavefront of the multi-pass classes (0: none)")
     t.append("size_t split_ws_bytes(int cls, int fp32) {")
     t.append("  static const size_t w64[21] = {" + ", ".join(str(wsb(i, 8)) for i in infos) + "};")

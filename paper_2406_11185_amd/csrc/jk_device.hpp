@@ -652,6 +652,38 @@ constexpr int stage_doubles() {
   return m > 0 ? m : 1;
 }
 
+// The same scatter for blocks already parked in a wavefront workspace: element
+// t of quartet slot q at w0[t * Q + q] (written by the slot's first lane).  rx
+// and cy are read from the slot's first lane; all lanes take part.
+template <int NX, int NY, int Q>
+__device__ __forceinline__ void scatter_ws(double* M, size_t n, int rx, int cy, const double* w0) {
+  using Sc = Scatter<NX, NY, Q>;
+  constexpr int S = Sc::S, R = Sc::R, P = Sc::P, GW = Sc::GW;
+  constexpr int G = kWave / Q;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g = lane / P, e = lane % P;
+  // the slots' values were stored by other lanes of this wavefront
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma nounroll
+  for (int q0 = 0; q0 < Q; q0 += GW) {
+    const int q = q0 + g < Q ? q0 + g : Q - 1;
+    const int src = q * G;
+    const int rxq = __shfl(rx, src, kWave), cyq = __shfl(cy, src, kWave);
+    if (e < S && q0 + g < Q) {
+#pragma nounroll
+      for (int r = 0; r < R; ++r) {
+        const int t = Sc::TR ? e * NY + r : r * NY + e;
+        const double v = w0[t * Q + q];
+        const size_t at = Sc::TR ? static_cast<size_t>(cyq + r) * n + rxq + e
+                                 : static_cast<size_t>(rxq + r) * n + cyq + e;
+        if (v != 0.0) atomic_add(&M[at], v);
+      }
+    }
+  }
+}
+
 // Integral + digestion of one work item {bra pair, ket range} of one class and
 // precision by one wavefront: the bra pair is uniform across the wave (scalar
 // data), each lane (each group of G lanes) takes one ket pair of the current
@@ -879,18 +911,21 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
   // workspace of this wave: T values (contracted [e0|f0], ket-transformed X),
   // then FP64 exchange accumulators; one slot per quartet of the wave step
   constexpr int NT = C::NACC + C::NE * NCD;
-  constexpr int NK = C::NA * C::NC + C::NA * C::ND + C::NB * C::NC + C::NB * C::ND;
+  constexpr int NK = C::NA * C::NC + C::NA * C::ND + C::NB * C::NC + C::NB * C::ND + NCD;
   using AT = LaneArr<T, QPW>;
   using AD = LaneArr<double, QPW>;
   char* wbase = static_cast<char*>(a.ws) +
                 static_cast<size_t>(wave) * QPW * (NT * sizeof(T) + NK * sizeof(double));
   const AT cacc{reinterpret_cast<T*>(wbase) + ql};
   const AT X{cacc.p + static_cast<size_t>(C::NACC) * QPW};
-  double* kbase = reinterpret_cast<double*>(wbase + static_cast<size_t>(QPW) * NT * sizeof(T)) + ql;
-  const AD kac{kbase};
-  const AD kad{kac.p + static_cast<size_t>(C::NA * C::NC) * QPW};
-  const AD kbc{kad.p + static_cast<size_t>(C::NA * C::ND) * QPW};
-  const AD kbd{kbc.p + static_cast<size_t>(C::NB * C::NC) * QPW};
+  // FP64 J_cd and K blocks of the quartet slots, scattered after the digestion
+  double* const kw0 = reinterpret_cast<double*>(wbase + static_cast<size_t>(QPW) * NT * sizeof(T));
+  double* const kac0 = kw0;
+  double* const kad0 = kac0 + C::NA * C::NC * QPW;
+  double* const kbc0 = kad0 + C::NA * C::ND * QPW;
+  double* const kbd0 = kbc0 + C::NB * C::NC * QPW;
+  double* const jcd0 = kbd0 + C::NB * C::ND * QPW;
+  const AD kac{kac0 + ql}, kad{kad0 + ql}, kbc{kbc0 + ql}, kbd{kbd0 + ql}, jcdw{jcd0 + ql};
   const int z = 0;
   const int nb = a.bra.n, nk = a.ket.n;
   const size_t n = static_cast<size_t>(a.n);
@@ -978,7 +1013,7 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
             tbc[y] += Dad[x] * v;
             tbd[y] += Dac[x] * v;
           }
-        if (active) atomic_add(&Jm[(c0 + c) * n + d0 + d], 2.0 * jcd);
+        jcdw[z + cd] = 2.0 * jcd;
 #pragma unroll
         for (int x = 0; x < C::NA; ++x) {
           kac[z + x * C::NC + c] += tac[x];
@@ -995,20 +1030,12 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
         const double s = wave_sum(jab[t]);
         if (lane == kWaveSumLane) atomic_add(&Jm[(a0 + t / C::NB) * n + b0 + t % C::NB], 2.0 * s);
       }
-      if (active) {
-#pragma unroll
-        for (int t = 0; t < C::NA * C::NC; ++t)
-          atomic_add(&Km[(a0 + t / C::NC) * n + c0 + t % C::NC], kac[z + t]);
-#pragma unroll
-        for (int t = 0; t < C::NA * C::ND; ++t)
-          atomic_add(&Km[(a0 + t / C::ND) * n + d0 + t % C::ND], kad[z + t]);
-#pragma unroll
-        for (int t = 0; t < C::NB * C::NC; ++t)
-          atomic_add(&Km[(b0 + t / C::NC) * n + c0 + t % C::NC], kbc[z + t]);
-#pragma unroll
-        for (int t = 0; t < C::NB * C::ND; ++t)
-          atomic_add(&Km[(b0 + t / C::ND) * n + d0 + t % C::ND], kbd[z + t]);
-      }
+      // out-of-range slots hold zeros (fq = 0)
+      scatter_ws<C::NC, C::ND, QPW>(Jm, n, c0, d0, jcd0);
+      scatter_ws<C::NA, C::NC, QPW>(Km, n, a0, c0, kac0);
+      scatter_ws<C::NA, C::ND, QPW>(Km, n, a0, d0, kad0);
+      scatter_ws<C::NB, C::NC, QPW>(Km, n, b0, c0, kbc0);
+      scatter_ws<C::NB, C::ND, QPW>(Km, n, b0, d0, kbd0);
     }
   }
   }
