@@ -572,9 +572,16 @@ def wrapper(info):
          "namespace jk {",
          f'#include "cls_{n}.inc"',
          f"void launch_eri_{n}(const EriLaunch& a, int fp32, hipStream_t s) {{",
-         *([f"  // Boys rows staged in LDS; the workgroups loop over the items",
+         *([f"  // Boys rows staged in LDS; as many workgroups as fit on the device claim the items",
             f"  constexpr int NT = {info.get('lds_block', 0)};",
-            f"  const dim3 lgrid(std::min((a.nitems + NT / kWave - 1) / (NT / kWave), kLdsMaxBlocks));",
+            f"  static int per_cu[2] = {{0, 0}};",
+            f"  if (!per_cu[fp32]) {{",
+            f"    int nb = 0;",
+            f"    if (fp32) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&eri_jk_lds_kernel<Cls_{n}, float, NT>), NT, 0);",
+            f"    else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&eri_jk_lds_kernel<Cls_{n}, double, NT>), NT, 0);",
+            f"    per_cu[fp32] = nb > 0 ? nb : 1;",
+            f"  }}",
+            f"  const dim3 lgrid(std::min((a.nitems + NT / kWave - 1) / (NT / kWave), per_cu[fp32] * a.num_cu));",
             f"  if (fp32) hipLaunchKernelGGL((eri_jk_lds_kernel<Cls_{n}, float, NT>), lgrid, dim3(NT), 0, s, a);",
             f"  else hipLaunchKernelGGL((eri_jk_lds_kernel<Cls_{n}, double, NT>), lgrid, dim3(NT), 0, s, a);",
             "}"] if info.get("lds") else []),

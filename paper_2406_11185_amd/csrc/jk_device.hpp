@@ -72,9 +72,18 @@ struct EriLaunch {
   const float* boys32;
   float boys_fp64_T;  // FP32 kernels: F_m in FP64 above this T
   void* ws;           // multi-pass classes: per-wave workspace (see split_ws_bytes)
-  int nwaves;         // multi-pass classes: wavefronts of the launch (item loop stride)
+  int nwaves;         // multi-pass classes: wavefronts of the launch
   int lanes;          // lanes sharing one shell quartet in this launch (1 or the class maximum)
+  int* next;          // persistent kernels: next unclaimed work item (zero before the launch)
+  int num_cu;         // compute units of the device (grid of the persistent kernels)
 };
+
+// Persistent kernels: each wavefront claims work items one at a time.
+__device__ __forceinline__ int claim_item(int* next) {
+  int item = 0;
+  if ((threadIdx.x & (kWave - 1)) == 0) item = atomicAdd(next, 1);
+  return __builtin_amdgcn_readfirstlane(item);
+}
 
 // Per-quartet array in a launch workspace.  The QPW quartets of a wavefront
 // are interleaved (stride QPW), so the lanes that carry them touch consecutive
@@ -803,12 +812,11 @@ __global__ __launch_bounds__(kBlock) void eri_jk_kernel(const EriLaunch a) {
 // vector-memory path.  Each workgroup of NT threads stages the rows of its
 // order in LDS once (FP64: T < 45, beyond which the asymptotic form is exact to
 // 2e-16 relative for orders <= 3; FP32: the whole FP32 table) and its
-// wavefronts then loop over work items.  NT = 1024 where the class fits in 128
-// VGPRs, else 512 (256 VGPRs).
+// wavefronts then claim work items until none is left.  NT = 1024 where the
+// class fits in 128 VGPRs, else 512 (256 VGPRs).
 constexpr int kLdsMaxL = 3;
 constexpr double kLdsTmax = 45.0;
 constexpr int kLdsRows64 = 901;   // T_i = 0.05 i <= 45
-constexpr int kLdsMaxBlocks = 512;
 
 template <class C, typename T, int NT>
 __global__ __launch_bounds__(NT) void eri_jk_lds_kernel(const EriLaunch a) {
@@ -831,7 +839,8 @@ __global__ __launch_bounds__(NT) void eri_jk_lds_kernel(const EriLaunch a) {
   constexpr int ST = stage_doubles<C, kWave>();
   __shared__ double stage[W * ST];
   __syncthreads();
-  for (int item = blockIdx.x * W + (threadIdx.x >> 6); item < a.nitems; item += gridDim.x * W)
+  (void)W;
+  for (int item = claim_item(a.next); item < a.nitems; item = claim_item(a.next))
     eri_item<C, T, 1>(a, bt, item, stage + (threadIdx.x >> 6) * ST);
 }
 
@@ -930,7 +939,7 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
   const int nb = a.bra.n, nk = a.ket.n;
   const size_t n = static_cast<size_t>(a.n);
   const size_t nn = n * n;
-  for (int item = wave; item < a.nitems; item += a.nwaves) {
+  for (int item = claim_item(a.next); item < a.nitems; item = claim_item(a.next)) {
   const int4 w = a.items[item];
   const int i = __builtin_amdgcn_readfirstlane(w.x);
   const int kbeg = __builtin_amdgcn_readfirstlane(w.y);

@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
   const AT XU{XC.p + static_cast<size_t>(C::NE_C) * C::NCP * QPW};
   const AT XV{XU.p + static_cast<size_t>(C::NE_U) * NCD * QPW};
   const int z = 0;
-  for (int item = wave; item < a.nitems; item += g.nwaves) {
+  for (int item = claim_item(a.next); item < a.nitems; item = claim_item(a.next)) {
   const int4 w = a.items[item];
   const int i = __builtin_amdgcn_readfirstlane(w.x);
   const int kbeg = __builtin_amdgcn_readfirstlane(w.y);

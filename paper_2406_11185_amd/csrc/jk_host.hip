@@ -333,13 +333,14 @@ enum Slot {
   sShellXyz, sShellI, sExps, sCoefs, sPairS, sBinOff, sBinNpp, sBinPrim, sPrimTmp, sPrim, sPrimTmpT, sPrimT,
   sA, sAB, sBf, sAtoms, sFpair, sAtmp, sABtmp, sBftmp, sAtomstmp, sFpairtmp, sQtmp, sQ,
   sIdx, sIdxSorted, sPerm, sBp, sCnt, sOff, sRng, sQstat, sSeg, sItems, sCub, sChunk, sWs0, sWs1,
-  sWs2, sWs3, sWsSchwarz, sNumSlots
+  sWs2, sWs3, sWsSchwarz, sNext, sNumSlots
 };
 
 }  // namespace
 
 struct jk_ctx {
   int device = 0;
+  int num_cu = 0;
   std::string err;
   DevBuf buf[sNumSlots];
   size_t scratch_limit = 0;
@@ -750,6 +751,7 @@ EriLaunch launch_args(jk_ctx* c, const Plan& P, const Setup& S, int X, int Y, in
   a.boys64 = c->boys64;
   a.boys32 = c->boys32;
   a.boys_fp64_T = static_cast<float>(o.boys_fp64_T);
+  a.num_cu = c->num_cu;
   return a;
 }
 
@@ -795,6 +797,11 @@ void dispatch(jk_ctx* c, const Plan& P, const Setup& S, hipStream_t s, jk_stats&
     where[q] = k;
   }
   prepare(recs, where);
+  // work-item counters of the persistent kernels, one per launch
+  int* next = dev<int>(c, sNext, std::max<size_t>(recs.size(), 1));
+  hipLaunchKernelGGL(fill_kernel<int>, dim3(grid_of(std::max<size_t>(recs.size(), 1), 256)),
+                     dim3(256), 0, s, recs.size(), next);
+  HIP_OK(hipGetLastError());
   HIP_OK(hipEventRecord(c->fork_ev, s));
   for (int k = 0; k < jk_ctx::kStreams; ++k) HIP_OK(hipStreamWaitEvent(c->streams[k], c->fork_ev, 0));
   for (size_t q = 0; q < recs.size(); ++q) {
@@ -803,7 +810,7 @@ void dispatch(jk_ctx* c, const Plan& P, const Setup& S, hipStream_t s, jk_stats&
     hipStream_t ls = c->streams[k];
     size_t e0 = 0;
     if (c->timed) e0 = event(c, ls);
-    launch_one(r, ls, k);
+    launch_one(r, ls, k, next + q);
     HIP_OK(hipGetLastError());
     if (c->timed) {
       event(c, ls);
@@ -861,6 +868,8 @@ int jk_ctx_create(jk_ctx** out, int device) {
     std::vector<double> t64;
     std::vector<float> t32;
     make_boys_tables(t64, t32);
+    HIP_OK(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device));
+    if (c->num_cu < 1) c->num_cu = 1;
     HIP_OK(hipMalloc(&c->boys64, t64.size() * sizeof(double)));
     HIP_OK(hipMalloc(&c->boys32, t32.size() * sizeof(float)));
     HIP_OK(hipMemcpy(c->boys64, t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -937,9 +946,10 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
     void* ws[jk_ctx::kStreams] = {};
     dispatch(
         c, P, S, s, st, false,
-        [&](const LaunchRec& r, hipStream_t ls, int k) {
+        [&](const LaunchRec& r, hipStream_t ls, int k, int* next) {
           EriLaunch a = launch_args(c, P, S, r.X, r.Y, r.i0, r.i1, D, J, K, nbf, o);
           a.lanes = r.lanes;
+          a.next = next;
           a.ws = ws[k];
           a.nwaves = waves_of(r).first;
           launch_eri(r.cls, r.pr, a, ls);
@@ -1002,10 +1012,11 @@ int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, dou
     void* ws[jk_ctx::kStreams] = {};
     dispatch(
         c, P, S, s, st, true,
-        [&](const LaunchRec& r, hipStream_t ls, int k) {
+        [&](const LaunchRec& r, hipStream_t ls, int k, int* next) {
           GradLaunch g{};
           g.e = launch_args(c, P, S, r.X, r.Y, r.i0, r.i1, D, nullptr, nullptr, nbf, o);
           g.e.lanes = r.lanes;
+          g.e.next = next;
           g.dEdR = dEdR;
           g.n_atoms = basis->n_atoms;
           g.ws = ws[k];
