@@ -64,8 +64,10 @@ struct EriLaunch {
   int nitems;
   int same_bin;       // bra and ket bins coincide (then ket == bra is a self-pair quartet)
   const double* D;
-  double* J;
+  double* J;           // accumulators A_J, A_K (the build returns A + A^T)
   double* K;
+  int ncopy;           // independent accumulator copies (item % ncopy), spreading the
+  size_t copy_stride;  // atomic traffic of small matrices over more lines; elements apart
   int n;              // basis functions
   int n_dm;
   const double* boys64;
@@ -776,8 +778,8 @@ __device__ __forceinline__ void eri_item(const EriLaunch& a, const BoysTab<T>& b
       C::template hrr_digest<T>(acc, ABx, ABy, ABz, CDx, CDy, CDz, fq, Dab, Dcd, Dac, Dad, Dbc,
                                 Dbd, jab, jcd, kac, kad, kbc, kbd);
 
-      double* Jm = a.J + m * nn;
-      double* Km = a.K + m * nn;
+      double* Jm = a.J + (item % a.ncopy) * a.copy_stride + m * nn;
+      double* Km = a.K + (item % a.ncopy) * a.copy_stride + m * nn;
 #pragma unroll
       for (int t = 0; t < C::NA * C::NB; ++t) {
         const double s = wave_sum(jab[t]);
@@ -964,8 +966,8 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
 
     for (int m = 0; m < a.n_dm; ++m) {
       const double* Dm = a.D + m * nn;
-      double* Jm = a.J + m * nn;
-      double* Km = a.K + m * nn;
+      double* Jm = a.J + (item % a.ncopy) * a.copy_stride + m * nn;
+      double* Km = a.K + (item % a.ncopy) * a.copy_stride + m * nn;
       double Dab[C::NA * C::NB], jab[C::NA * C::NB];
 #pragma unroll
       for (int x = 0; x < C::NA; ++x)

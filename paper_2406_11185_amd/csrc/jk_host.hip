@@ -297,6 +297,31 @@ __global__ void fill_kernel(size_t n, T* a) {
   if (i < n) a[i] = T(0);
 }
 
+// J = sum over the accumulator copies of A + A^T (one thread per upper-triangle
+// element and density); the copies are [ncopy][n_dm][n][n].
+__global__ void finalize_copies_kernel(int n, int n_dm, int ncopy, const double* AJ,
+                                       const double* AK, double* J, double* K) {
+  const size_t nn = static_cast<size_t>(n) * n;
+  const size_t id = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= nn * n_dm) return;
+  const int m = static_cast<int>(id / nn);
+  const size_t r = id % nn;
+  const int i = static_cast<int>(r / n), j = static_cast<int>(r % n);
+  if (j < i) return;
+  const size_t ij = m * nn + static_cast<size_t>(i) * n + j;
+  const size_t ji = m * nn + static_cast<size_t>(j) * n + i;
+  const size_t stride = nn * n_dm;
+  double sj = 0.0, sk = 0.0;
+  for (int c = 0; c < ncopy; ++c) {
+    sj += AJ[c * stride + ij] + AJ[c * stride + ji];
+    sk += AK[c * stride + ij] + AK[c * stride + ji];
+  }
+  J[ij] = sj;
+  J[ji] = sj;
+  K[ij] = sk;
+  K[ji] = sk;
+}
+
 // J = A + A^T in place, per density (one thread per upper-triangle element).
 __global__ void finalize_kernel(int n, int n_dm, double* J, double* K) {
   const size_t nn = static_cast<size_t>(n) * n;
@@ -321,6 +346,8 @@ inline unsigned grid_of(size_t n, int block) { return static_cast<unsigned>((n +
 // Upper bound of the workspace one launch of a multi-pass or gradient kernel
 // uses; the launch then loops over its items with correspondingly few waves.
 constexpr size_t kWsBudget = size_t(1) << 30;
+constexpr size_t kMaxCopies = 8;                  // accumulator copies of J and K
+constexpr size_t kAccBudget = size_t(256) << 20;   // bytes for them
 
 // ---------------------------------------------------------------------------------
 // Grow-only device buffers owned by a context.
@@ -333,7 +360,7 @@ enum Slot {
   sShellXyz, sShellI, sExps, sCoefs, sPairS, sBinOff, sBinNpp, sBinPrim, sPrimTmp, sPrim, sPrimTmpT, sPrimT,
   sA, sAB, sBf, sAtoms, sFpair, sAtmp, sABtmp, sBftmp, sAtomstmp, sFpairtmp, sQtmp, sQ,
   sIdx, sIdxSorted, sPerm, sBp, sCnt, sOff, sRng, sQstat, sSeg, sItems, sCub, sChunk, sWs0, sWs1,
-  sWs2, sWs3, sWsSchwarz, sNext, sNumSlots
+  sWs2, sWs3, sWsSchwarz, sNext, sAcc, sNumSlots
 };
 
 }  // namespace
@@ -746,6 +773,8 @@ EriLaunch launch_args(jk_ctx* c, const Plan& P, const Setup& S, int X, int Y, in
   a.D = D;
   a.J = J;
   a.K = K;
+  a.ncopy = 1;
+  a.copy_stride = 0;
   a.n = nbf;
   a.n_dm = o.n_dm;
   a.boys64 = c->boys64;
@@ -932,8 +961,25 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
     const Plan& P = S.P;
     if (c->timed) c->ev_setup1 = event(c, s);
     const size_t nn = static_cast<size_t>(nbf) * nbf;
-    hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(nn * o.n_dm, 256)), dim3(256), 0, s, nn * o.n_dm, J);
-    hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(nn * o.n_dm, 256)), dim3(256), 0, s, nn * o.n_dm, K);
+    const size_t mat = nn * o.n_dm;   // elements of J (and of K)
+    // Atomic adds to one 64-byte line serialise at the memory side, and a small
+    // J/K receives many adds per line: accumulate into up to kMaxCopies copies
+    // (item % ncopy) within kAccBudget bytes, then sum them in the finalize.
+    int ncopy = static_cast<int>(std::min<size_t>(kMaxCopies, kAccBudget / (2 * mat * sizeof(double))));
+    if (c->scratch_limit)
+      ncopy = std::min<int>(ncopy, static_cast<int>(c->scratch_limit / 4 / (2 * mat * sizeof(double))));
+    double* AJ = J;
+    double* AK = K;
+    if (ncopy > 1) {
+      AJ = dev<double>(c, sAcc, 2 * mat * ncopy);
+      AK = AJ + mat * ncopy;
+      hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(2 * mat * ncopy, 256)), dim3(256), 0, s,
+                         2 * mat * ncopy, AJ);
+    } else {
+      ncopy = 1;
+      hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(mat, 256)), dim3(256), 0, s, mat, J);
+      hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(mat, 256)), dim3(256), 0, s, mat, K);
+    }
     HIP_OK(hipGetLastError());
 
     jk_stats st = base_stats(P, S);
@@ -947,7 +993,9 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
     dispatch(
         c, P, S, s, st, false,
         [&](const LaunchRec& r, hipStream_t ls, int k, int* next) {
-          EriLaunch a = launch_args(c, P, S, r.X, r.Y, r.i0, r.i1, D, J, K, nbf, o);
+          EriLaunch a = launch_args(c, P, S, r.X, r.Y, r.i0, r.i1, D, AJ, AK, nbf, o);
+          a.ncopy = ncopy;
+          a.copy_stride = mat;
           a.lanes = r.lanes;
           a.next = next;
           a.ws = ws[k];
@@ -963,8 +1011,12 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
           for (int k = 0; k < jk_ctx::kStreams; ++k)
             if (need[k]) ws[k] = dev<char>(c, static_cast<Slot>(sWs0 + k), need[k]);
         });
-    hipLaunchKernelGGL(finalize_kernel, dim3(grid_of(nn * o.n_dm, 256)), dim3(256), 0, s, nbf,
-                       o.n_dm, J, K);
+    if (ncopy > 1)
+      hipLaunchKernelGGL(finalize_copies_kernel, dim3(grid_of(mat, 256)), dim3(256), 0, s, nbf,
+                         o.n_dm, ncopy, AJ, AK, J, K);
+    else
+      hipLaunchKernelGGL(finalize_kernel, dim3(grid_of(mat, 256)), dim3(256), 0, s, nbf, o.n_dm,
+                         J, K);
     HIP_OK(hipGetLastError());
     if (c->timed) c->ev_end = event(c, s);
     c->stats = st;
