@@ -630,21 +630,22 @@ def table(infos):
     t.append("  return grad ? g[cls] : e[cls];")
     t.append("}")
     def wsb(i, tb):
-        if not i["split"]:
-            return 0
         ncd = (i["lc"] + 1) * (i["lc"] + 2) // 2 * ((i["ld"] + 1) * (i["ld"] + 2) // 2)
         na = (i["la"] + 1) * (i["la"] + 2) // 2
         nb = (i["lb"] + 1) * (i["lb"] + 2) // 2
         nc = (i["lc"] + 1) * (i["lc"] + 2) // 2
         nd = (i["ld"] + 1) * (i["ld"] + 2) // 2
         ne = i["nacc"] // i["nf"]
-        return 64 * ((i["nacc"] + ne * ncd) * tb + (na * nc + na * nd + nb * nc + nb * nd + ncd) * 8)
-    t.append("// bytes of workspace per wavefront of the multi-pass classes (0: none)")
-    t.append("size_t split_ws_bytes(int cls, int fp32) {")
-    t.append("  static const size_t w64[21] = {" + ", ".join(str(wsb(i, 8)) for i in infos) + "};")
-    t.append("  static const size_t w32[21] = {" + ", ".join(str(wsb(i, 4)) for i in infos) + "};")
-    t.append("  if (cls < 0 || cls >= 21) return 0;")
-    t.append("  return fp32 ? w32[cls] : w64[cls];")
+        # per quartet slot: T values and the J_cd block; per lane: K partial blocks
+        return ((i["nacc"] + ne * ncd) * tb + ncd * 8), 64 * (na * nc + na * nd + nb * nc + nb * nd) * 8
+    t.append("// bytes of workspace per wavefront of the multi-pass classes with `lanes` lanes")
+    t.append("// per quartet (0: not a multi-pass class); the kernels use split_wave_bytes")
+    t.append("size_t split_ws_bytes(int cls, int fp32, int lanes) {")
+    t.append("  static const size_t s64[21] = {" + ", ".join(str(wsb(i, 8)[0]) if i["split"] else "0" for i in infos) + "};")
+    t.append("  static const size_t s32[21] = {" + ", ".join(str(wsb(i, 4)[0]) if i["split"] else "0" for i in infos) + "};")
+    t.append("  static const size_t k[21] = {" + ", ".join(str(wsb(i, 8)[1]) if i["split"] else "0" for i in infos) + "};")
+    t.append("  if (cls < 0 || cls >= 21 || lanes < 1 || !k[cls]) return 0;")
+    t.append("  return static_cast<size_t>(64 / lanes) * (fp32 ? s32[cls] : s64[cls]) + k[cls];")
     t.append("}")
     t.append("// bytes per wavefront of the multi-pass Schwarz kernel of a diagonal class (FP64)")
     t.append("size_t split_schwarz_ws_bytes(int cls) {")

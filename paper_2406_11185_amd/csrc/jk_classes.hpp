@@ -7,7 +7,7 @@ namespace jk {
 // class Y, index X(X+1)/2 + Y over pair classes ss, ps, pp, ds, dp, dd).
 void launch_eri(int cls, int fp32, const EriLaunch& a, hipStream_t s);
 // Workspace bytes per wavefront of the multi-pass classes (0 for the others).
-size_t split_ws_bytes(int cls, int fp32);
+size_t split_ws_bytes(int cls, int fp32, int lanes);
 size_t split_schwarz_ws_bytes(int cls);
 // Lanes that share one shell quartet in the class's kernel (the most it has),
 // and the set of lane counts compiled for it (bit g for g lanes).

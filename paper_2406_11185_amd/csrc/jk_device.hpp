@@ -663,20 +663,41 @@ constexpr int stage_doubles() {
   return m > 0 ? m : 1;
 }
 
-// The same scatter for blocks already parked in a wavefront workspace: element
-// t of quartet slot q at w0[t * Q + q] (written by the slot's first lane).  rx
-// and cy are read from the slot's first lane; all lanes take part.
-template <int NX, int NY, int Q>
+// Bytes of workspace per wavefront of a multi-pass class with G lanes per
+// quartet: contracted [e0|f0] and ket-transformed values (type T) and the J_cd
+// block per quartet slot, the K partial blocks per lane.  The host sizes the
+// workspace with the same expression (generated table).
+template <class C, typename T>
+__host__ __device__ constexpr size_t split_wave_bytes(int G) {
+  constexpr int NCD = C::NC * C::ND;
+  constexpr int NT = C::NACC + C::NE * NCD;
+  constexpr int NK = C::NA * C::NC + C::NA * C::ND + C::NB * C::NC + C::NB * C::ND;
+  return static_cast<size_t>(kWave / G) * (NT * sizeof(T) + NCD * sizeof(double)) +
+         static_cast<size_t>(kWave) * NK * sizeof(double);
+}
+
+// Workspace written by other lanes of the wavefront becomes visible to all.
+__device__ __forceinline__ void lanes_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// The same scatter for blocks parked in a wavefront workspace.  PARTS == 1:
+// element t of quartet slot q at w0[t * Q + q]; PARTS == 64 / Q: each lane
+// holds a partial block, element t of lane L at w0[t * 64 + L], and a slot's
+// value is the sum over its PARTS lanes.  rx and cy are read from the slot's
+// first lane; all lanes take part.
+template <int NX, int NY, int Q, int PARTS>
 __device__ __forceinline__ void scatter_ws(double* M, size_t n, int rx, int cy, const double* w0) {
   using Sc = Scatter<NX, NY, Q>;
   constexpr int S = Sc::S, R = Sc::R, P = Sc::P, GW = Sc::GW;
   constexpr int G = kWave / Q;
+  static_assert(PARTS == 1 || PARTS == G, "partial blocks: one per lane of the slot");
+  constexpr int STRIDE = PARTS == 1 ? Q : kWave;
   const int lane = threadIdx.x & (kWave - 1);
   const int g = lane / P, e = lane % P;
-  // the slots' values were stored by other lanes of this wavefront
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  lanes_sync();   // the blocks were stored by other lanes of this wavefront
 #pragma nounroll
   for (int q0 = 0; q0 < Q; q0 += GW) {
     const int q = q0 + g < Q ? q0 + g : Q - 1;
@@ -686,13 +707,16 @@ __device__ __forceinline__ void scatter_ws(double* M, size_t n, int rx, int cy, 
 #pragma nounroll
       for (int r = 0; r < R; ++r) {
         const int t = Sc::TR ? e * NY + r : r * NY + e;
-        const double v = w0[t * Q + q];
+        double v = 0.0;
+#pragma unroll
+        for (int u = 0; u < PARTS; ++u) v += w0[t * STRIDE + (PARTS == 1 ? q : q * G + u)];
         const size_t at = Sc::TR ? static_cast<size_t>(cyq + r) * n + rxq + e
                                  : static_cast<size_t>(rxq + r) * n + cyq + e;
         if (v != 0.0) atomic_add(&M[at], v);
       }
     }
   }
+  lanes_sync();   // the workspace is rewritten for the next quartets
 }
 
 // Integral + digestion of one work item {bra pair, ket range} of one class and
@@ -897,10 +921,11 @@ __device__ __forceinline__ void split_passes(const EriLaunch& a, int i, int k, i
 }
 
 template <class C, typename T, class A>
-__device__ __forceinline__ void split_ket_hrr(A cacc, A X, int z, T CDx, T CDy, T CDz) {
+__device__ __forceinline__ void split_ket_hrr(A cacc, A X, int z, T CDx, T CDy, T CDz, int e0,
+                                              int de) {
   constexpr int NCD = C::NC * C::ND;
 #pragma nounroll
-  for (int e = 0; e < C::NE; ++e) {
+  for (int e = e0; e < C::NE; e += de) {
     T f[C::NF];
 #pragma unroll
     for (int t = 0; t < C::NF; ++t) f[t] = cacc[z + e * C::NF + t];
@@ -922,21 +947,22 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
   // workspace of this wave: T values (contracted [e0|f0], ket-transformed X),
   // then FP64 exchange accumulators; one slot per quartet of the wave step
   constexpr int NT = C::NACC + C::NE * NCD;
-  constexpr int NK = C::NA * C::NC + C::NA * C::ND + C::NB * C::NC + C::NB * C::ND + NCD;
+  constexpr int NK = C::NA * C::NC + C::NA * C::ND + C::NB * C::NC + C::NB * C::ND;
   using AT = LaneArr<T, QPW>;
-  using AD = LaneArr<double, QPW>;
-  char* wbase = static_cast<char*>(a.ws) +
-                static_cast<size_t>(wave) * QPW * (NT * sizeof(T) + NK * sizeof(double));
+  using AD = LaneArr<double, kWave>;
+  char* wbase = static_cast<char*>(a.ws) + static_cast<size_t>(wave) * split_wave_bytes<C, T>(G);
   const AT cacc{reinterpret_cast<T*>(wbase) + ql};
   const AT X{cacc.p + static_cast<size_t>(C::NACC) * QPW};
-  // FP64 J_cd and K blocks of the quartet slots, scattered after the digestion
+  // FP64 K partial blocks of every lane (the G lanes of a quartet split its
+  // (c, d) loop) and the J_cd block of every quartet slot
   double* const kw0 = reinterpret_cast<double*>(wbase + static_cast<size_t>(QPW) * NT * sizeof(T));
   double* const kac0 = kw0;
-  double* const kad0 = kac0 + C::NA * C::NC * QPW;
-  double* const kbc0 = kad0 + C::NA * C::ND * QPW;
-  double* const kbd0 = kbc0 + C::NB * C::NC * QPW;
-  double* const jcd0 = kbd0 + C::NB * C::ND * QPW;
-  const AD kac{kac0 + ql}, kad{kad0 + ql}, kbc{kbc0 + ql}, kbd{kbd0 + ql}, jcdw{jcd0 + ql};
+  double* const kad0 = kac0 + C::NA * C::NC * kWave;
+  double* const kbc0 = kad0 + C::NA * C::ND * kWave;
+  double* const kbd0 = kbc0 + C::NB * C::NC * kWave;
+  double* const jcd0 = kbd0 + C::NB * C::ND * kWave;
+  const AD kac{kac0 + lane}, kad{kad0 + lane}, kbc{kbc0 + lane}, kbd{kbd0 + lane};
+  const LaneArr<double, QPW> jcdw{jcd0 + ql};
   const int z = 0;
   const int nb = a.bra.n, nk = a.ket.n;
   const size_t n = static_cast<size_t>(a.n);
@@ -959,10 +985,15 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
             ACz = T(Az - a.ket.A[2 * nk + k]);
     split_passes<C, T, G, 0, AT>(a, i, k, sub, ACx, ACy, ACz, cacc, z);
     const T CDx = T(a.ket.AB[k]), CDy = T(a.ket.AB[nk + k]), CDz = T(a.ket.AB[2 * nk + k]);
-    if (sub == 0) split_ket_hrr<C, T, AT>(cacc, X, z, CDx, CDy, CDz);
+    // the G lanes of a quartet share the horizontal recurrences and the
+    // digestion: lane `sub` takes e = sub, sub+G, ... and (c,d) = sub, sub+G, ...
+    lanes_sync();   // cacc was written by the group's first lane
+    split_ket_hrr<C, T, AT>(cacc, X, z, CDx, CDy, CDz, sub, G);
+    lanes_sync();   // X rows come from all lanes of the group
     const int c0 = a.ket.bf[k], d0 = a.ket.bf[nk + k];
+    (void)active;
     const double fq =
-        active ? fbra * a.ket.fpair[k] * ((a.same_bin && k == i) ? 0.5 : 1.0) : 0.0;
+        inrange ? fbra * a.ket.fpair[k] * ((a.same_bin && k == i) ? 0.5 : 1.0) : 0.0;
 
     for (int m = 0; m < a.n_dm; ++m) {
       const double* Dm = a.D + m * nn;
@@ -976,19 +1007,17 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
           Dab[x * C::NB + y] = Dm[(a0 + x) * n + b0 + y];
           jab[x * C::NB + y] = 0.0;
         }
-      if (sub == 0) {
 #pragma unroll
-        for (int t = 0; t < C::NA * C::NC; ++t) kac[z + t] = 0.0;
+      for (int t = 0; t < C::NA * C::NC; ++t) kac[z + t] = 0.0;
 #pragma unroll
-        for (int t = 0; t < C::NA * C::ND; ++t) kad[z + t] = 0.0;
+      for (int t = 0; t < C::NA * C::ND; ++t) kad[z + t] = 0.0;
 #pragma unroll
-        for (int t = 0; t < C::NB * C::NC; ++t) kbc[z + t] = 0.0;
+      for (int t = 0; t < C::NB * C::NC; ++t) kbc[z + t] = 0.0;
 #pragma unroll
-        for (int t = 0; t < C::NB * C::ND; ++t) kbd[z + t] = 0.0;
-      }
+      for (int t = 0; t < C::NB * C::ND; ++t) kbd[z + t] = 0.0;
 
 #pragma nounroll
-      for (int cd = 0; cd < (sub == 0 ? NCD : 0); ++cd) {
+      for (int cd = sub; cd < NCD; cd += G) {
         const int c = cd / C::ND, d = cd % C::ND;
         T ev[C::NE];
 #pragma unroll
@@ -1041,12 +1070,13 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
         const double s = wave_sum(jab[t]);
         if (lane == kWaveSumLane) atomic_add(&Jm[(a0 + t / C::NB) * n + b0 + t % C::NB], 2.0 * s);
       }
-      // out-of-range slots hold zeros (fq = 0)
-      scatter_ws<C::NC, C::ND, QPW>(Jm, n, c0, d0, jcd0);
-      scatter_ws<C::NA, C::NC, QPW>(Km, n, a0, c0, kac0);
-      scatter_ws<C::NA, C::ND, QPW>(Km, n, a0, d0, kad0);
-      scatter_ws<C::NB, C::NC, QPW>(Km, n, b0, c0, kbc0);
-      scatter_ws<C::NB, C::ND, QPW>(Km, n, b0, d0, kbd0);
+      // out-of-range slots hold zeros (fq = 0); K blocks are summed over the
+      // G lanes of each slot
+      scatter_ws<C::NC, C::ND, QPW, 1>(Jm, n, c0, d0, jcd0);
+      scatter_ws<C::NA, C::NC, QPW, G>(Km, n, a0, c0, kac0);
+      scatter_ws<C::NA, C::ND, QPW, G>(Km, n, a0, d0, kad0);
+      scatter_ws<C::NB, C::NC, QPW, G>(Km, n, b0, c0, kbc0);
+      scatter_ws<C::NB, C::ND, QPW, G>(Km, n, b0, d0, kbd0);
     }
   }
   }
@@ -1072,7 +1102,7 @@ __global__ __launch_bounds__(kBlock) void schwarz_split_kernel(const EriLaunch a
     const int t = t0 < n ? t0 : n - 1;
     split_passes<C, double, G, 0, AD>(a, t, t, sub, 0.0, 0.0, 0.0, cacc, z);
     const double ABx = a.bra.AB[t], ABy = a.bra.AB[n + t], ABz = a.bra.AB[2 * n + t];
-    if (sub == 0) split_ket_hrr<C, double, AD>(cacc, X, z, ABx, ABy, ABz);
+    if (sub == 0) split_ket_hrr<C, double, AD>(cacc, X, z, ABx, ABy, ABz, 0, 1);
     double mx = 0.0;
 #pragma nounroll
     for (int cd = 0; cd < (sub == 0 ? NCD : 0); ++cd) {

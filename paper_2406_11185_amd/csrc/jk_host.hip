@@ -984,7 +984,7 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
 
     jk_stats st = base_stats(P, S);
     auto waves_of = [&](const LaunchRec& r) {
-      const size_t per_wave = split_ws_bytes(r.cls, r.pr) / r.lanes;  // one slot per quartet
+      const size_t per_wave = split_ws_bytes(r.cls, r.pr, r.lanes);
       if (!per_wave) return std::pair<int, size_t>(0, 0);
       const size_t cap = std::max<size_t>(64, kWsBudget / per_wave);
       return std::pair<int, size_t>(static_cast<int>(std::min<size_t>(r.i1 - r.i0, cap)), per_wave);
