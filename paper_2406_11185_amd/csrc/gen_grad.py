@@ -310,8 +310,9 @@ def wrapper(name):
         f"void launch_grad_{name}(const GradLaunch& a, int fp32, hipStream_t s) {{",
         "  const dim3 grid((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);",
         f"  constexpr int GM = GCls_{name}::GMAX;  // gradient launches always use the class maximum",
-        f"  if (fp32) hipLaunchKernelGGL((grad_kernel<GCls_{name}, float, GM>), grid, block, 0, s, a);",
-        f"  else hipLaunchKernelGGL((grad_kernel<GCls_{name}, double, GM>), grid, block, 0, s, a);",
+        "  const size_t lds = static_cast<size_t>(a.lds_doubles) * sizeof(double);",
+        f"  if (fp32) hipLaunchKernelGGL((grad_kernel<GCls_{name}, float, GM>), grid, block, lds, s, a);",
+        f"  else hipLaunchKernelGGL((grad_kernel<GCls_{name}, double, GM>), grid, block, lds, s, a);",
         "}",
         "}  // namespace jk", ""])
 

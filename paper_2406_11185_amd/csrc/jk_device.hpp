@@ -20,6 +20,7 @@ namespace jk {
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kSchwarzSplitLanes = 64;   // multi-pass diagonal classes: lanes per pair
 constexpr int kMaxItemChunks = 16;   // a work item covers 1..16 wave-wide ket chunks
 #ifndef JK_TARGET_WAVES
 #define JK_TARGET_WAVES 8192
@@ -389,19 +390,6 @@ __device__ __forceinline__ void prim_setup(T p, T oo2p, T PAx, T PAy, T PAz, T K
 // space lets the compiler use scalar loads where the address is uniform.
 using CDouble = const __attribute__((address_space(4))) double*;
 
-// Keeps the compiler from moving instructions across this point: the Boys
-// row of the next primitive quartet is requested before the current one is
-// used, so that its latency overlaps the current recurrences.
-__device__ __forceinline__ void pipeline_fence() { __builtin_amdgcn_sched_barrier(0); }
-
-// Classes with at most this many contracted intermediates software-pipeline
-// their primitive loop (two Boys rows in flight need about 40 more VGPRs).
-#ifndef JK_PIPE_MAX_NACC
-#define JK_PIPE_MAX_NACC 0
-#endif
-template <class C>
-constexpr bool kPipelined = C::NACC <= JK_PIPE_MAX_NACC;
-
 // Contraction loop of one shell quartet: bra pair i, ket pair k.  `vrr(F, c)`
 // adds one primitive quartet to the caller's accumulators.
 //
@@ -412,11 +400,7 @@ constexpr bool kPipelined = C::NACC <= JK_PIPE_MAX_NACC;
 // G > 1: the G lanes of a group share the quartet; lane `sub` takes the
 // primitive quartets sub, sub+G, ... as (kl, ij) with ij running fastest; the
 // group's accumulators are summed by the caller.
-//
-// PIPE: the loop is software-pipelined by one step (two alternating stages):
-// the Boys row of the next primitive quartet is requested before the current
-// one is finished.
-template <int L, typename T, int G, bool PIPE, class V>
+template <int L, typename T, int G, class V>
 __device__ __forceinline__ void contract(const EriLaunch& a, const BoysTab<T>& bt, int i, int k,
                                          int sub, T ACx, T ACy, T ACz, V&& vrr) {
   const int nk = a.ket.n;
@@ -442,25 +426,10 @@ __device__ __forceinline__ void contract(const EriLaunch& a, const BoysTab<T>& b
                           T(b[kKt]), q, oo2q, QCx, QCy, QCz, Kcd, bt, F, c);
         vrr(F, c);
       };
-      if constexpr (PIPE) {
-        PrimGeo<L, T> g0, g1;
-        geo(0, g0);
-        for (int ij = 0;;) {
-          if (ij + 1 < nppb) geo(ij + 1, g1);
-          pipeline_fence();
-          finish(ij, g0);
-          if (++ij == nppb) break;
-          if (ij + 1 < nppb) geo(ij + 1, g0);
-          pipeline_fence();
-          finish(ij, g1);
-          if (++ij == nppb) break;
-        }
-      } else {
-        for (int ij = 0; ij < nppb; ++ij) {
-          PrimGeo<L, T> g;
-          geo(ij, g);
-          finish(ij, g);
-        }
+      for (int ij = 0; ij < nppb; ++ij) {
+        PrimGeo<L, T> g;
+        geo(ij, g);
+        finish(ij, g);
       }
     }
   } else {
@@ -488,34 +457,11 @@ __device__ __forceinline__ void contract(const EriLaunch& a, const BoysTab<T>& b
     };
     int kl0 = 0, ij0 = sub;
     while (ij0 >= nppb) { ij0 -= nppb; ++kl0; }
-    if constexpr (PIPE) {
-      // (kl0, ij0): quartet t held by the stage about to be finished
-      int t = sub;
-      PrimGeo<L, T> g0, g1;
-      if (t < npq) geo(kl0, ij0, g0);
-      while (t < npq) {
-        int kl1 = kl0, ij1 = ij0;
-        step(kl1, ij1);
-        if (t + G < npq) geo(kl1, ij1, g1);
-        pipeline_fence();
-        finish(kl0, ij0, g0);
-        t += G;
-        if (t >= npq) break;
-        kl0 = kl1; ij0 = ij1;
-        step(kl1, ij1);
-        if (t + G < npq) geo(kl1, ij1, g0);
-        pipeline_fence();
-        finish(kl0, ij0, g1);
-        t += G;
-        kl0 = kl1; ij0 = ij1;
-      }
-    } else {
-      for (int t = sub; t < npq; t += G) {
-        PrimGeo<L, T> g;
-        geo(kl0, ij0, g);
-        finish(kl0, ij0, g);
-        step(kl0, ij0);
-      }
+    for (int t = sub; t < npq; t += G) {
+      PrimGeo<L, T> g;
+      geo(kl0, ij0, g);
+      finish(kl0, ij0, g);
+      step(kl0, ij0);
     }
   }
 }
@@ -552,11 +498,27 @@ __device__ __forceinline__ T dpp_t(T v) {
 // pairs within a quad, mirror within half-rows, mirror within rows.
 template <int G, typename T>
 __device__ __forceinline__ T group_sum(T v) {
-  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group size");
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16 || G == 64, "group size");
   if constexpr (G >= 2) v += dpp_t<0xB1>(v);    // quad_perm [1,0,3,2]
   if constexpr (G >= 4) v += dpp_t<0x4E>(v);    // quad_perm [2,3,0,1]
   if constexpr (G >= 8) v += dpp_t<0x141>(v);   // row_half_mirror
   if constexpr (G >= 16) v += dpp_t<0x140>(v);  // row_mirror
+  if constexpr (G == 64) {
+    // rows 0..3: row 0 into row 1, rows 0-1 into rows 2-3, then lane 63 to all
+    if constexpr (sizeof(T) == 8) {
+      v += dpp_f64<0x142, 0xA>(v, 0.0);
+      v += dpp_f64<0x143, 0xC>(v, 0.0);
+      const long long b = __builtin_bit_cast(long long, v);
+      const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), 63);
+      const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), 63);
+      v = __builtin_bit_cast(T, (static_cast<long long>(hi) << 32) |
+                                    static_cast<unsigned long long>(static_cast<unsigned>(lo)));
+    } else {
+      v += dpp_f32<0x142, 0xA>(v, 0.0f);
+      v += dpp_f32<0x143, 0xC>(v, 0.0f);
+      v = __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+    }
+  }
   return v;
 }
 
@@ -750,7 +712,7 @@ __device__ __forceinline__ void eri_item(const EriLaunch& a, const BoysTab<T>& b
     T acc[C::NACC];
 #pragma unroll
     for (int t = 0; t < C::NACC; ++t) acc[t] = T(0);
-    contract<C::L, T, G, kPipelined<C>>(a, bt, i, k, sub, ACx, ACy, ACz,
+    contract<C::L, T, G>(a, bt, i, k, sub, ACx, ACy, ACz,
                          [&](const T* F, const VrrCoef<T>& c) { C::template vrr<T>(F, c, acc); });
     group_sum_all<G>(acc);
 
@@ -884,7 +846,7 @@ __global__ __launch_bounds__(kBlock) void schwarz_kernel(const EriLaunch a, doub
   double acc[C::NACC];
 #pragma unroll
   for (int s = 0; s < C::NACC; ++s) acc[s] = 0.0;
-  contract<C::L, double, G, false>(a, global_boys<C::L, double>(a), t, t, sub, 0.0, 0.0, 0.0,
+  contract<C::L, double, G>(a, global_boys<C::L, double>(a), t, t, sub, 0.0, 0.0, 0.0,
                             [&](const double* F, const VrrCoef<double>& c) {
                               C::template vrr<double>(F, c, acc);
                             });
@@ -906,7 +868,7 @@ __device__ __forceinline__ void split_passes(const EriLaunch& a, int i, int k, i
   T acc[C::NE * NFJ];
 #pragma unroll
   for (int t = 0; t < C::NE * NFJ; ++t) acc[t] = T(0);
-  contract<C::L, T, G, kPipelined<C>>(a, global_boys<C::L, T>(a), i, k, sub, ACx, ACy, ACz,
+  contract<C::L, T, G>(a, global_boys<C::L, T>(a), i, k, sub, ACx, ACy, ACz,
                                       [&](const T* F, const VrrCoef<T>& c) {
     C::template vrr_pass<J, T>(F, c, acc);
   });
@@ -1085,37 +1047,40 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
 template <class C>
 __global__ __launch_bounds__(kBlock) void schwarz_split_kernel(const EriLaunch a, double* Qout) {
   constexpr int NCD = C::NC * C::ND;
-  constexpr int G = C::GMAX, PPW = kWave / G;   // pairs per wave step
+  constexpr int G = kSchwarzSplitLanes;   // one wavefront per pair
   constexpr int NT = C::NACC + C::NE * NCD;
+  static_assert(C::NA * C::NB == NCD, "diagonal class");
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (wave >= a.nwaves) return;
-  const int sub = lane & (G - 1), ql = lane / G;
   const int n = a.bra.n;
-  using AD = LaneArr<double, PPW>;
-  double* wl = static_cast<double*>(a.ws) + static_cast<size_t>(wave) * PPW * NT + ql;
+  using AD = LaneArr<double, 1>;
+  double* wl = static_cast<double*>(a.ws) + static_cast<size_t>(wave) * NT;
   const AD cacc{wl};
-  const AD X{wl + static_cast<size_t>(C::NACC) * PPW};
+  const AD X{wl + C::NACC};
   const int z = 0;
-  for (int p0 = wave * PPW; p0 < n; p0 += a.nwaves * PPW) {
-    const int t0 = p0 + ql;
-    const int t = t0 < n ? t0 : n - 1;
-    split_passes<C, double, G, 0, AD>(a, t, t, sub, 0.0, 0.0, 0.0, cacc, z);
+  for (int t = wave; t < n; t += a.nwaves) {
+    split_passes<C, double, G, 0, AD>(a, t, t, lane, 0.0, 0.0, 0.0, cacc, z);
     const double ABx = a.bra.AB[t], ABy = a.bra.AB[n + t], ABz = a.bra.AB[2 * n + t];
-    if (sub == 0) split_ket_hrr<C, double, AD>(cacc, X, z, ABx, ABy, ABz, 0, 1);
+    lanes_sync();
+    split_ket_hrr<C, double, AD>(cacc, X, z, ABx, ABy, ABz, lane, G);
+    lanes_sync();
+    // diagonal (ab|ab): lane cd takes component cd of the bra recurrence
     double mx = 0.0;
-#pragma nounroll
-    for (int cd = 0; cd < (sub == 0 ? NCD : 0); ++cd) {
+    if (lane < NCD) {
       double ev[C::NE];
 #pragma unroll
-      for (int e = 0; e < C::NE; ++e) ev[e] = X[z + e * NCD + cd];
+      for (int e = 0; e < C::NE; ++e) ev[e] = X[z + e * NCD + lane];
       double ab[C::NA * C::NB];
       C::template bra_hrr<double>(ev, ABx, ABy, ABz, ab);
 #pragma unroll
       for (int s = 0; s < C::NA * C::NB; ++s)
-        if (s == cd) mx = fmax(mx, ab[s]);
+        if (s == lane) mx = ab[s];
     }
-    if (t0 < n && sub == 0) Qout[t] = sqrt(fmax(mx, 0.0));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
+    if (lane == 0) Qout[t] = sqrt(fmax(mx, 0.0));
+    lanes_sync();   // the workspace is rewritten for the next pair
   }
 }
 

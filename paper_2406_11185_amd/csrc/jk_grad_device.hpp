@@ -11,8 +11,19 @@ struct GradLaunch {
   double* dEdR;     // [n_dm][n_atoms][3]
   int n_atoms;
   void* ws;         // workspace: nwaves * 64 lanes * C::WS values of type T
-  int nwaves;       // wavefronts of the launch; each loops over items with this stride
+  int nwaves;       // wavefronts of the launch; each claims items until none is left
+  int lds_doubles;  // n_dm * n_atoms * 3 when the workgroup accumulates dE/dR in LDS
+                    // (dynamic shared memory of that many doubles), else 0
 };
+
+// Gradient contributions go to a workgroup copy of dE/dR in LDS (the whole
+// gradient is a few hundred values, so direct global atomics from every
+// quartet would serialise on a handful of lines) and are added to global
+// memory once per workgroup at the end; without LDS room, directly.
+__device__ __forceinline__ void grad_add(double* lds, double* glob, int idx, double v) {
+  if (lds) atomicAdd(&lds[idx], v);
+  else atomic_add(&glob[idx], v);
+}
 
 
 
@@ -85,9 +96,16 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
   const int lane = threadIdx.x & (kWave - 1);
   const int sub = lane & (GL - 1), ql = lane / GL;
   const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (wave >= g.nwaves) return;
+  extern __shared__ double gacc[];   // [n_dm][n_atoms][3] when g.lds_doubles > 0
+  double* const lds = g.lds_doubles > 0 ? gacc : nullptr;
+  if (lds) {
+    for (int t = threadIdx.x; t < g.lds_doubles; t += kBlock) gacc[t] = 0.0;
+    __syncthreads();
+  }
+  // waves past the launch's wavefront count only take part in the final flush
+  const bool idle = wave >= g.nwaves;
   using AT = LaneArr<T, QPW>;
-  T* wsl = static_cast<T*>(g.ws) + static_cast<size_t>(wave) * C::WS * QPW + ql;
+  T* wsl = static_cast<T*>(g.ws) + static_cast<size_t>(idle ? 0 : wave) * C::WS * QPW + ql;
   const AT G{wsl};
   const AT XA{wsl + static_cast<size_t>(C::NG) * QPW};
   const AT XB{XA.p + static_cast<size_t>(C::NE_A) * NCD * QPW};
@@ -95,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
   const AT XU{XC.p + static_cast<size_t>(C::NE_C) * C::NCP * QPW};
   const AT XV{XU.p + static_cast<size_t>(C::NE_U) * NCD * QPW};
   const int z = 0;
-  for (int item = claim_item(a.next); item < a.nitems; item = claim_item(a.next)) {
+  for (int item = idle ? a.nitems : claim_item(a.next); item < a.nitems; item = claim_item(a.next)) {
   const int4 w = a.items[item];
   const int i = __builtin_amdgcn_readfirstlane(w.x);
   const int kbeg = __builtin_amdgcn_readfirstlane(w.y);
@@ -245,23 +263,28 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
           }
         }
       }
-      double* G3 = g.dEdR + static_cast<size_t>(m) * g.n_atoms * 3;
+      const int o3 = m * g.n_atoms * 3;
 #pragma unroll
       for (int x = 0; x < 3; ++x) {
         const double ga = fq * gA[x], gb = fq * gB[x], gc = fq * gC[x];
         const double gd = -(ga + gb + gc);
         const double sa = wave_sum(ga), sb = wave_sum(gb);
         if (lane == kWaveSumLane) {
-          atomic_add(&G3[atA * 3 + x], sa);
-          atomic_add(&G3[atB * 3 + x], sb);
+          grad_add(lds, g.dEdR, o3 + atA * 3 + x, sa);
+          grad_add(lds, g.dEdR, o3 + atB * 3 + x, sb);
         }
         if (active) {
-          atomic_add(&G3[atC * 3 + x], gc);
-          atomic_add(&G3[atD * 3 + x], gd);
+          grad_add(lds, g.dEdR, o3 + atC * 3 + x, gc);
+          grad_add(lds, g.dEdR, o3 + atD * 3 + x, gd);
         }
       }
     }
   }
+  }
+  if (lds) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < g.lds_doubles; t += kBlock)
+      if (gacc[t] != 0.0) atomic_add(&g.dEdR[t], gacc[t]);
   }
 }
 

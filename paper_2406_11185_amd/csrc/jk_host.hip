@@ -226,25 +226,39 @@ __device__ __forceinline__ int first_below(const double* Qk, int lo, int hi, dou
 
 __global__ void ranges_kernel(RangeArgs r) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= r.nt) return;
-  const int bp = find_bin(r.bp_t0, r.nbp, t);
-  const int X = r.bp_x[bp], Y = r.bp_y[bp];
-  const int i = t - r.bp_t0[bp];
-  const double* QX = r.Q + r.bin_off[X];
-  const double* QY = r.Q + r.bin_off[Y];
-  const int nY = r.bin_off[Y + 1] - r.bin_off[Y];
-  const int klo = (X == Y) ? i : 0;
-  const double qi = QX[i];
-  const int ktol = (r.tol > 0.0) ? first_below(QY, klo, nY, qi, r.tol) : nY;
-  int k64 = ktol;
-  if (r.mixed) k64 = first_below(QY, klo, ktol, qi, r.thr);
-  const int n64 = k64 - klo, n32 = ktol - k64;
-  r.rng[t] = klo;
-  r.rng[r.nt + t] = k64;
-  r.rng[2 * r.nt + t] = ktol;
-  atomicAdd(&r.qstat[3 * bp + 0], static_cast<unsigned long long>(n64));
-  atomicAdd(&r.qstat[3 * bp + 1], static_cast<unsigned long long>(n32));
-  atomicAdd(&r.qstat[3 * bp + 2], static_cast<unsigned long long>(nY - ktol));
+  const bool live = t < r.nt;
+  const int bp = live ? find_bin(r.bp_t0, r.nbp, t) : -1;
+  unsigned long long cnt[3] = {0, 0, 0};
+  if (live) {
+    const int X = r.bp_x[bp], Y = r.bp_y[bp];
+    const int i = t - r.bp_t0[bp];
+    const double* QX = r.Q + r.bin_off[X];
+    const double* QY = r.Q + r.bin_off[Y];
+    const int nY = r.bin_off[Y + 1] - r.bin_off[Y];
+    const int klo = (X == Y) ? i : 0;
+    const double qi = QX[i];
+    const int ktol = (r.tol > 0.0) ? first_below(QY, klo, nY, qi, r.tol) : nY;
+    int k64 = ktol;
+    if (r.mixed) k64 = first_below(QY, klo, ktol, qi, r.thr);
+    r.rng[t] = klo;
+    r.rng[r.nt + t] = k64;
+    r.rng[2 * r.nt + t] = ktol;
+    cnt[0] = static_cast<unsigned long long>(k64 - klo);
+    cnt[1] = static_cast<unsigned long long>(ktol - k64);
+    cnt[2] = static_cast<unsigned long long>(nY - ktol);
+  }
+  // quartet counts per bin pair: one atomic per wavefront when all its lanes
+  // belong to the same bin pair (the usual case), else one per lane
+  const int bp0 = __shfl(bp, 0, 64);
+  if (__all(bp == bp0 || bp < 0)) {
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+      for (int off = 32; off > 0; off >>= 1) cnt[x] += __shfl_xor(cnt[x], off, 64);
+    if ((threadIdx.x & 63) == 0 && bp0 >= 0)
+      for (int x = 0; x < 3; ++x) atomicAdd(&r.qstat[3 * bp0 + x], cnt[x]);
+  } else if (live) {
+    for (int x = 0; x < 3; ++x) atomicAdd(&r.qstat[3 * bp + x], cnt[x]);
+  }
 }
 
 // Work items per (thread, precision) for the item sizes chosen per bin pair.
@@ -346,6 +360,7 @@ inline unsigned grid_of(size_t n, int block) { return static_cast<unsigned>((n +
 // Upper bound of the workspace one launch of a multi-pass or gradient kernel
 // uses; the launch then loops over its items with correspondingly few waves.
 constexpr size_t kWsBudget = size_t(1) << 30;
+constexpr size_t kGradLdsBytes = 48 << 10;   // workgroup copy of dE/dR in LDS up to this size
 constexpr size_t kMaxCopies = 8;                  // accumulator copies of J and K
 constexpr size_t kAccBudget = size_t(256) << 20;   // bytes for them
 
@@ -631,9 +646,9 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
     a.boys64 = c->boys64;
     a.boys32 = c->boys32;
     const int dcls = quartet_class(P.bin_cls[bb], P.bin_cls[bb]);
-    const size_t per_wave = split_schwarz_ws_bytes(dcls) / class_lanes(dcls);
+    const size_t per_wave = split_schwarz_ws_bytes(dcls) / kSchwarzSplitLanes;
     if (per_wave) {  // multi-pass diagonal class: workspace, waves loop over the pairs
-      const int pairs_per_wave = kWave / class_lanes(dcls);
+      const int pairs_per_wave = kWave / kSchwarzSplitLanes;
       const size_t want = (static_cast<size_t>(a.bra.n) + pairs_per_wave - 1) / pairs_per_wave;
       const size_t cap = std::max<size_t>(64, kWsBudget / per_wave);
       a.nwaves = static_cast<int>(std::min(want, cap));
@@ -1071,6 +1086,8 @@ int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, dou
           g.e.next = next;
           g.dEdR = dEdR;
           g.n_atoms = basis->n_atoms;
+          const size_t ng = static_cast<size_t>(o.n_dm) * basis->n_atoms * 3;
+          g.lds_doubles = ng * sizeof(double) <= kGradLdsBytes ? static_cast<int>(ng) : 0;
           g.ws = ws[k];
           g.nwaves = waves_of(r).first;
           launch_grad(r.cls, r.pr, g, ls);
