@@ -16,9 +16,9 @@ the lower-order (a-1_i b|cd), (a b-1_i|cd), (ab|c-1_i d), which are contracted
 with Gamma_abcd = 1/2 D_ab D_cd - 1/8 (D_ac D_bd + D_ad D_bc).  The derivative
 with respect to the fourth centre follows from translational invariance.
 
-The accumulators are built in passes of at most PASS_ACC values (one pass of
-the primitive loop each) and parked in private memory, as in the multi-pass
-energy classes.
+The accumulators are built in balanced passes of at most PASS_ACC values (one
+pass of the primitive loop each) and parked in a global workspace, as in the
+multi-pass energy classes.
 """
 from __future__ import annotations
 
@@ -28,7 +28,7 @@ import sys
 
 import gen_hgp as g
 
-PASS_ACC = 96
+PASS_ACC = 64
 XYZ = "xyz"
 
 
@@ -142,10 +142,13 @@ def gen_grad_class(la, lb, lc, ld):
             for jf, f in enumerate(Fs):
                 nodes.setdefault((f, e), []).append((w, off[nm] + ie * len(Fs) + jf))
     order = sorted(nodes, key=lambda fe: (sum(fe[0]), fe[0], sum(fe[1]), fe[1]))
+    # balanced passes of at most PASS_ACC accumulators
+    total = sum(len(v) for v in nodes.values())
+    cap = -(-total // -(-total // PASS_ACC))
     passes, cur, cnt = [], [], 0
     for fe in order:
         k = len(nodes[fe])
-        if cnt + k > PASS_ACC and cur:
+        if cnt + k > cap and cur:
             passes.append(cur)
             cur, cnt = [], 0
         cur.append(fe)
@@ -177,7 +180,8 @@ def gen_grad_class(la, lb, lc, ld):
         for fe in pas:
             val = v.node(fe[1], fe[0], 0)
             for w, gi in nodes[fe]:
-                lines.append(f"acc[{k}] += {w} * {val};" if w else f"acc[{k}] += {val};")
+                # accumulate right after the value is formed: few live temporaries
+                v.lines.append(f"acc[{k}] += {w} * {val};" if w else f"acc[{k}] += {val};")
                 store.append(f"G[z + {gi}] = acc[{k}];")
                 k += 1
         vrr_flops += v.flops + 2 * k

@@ -136,9 +136,11 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
     grad_passes<C, T, GL, 0>(a, i, k, sub, ACx, ACy, ACz, G, z);
     const T CDx = T(a.ket.AB[k]), CDy = T(a.ket.AB[nk + k]), CDz = T(a.ket.AB[2 * nk + k]);
 
-    // ket horizontal recurrences, one bra index e at a time
+    // ket horizontal recurrences, one bra index e at a time; the G lanes of a
+    // quartet share them (e = sub, sub+G, ...) and then the (c, d) loop
+    lanes_sync();   // the passes were stored by the group's first lane
 #pragma nounroll
-    for (int e = 0; e < (sub == 0 ? C::NE_A : 0); ++e) {
+    for (int e = sub; e < C::NE_A; e += GL) {
       T f[C::NF_A], o[NCD];
 #pragma unroll
       for (int t = 0; t < C::NF_A; ++t) f[t] = G[z + C::OFF_A + e * C::NF_A + t];
@@ -147,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
       for (int t = 0; t < NCD; ++t) XA[z + e * NCD + t] = o[t];
     }
 #pragma nounroll
-    for (int e = 0; e < (sub == 0 ? C::NE_B : 0); ++e) {
+    for (int e = sub; e < C::NE_B; e += GL) {
       T f[C::NF_B], o[NCD];
 #pragma unroll
       for (int t = 0; t < C::NF_B; ++t) f[t] = G[z + C::OFF_B + e * C::NF_B + t];
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
       for (int t = 0; t < NCD; ++t) XB[z + e * NCD + t] = o[t];
     }
 #pragma nounroll
-    for (int e = 0; e < (sub == 0 ? C::NE_C : 0); ++e) {
+    for (int e = sub; e < C::NE_C; e += GL) {
       T f[C::NF_C], o[C::NCP];
 #pragma unroll
       for (int t = 0; t < C::NF_C; ++t) f[t] = G[z + C::OFF_C + e * C::NF_C + t];
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
     }
     if constexpr (C::USE_U) {
 #pragma nounroll
-      for (int e = 0; e < (sub == 0 ? C::NE_U : 0); ++e) {
+      for (int e = sub; e < C::NE_U; e += GL) {
         T f[C::NF_U], o[NCD];
 #pragma unroll
         for (int t = 0; t < C::NF_U; ++t) f[t] = G[z + C::OFF_U + e * C::NF_U + t];
@@ -182,10 +184,11 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
       }
     }
 
+    lanes_sync();   // the transformed rows come from all lanes of the group
     const int c0 = a.ket.bf[k], d0 = a.ket.bf[nk + k];
     const int atC = a.ket.atoms[k], atD = a.ket.atoms[nk + k];
     const double fq =
-        active ? 8.0 * fbra * a.ket.fpair[k] * ((a.same_bin && k == i) ? 0.5 : 1.0) : 0.0;
+        inrange ? 8.0 * fbra * a.ket.fpair[k] * ((a.same_bin && k == i) ? 0.5 : 1.0) : 0.0;
 
     for (int m = 0; m < a.n_dm; ++m) {
       const double* Dm = a.D + m * nn;
@@ -196,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
         for (int y = 0; y < C::NB; ++y) Dab[x * C::NB + y] = Dm[(a0 + x) * n + b0 + y];
       double gA[3] = {0.0, 0.0, 0.0}, gB[3] = {0.0, 0.0, 0.0}, gC[3] = {0.0, 0.0, 0.0};
 #pragma nounroll
-      for (int cd = 0; cd < (sub == 0 ? NCD : 0); ++cd) {
+      for (int cd = sub; cd < NCD; cd += GL) {
         const int c = cd / C::ND, d = cd % C::ND;
         const double Dcd = Dm[(c0 + c) * n + d0 + d];
         double Dac[C::NA], Dad[C::NA], Dbc[C::NB], Dbd[C::NB];
@@ -266,8 +269,10 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
       const int o3 = m * g.n_atoms * 3;
 #pragma unroll
       for (int x = 0; x < 3; ++x) {
-        const double ga = fq * gA[x], gb = fq * gB[x], gc = fq * gC[x];
-        const double gd = -(ga + gb + gc);
+        // partial sums of this lane's (c, d) share; C and D need the quartet's sum
+        const double ga = fq * gA[x], gb = fq * gB[x];
+        const double gc = fq * group_sum<GL>(gC[x]);
+        const double gd = -(group_sum<GL>(ga + gb) + gc);
         const double sa = wave_sum(ga), sb = wave_sum(gb);
         if (lane == kWaveSumLane) {
           grad_add(lds, g.dEdR, o3 + atA * 3 + x, sa);
