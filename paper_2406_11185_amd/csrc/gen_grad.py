@@ -305,20 +305,34 @@ def gen_grad_class(la, lb, lc, ld):
     return "\n".join(s) + "\n", info
 
 
-def wrapper(name):
-    return "\n".join([
-        "// generated by gen_grad.py -- do not edit",
-        '#include "jk_grad_device.hpp"',
-        "namespace jk {",
-        f'#include "gcls_{name}.inc"',
-        f"void launch_grad_{name}(const GradLaunch& a, int fp32, hipStream_t s) {{",
-        "  const dim3 grid((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);",
-        f"  constexpr int GM = GCls_{name}::GMAX;  // gradient launches always use the class maximum",
-        "  const size_t lds = static_cast<size_t>(a.lds_doubles) * sizeof(double);",
-        f"  if (fp32) hipLaunchKernelGGL((grad_kernel<GCls_{name}, float, GM>), grid, block, lds, s, a);",
-        f"  else hipLaunchKernelGGL((grad_kernel<GCls_{name}, double, GM>), grid, block, lds, s, a);",
-        "}",
-        "}  // namespace jk", ""])
+WS_WAVES = 4096                       # wavefronts the 1 GiB workspace should hold
+
+
+def grad_lane_options(gmax, ws):
+    """Lane counts a gradient class is compiled for; the host picks one per launch.
+    Fewer lanes per quartet mean more quartets per wavefront and a larger FP64
+    workspace: only counts whose workspace lets WS_WAVES wavefronts run."""
+    return [x for x in (1, 4, 16) if x <= gmax and
+            (x == gmax or (64 // x) * ws * 8 * WS_WAVES <= (1 << 30))]
+
+
+def wrapper(name, gmax, ws):
+    opts = grad_lane_options(gmax, ws)
+    lines = ["// generated by gen_grad.py -- do not edit",
+             '#include "jk_grad_device.hpp"',
+             "namespace jk {",
+             f'#include "gcls_{name}.inc"',
+             f"void launch_grad_{name}(const GradLaunch& a, int fp32, hipStream_t s) {{",
+             "  const dim3 grid((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);",
+             "  const size_t lds = static_cast<size_t>(a.lds_doubles) * sizeof(double);"]
+    for j, gl in enumerate(opts):
+        cond = "true" if j == len(opts) - 1 else f"a.e.lanes == {gl}"
+        lines += [f"  {'if' if j == 0 else 'else if'} ({cond}) {{",
+                  f"    if (fp32) hipLaunchKernelGGL((grad_kernel<GCls_{name}, float, {gl}>), grid, block, lds, s, a);",
+                  f"    else hipLaunchKernelGGL((grad_kernel<GCls_{name}, double, {gl}>), grid, block, lds, s, a);",
+                  "  }"]
+    lines += ["}", "}  // namespace jk", ""]
+    return "\n".join(lines)
 
 
 def table(names, infos):
@@ -328,6 +342,12 @@ def table(names, infos):
     t.append("int grad_ws_elems(int cls) {")
     t.append("  static const int w[21] = {" + ", ".join(str(i["ws"]) for i in infos) + "};")
     t.append("  return (cls >= 0 && cls < 21) ? w[cls] : 0;")
+    t.append("}")
+    t.append("// bit g set: the gradient class has a kernel with g lanes per shell quartet")
+    t.append("int grad_lane_mask(int cls) {")
+    t.append("  static const int m[21] = {" + ", ".join(
+        str(sum(1 << x for x in grad_lane_options(i["lanes"], i["ws"]))) for i in infos) + "};")
+    t.append("  return (cls >= 0 && cls < 21) ? m[cls] : 2;")
     t.append("}")
     t.append("int grad_lanes(int cls) {")
     t.append("  static const int g[21] = {" + ", ".join(str(i["lanes"]) for i in infos) + "};")
@@ -350,7 +370,7 @@ def main(outdir):
         names.append(info["name"])
         g.write_if_changed(os.path.join(outdir, f"gcls_{info['name']}.inc"),
                            "// generated by gen_grad.py -- do not edit\n" + code)
-        g.write_if_changed(os.path.join(outdir, f"gcls_{info['name']}.hip"), wrapper(info["name"]))
+        g.write_if_changed(os.path.join(outdir, f"gcls_{info['name']}.hip"), wrapper(info["name"], info["lanes"], info["ws"]))
     g.write_if_changed(os.path.join(outdir, "jk_grad_table.hip"), table(names, infos))
     g.write_if_changed(os.path.join(outdir, "grad_classes.json"), json.dumps(infos, indent=1))
     return infos

@@ -296,5 +296,6 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
 void launch_grad(int cls, int fp32, const GradLaunch& a, hipStream_t s);
 int grad_ws_elems(int cls);
 int grad_lanes(int cls);
+int grad_lane_mask(int cls);
 
 }  // namespace jk

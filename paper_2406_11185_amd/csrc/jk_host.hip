@@ -706,18 +706,17 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
     const int cls = quartet_class(P.bin_cls[P.bp_x[bp]], P.bin_cls[P.bp_y[bp]]);
     const int gmax = grad ? grad_lanes(cls) : class_lanes(cls);
     for (int pr = 0; pr < 2; ++pr) {
-      // several lanes per quartet only when the launch would otherwise be
-      // short of wavefronts
       // the fewest lanes per quartet that still give kTargetWaves/2 wavefronts
       const unsigned long long q = S.qstat[3 * bp + pr];
+      // (gradient: and whose workspace still lets kTargetWaves/2 wavefronts run)
       int lanes = gmax;
-      if (!grad) {
-        const int mask = class_lane_mask(cls);
-        for (int g = 1; g <= gmax; g *= 2) {
-          if (!(mask & (1 << g))) continue;
-          lanes = g;
-          if (q * g >= static_cast<unsigned long long>(kWave) * (kTargetWaves / 2)) break;
-        }
+      const int mask = grad ? grad_lane_mask(cls) : class_lane_mask(cls);
+      for (int g = 1; g <= gmax; g *= 2) {
+        if (!(mask & (1 << g))) continue;
+        const size_t ws = grad ? size_t(kWave / g) * grad_ws_elems(cls) * (pr ? 4 : 8) : 0;
+        if (g < gmax && ws && kWsBudget / ws < static_cast<size_t>(kTargetWaves / 2)) continue;
+        lanes = g;
+        if (q * g >= static_cast<unsigned long long>(kWave) * (kTargetWaves / 2)) break;
       }
       S.lanes[pr * nbp + bp] = lanes;
       const int qpw = kWave / lanes;  // kets per wave step
