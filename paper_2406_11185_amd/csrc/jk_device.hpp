@@ -134,8 +134,8 @@ __device__ __forceinline__ float rsqrt_f32(float x) {
 // asymptotic F_0 = sqrt(pi/(4T)) and upward recursion F_{m+1} = (2m+1)/(2T) F_m
 // (the dropped e^{-T} terms are below 1e-15 relative there for m <= 10).
 // Both forms are evaluated and selected per lane, so a wavefront with mixed T
-// does not diverge.  The table row is fetched by a separate call so that the
-// load can be issued one primitive quartet ahead of its use.
+// does not diverge.  The table row is fetched by a separate call from its
+// evaluation.
 struct BoysRow64 {
   double2 q0, q1, q2, q3;   // F_L(T_i) ... F_{L+6}(T_i), exp(-T_i)
   double x;                 // T_i - T
@@ -159,21 +159,24 @@ __device__ __forceinline__ void boys64_eval(double T, const BoysRow64& row, doub
   const double x = row.x;
   const double r[8] = {row.q0.x, row.q0.y, row.q1.x, row.q1.y,
                        row.q2.x, row.q2.y, row.q3.x, row.q3.y};
+  // Horner steps with x/k, shared by the Taylor series of F_L and of e^{x}
+  const double x2 = x * 0.5, x3 = x * (1.0 / 3.0), x4 = x * 0.25, x5 = x * 0.2,
+               x6 = x * (1.0 / 6.0);
   double s = r[6];
-  s = r[5] + x * s * (1.0 / 6.0);
-  s = r[4] + x * s * (1.0 / 5.0);
-  s = r[3] + x * s * 0.25;
-  s = r[2] + x * s * (1.0 / 3.0);
-  s = r[1] + x * s * 0.5;
+  s = r[5] + x6 * s;
+  s = r[4] + x5 * s;
+  s = r[3] + x4 * s;
+  s = r[2] + x3 * s;
+  s = r[1] + x2 * s;
   s = r[0] + x * s;
   double Ft[L + 1];
   Ft[L] = s;
   if constexpr (L > 0) {
-    double e = 1.0 + x * (1.0 / 6.0);
-    e = 1.0 + x * 0.2 * e;
-    e = 1.0 + x * 0.25 * e;
-    e = 1.0 + x * (1.0 / 3.0) * e;
-    e = 1.0 + x * 0.5 * e;
+    double e = 1.0 + x6;
+    e = 1.0 + x5 * e;
+    e = 1.0 + x4 * e;
+    e = 1.0 + x3 * e;
+    e = 1.0 + x2 * e;
     e = 1.0 + x * e;
     e *= r[7];
     const double T2 = 2.0 * Tt;
@@ -530,14 +533,6 @@ __device__ __forceinline__ void group_sum_all(T (&acc)[N]) {
   }
 }
 
-// A zero the compiler cannot see through: indexing a private array with it
-// keeps the array in scratch memory instead of registers.
-__device__ __forceinline__ int opaque_zero() {
-  int z;
-  asm volatile("s_mov_b32 %0, 0" : "=s"(z));
-  return z;
-}
-
 // Sum over the wavefront; the result is complete in lane kWaveSumLane only.
 // Row sums by DPP, then row 0 is added into row 1 and rows 0-1 into rows 2-3
 // (row broadcasts of lanes 15 and 31).
@@ -858,7 +853,7 @@ __global__ __launch_bounds__(kBlock) void schwarz_kernel(const EriLaunch a, doub
 // ---------------------------------------------------------------------------------
 // Multi-pass form for the classes with many contracted intermediates.  Pass J
 // accumulates [e0|f0] for every e and a chunk of f in registers over the whole
-// primitive loop and parks the chunk in a private (scratch) array; the
+// primitive loop and parks the chunk in the wavefront's workspace; the
 // horizontal recurrences then run as short loops: the ket step for one e at a
 // time into X[e][cd], the bra step plus digestion for one (c, d) at a time.
 template <class C, typename T, int G, int J, class A>

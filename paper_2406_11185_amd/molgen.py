@@ -189,6 +189,28 @@ def workload(name: str) -> Molecule:
                          n_dm=w["n_dm"])
 
 
+def ragged_molecule(n_heavy: int, n_h: int, seed: int, counts=(1, 2, 4, 8)) -> Molecule:
+    """Edge case for the contraction loops: the geometry and density of
+    make_molecule, but every shell redrawn with a primitive count taken from
+    `counts` (up to the library's maximum of 8), exponents a0 * 3^k."""
+    base = make_molecule(n_heavy, n_h, seed)
+    rng = np.random.default_rng([seed, 77])
+    nps, exps, coefs = [], [], []
+    for l in base.shell_l:
+        k = int(rng.choice(counts))
+        e = rng.uniform(0.1, 0.5) * 3.0 ** np.arange(k)
+        nps.append(k)
+        exps.append(e)
+        coefs.append(normalise(int(l), e, rng.uniform(0.2, 1.0, k)))
+    nps = np.array(nps, np.int32)
+    return Molecule(xyz=base.xyz, Z=base.Z, shell_atom=base.shell_atom, shell_l=base.shell_l,
+                    shell_nprim=nps,
+                    shell_prim0=np.concatenate([[0], np.cumsum(nps)[:-1]]).astype(np.int32),
+                    exps=np.concatenate(exps).astype(np.float64),
+                    coefs=np.concatenate(coefs).astype(np.float64),
+                    name=f"r{n_heavy}_{n_h}_{seed}").with_D(base.D)
+
+
 def small_molecule(n_heavy: int, n_h: int, seed: int, n_dm: int = 1) -> Molecule:
     """Extra parity cases between the named workloads (same recipe)."""
     return make_molecule(n_heavy, n_h, seed, None, name=f"m{n_heavy}_{n_h}_{seed}", n_dm=n_dm)

@@ -42,6 +42,20 @@ def test_small_molecules_full(nh, nH, seed, tol):
     assert np.abs(K - Ko).max() <= TOL_ABS
 
 
+@pytest.mark.parametrize("nh,nH,seed,tol", [(2, 3, 5, 0.0), (3, 2, 9, 1e-8)])
+def test_ragged_contraction_lengths(nh, nH, seed, tol):
+    """Shells of 1, 2, 4 and 8 primitives (the library maximum): bins of 1 to 64
+    primitive pairs, bra and ket bins of different lengths."""
+    mol = molgen.ragged_molecule(nh, nH, seed)
+    say(f"case {mol.name} ({mol.n_bf} functions, primitives {sorted(set(mol.shell_nprim.tolist()))},"
+        f" tol {tol})")
+    J, K = gpu_jk(mol, tol)
+    Jo, Ko, _ = oracle.jk(mol, tol)
+    say("  max|dJ| =", np.abs(J - Jo).max(), " max|dK| =", np.abs(K - Ko).max())
+    assert np.abs(J - Jo).max() <= TOL_ABS
+    assert np.abs(K - Ko).max() <= TOL_ABS
+
+
 def test_multiple_densities_share_one_pass():
     mol = molgen.make_molecule(2, 2, 11, n_dm=3)
     say(f"case n_dm=3 ({mol.n_bf} functions)")
@@ -63,6 +77,20 @@ def test_w30_sampled_blocks():
         assert np.abs(gk - ok).max() <= TOL_ABS
     np.testing.assert_allclose(J, J.transpose(0, 2, 1), atol=1e-13)
     np.testing.assert_allclose(K, K.transpose(0, 2, 1), atol=1e-13)
+
+
+def test_w120_sampled_blocks():
+    """The 1080-function molecule in FP64 at tol 1e-10, in the launch configuration
+    of the benchmark's extra measurement: sampled blocks against the oracle."""
+    mol = molgen.workload("w120")
+    say("case w120 (1080 functions, tol 1e-10, FP64), sampled blocks")
+    J, K = gpu_jk(mol, 1e-10)
+    pairs = sample_pairs(mol, 4, seed=120)
+    ref = oracle.jk_blocks(mol, 1e-10, pairs)
+    for (m, n), gj, gk, (oj, ok) in zip(pairs, blocks_of(mol, J, pairs), blocks_of(mol, K, pairs), ref):
+        say(f"  block ({m},{n}) dJ={np.abs(gj - oj).max():.2e} dK={np.abs(gk - ok).max():.2e}")
+        assert np.abs(gj - oj).max() <= TOL_ABS
+        assert np.abs(gk - ok).max() <= TOL_ABS
 
 
 def test_w30_rank_one_identity():
