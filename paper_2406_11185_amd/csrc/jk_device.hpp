@@ -859,10 +859,11 @@ __global__ __launch_bounds__(kBlock) void schwarz_kernel(const EriLaunch a, doub
 template <class C, typename T, int G, int J, class A>
 __device__ __forceinline__ void split_passes(const EriLaunch& a, int i, int k, int sub, T ACx,
                                              T ACy, T ACz, A cacc, int z) {
-  constexpr int NFJ = C::template Pass<J>::NF, F0 = C::template Pass<J>::F0;
-  T acc[C::NE * NFJ];
+  // pass J accumulates the rows e = E0 .. E0+NEJ-1 of the contracted [e0|f0]
+  constexpr int NEJ = C::template Pass<J>::NE, E0 = C::template Pass<J>::E0;
+  T acc[NEJ * C::NF];
 #pragma unroll
-  for (int t = 0; t < C::NE * NFJ; ++t) acc[t] = T(0);
+  for (int t = 0; t < NEJ * C::NF; ++t) acc[t] = T(0);
   contract<C::L, T, G>(a, global_boys<C::L, T>(a), i, k, sub, ACx, ACy, ACz,
                                       [&](const T* F, const VrrCoef<T>& c) {
     C::template vrr_pass<J, T>(F, c, acc);
@@ -870,9 +871,7 @@ __device__ __forceinline__ void split_passes(const EriLaunch& a, int i, int k, i
   group_sum_all<G>(acc);
   if (sub == 0) {  // the group's first lane carries the quartet from here on
 #pragma unroll
-    for (int e = 0; e < C::NE; ++e)
-#pragma unroll
-      for (int f = 0; f < NFJ; ++f) cacc[z + e * C::NF + F0 + f] = acc[e * NFJ + f];
+    for (int t = 0; t < NEJ * C::NF; ++t) cacc[z + E0 * C::NF + t] = acc[t];
   }
   if constexpr (J + 1 < C::NPASS) split_passes<C, T, G, J + 1, A>(a, i, k, sub, ACx, ACy, ACz, cacc, z);
 }

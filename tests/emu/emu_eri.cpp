@@ -96,10 +96,10 @@ static void block_single(const Sh& a, const Sh& b, const Sh& c, const Sh& d, dou
 
 template <class C, int J>
 static void passes(const Sh& a, const Sh& b, const Sh& c, const Sh& d, double* cacc) {
-  constexpr int NFJ = C::template Pass<J>::NF, F0 = C::template Pass<J>::F0;
-  double acc[C::NE * NFJ] = {0};
+  constexpr int NEJ = C::template Pass<J>::NE, E0 = C::template Pass<J>::E0;
+  double acc[NEJ * C::NF] = {0};
   contract<C>(a, b, c, d, [&](const double* F, const VrrCoef<double>& cf) { C::template vrr_pass<J, double>(F, cf, acc); });
-  for (int e = 0; e < C::NE; ++e) for (int f = 0; f < NFJ; ++f) cacc[e * C::NF + F0 + f] = acc[e * NFJ + f];
+  for (int t = 0; t < NEJ * C::NF; ++t) cacc[E0 * C::NF + t] = acc[t];
   if constexpr (J + 1 < C::NPASS) passes<C, J + 1>(a, b, c, d, cacc);
 }
 
