@@ -830,9 +830,15 @@ void dispatch(jk_ctx* c, const Plan& P, const Setup& S, hipStream_t s, jk_stats&
   }
   std::stable_sort(recs.begin(), recs.end(),
                    [](const LaunchRec& a, const LaunchRec& b) { return a.cost > b.cost; });
-  std::vector<int> where(recs.size());
+  // The launch with the most estimated work runs alone on the caller's stream,
+  // with the whole GPU, and its timing events bracket its own run time; the
+  // others follow on the internal streams (largest first, each to the least
+  // loaded), where launches of different classes share the GPU.  The first
+  // launch uses stream 0's workspace, which stream 0 touches only after it.
+  std::vector<int> where(recs.size(), 0);
   double load[jk_ctx::kStreams] = {};
-  for (size_t q = 0; q < recs.size(); ++q) {
+  const size_t q0 = recs.empty() ? 0 : 1;
+  for (size_t q = q0; q < recs.size(); ++q) {
     int k = 0;
     for (int j = 1; j < jk_ctx::kStreams; ++j)
       if (load[j] < load[k]) k = j;
@@ -845,12 +851,15 @@ void dispatch(jk_ctx* c, const Plan& P, const Setup& S, hipStream_t s, jk_stats&
   hipLaunchKernelGGL(fill_kernel<int>, dim3(grid_of(std::max<size_t>(recs.size(), 1), 256)),
                      dim3(256), 0, s, recs.size(), next);
   HIP_OK(hipGetLastError());
-  HIP_OK(hipEventRecord(c->fork_ev, s));
-  for (int k = 0; k < jk_ctx::kStreams; ++k) HIP_OK(hipStreamWaitEvent(c->streams[k], c->fork_ev, 0));
   for (size_t q = 0; q < recs.size(); ++q) {
     const LaunchRec& r = recs[q];
     const int k = where[q];
-    hipStream_t ls = c->streams[k];
+    if (q == q0) {
+      HIP_OK(hipEventRecord(c->fork_ev, s));
+      for (int j = 0; j < jk_ctx::kStreams; ++j)
+        HIP_OK(hipStreamWaitEvent(c->streams[j], c->fork_ev, 0));
+    }
+    hipStream_t ls = q < q0 ? s : c->streams[k];
     size_t e0 = 0;
     if (c->timed) e0 = event(c, ls);
     launch_one(r, ls, k, next + q);
@@ -861,10 +870,11 @@ void dispatch(jk_ctx* c, const Plan& P, const Setup& S, hipStream_t s, jk_stats&
     }
     (r.pr ? st.launches_fp32 : st.launches_fp64)[r.cls] += 1;
   }
-  for (int k = 0; k < jk_ctx::kStreams; ++k) {
-    HIP_OK(hipEventRecord(c->join_ev[k], c->streams[k]));
-    HIP_OK(hipStreamWaitEvent(s, c->join_ev[k], 0));
-  }
+  if (recs.size() > q0)
+    for (int k = 0; k < jk_ctx::kStreams; ++k) {
+      HIP_OK(hipEventRecord(c->join_ev[k], c->streams[k]));
+      HIP_OK(hipStreamWaitEvent(s, c->join_ev[k], 0));
+    }
 }
 
 int check_opts(const jk_opts* o, jk_opts* out, std::string* msg) {
