@@ -26,6 +26,15 @@ constexpr int kMaxItemChunks = 16;   // a work item covers 1..16 wave-wide ket c
 #define JK_TARGET_WAVES 8192
 #endif
 constexpr int kTargetWaves = JK_TARGET_WAVES;   // aim for this many work items per class launch
+#ifndef JK_SPLIT_TARGET_WAVES
+#define JK_SPLIT_TARGET_WAVES (JK_TARGET_WAVES / 4)
+#endif
+// multi-pass classes: wavefronts their lane count aims for.  They run one
+// wavefront per SIMD, so fewer fill the chip, and fewer lanes per quartet mean
+// fewer cross-lane sums of the pass accumulators (measured on gfx950 for the
+// 270-function molecule: (dd|dp) 3.25 -> 2.08 ms with 4 instead of 16 lanes at
+// 2048; at 1024 (dp|dp) and (dd|ds) lose more than that)
+constexpr int kSplitTargetWaves = JK_SPLIT_TARGET_WAVES;
 
 // primitive-pair fields
 enum : int { kP = 0, kOo2p = 1, kPAx = 2, kPAy = 3, kPAz = 4, kKt = 5, kTwoA = 6, kTwoB = 7,

@@ -711,12 +711,14 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
       // (gradient: and whose workspace still lets kTargetWaves/2 wavefronts run)
       int lanes = gmax;
       const int mask = grad ? grad_lane_mask(cls) : class_lane_mask(cls);
+      const bool split = !grad && split_ws_bytes(cls, pr, 1) != 0;
+      const unsigned long long want = split ? kSplitTargetWaves : kTargetWaves / 2;
       for (int g = 1; g <= gmax; g *= 2) {
         if (!(mask & (1 << g))) continue;
         const size_t ws = grad ? size_t(kWave / g) * grad_ws_elems(cls) * (pr ? 4 : 8) : 0;
         if (g < gmax && ws && kWsBudget / ws < static_cast<size_t>(kTargetWaves / 2)) continue;
         lanes = g;
-        if (q * g >= static_cast<unsigned long long>(kWave) * (kTargetWaves / 2)) break;
+        if (q * g >= static_cast<unsigned long long>(kWave) * want) break;
       }
       S.lanes[pr * nbp + bp] = lanes;
       const int qpw = kWave / lanes;  // kets per wave step

@@ -214,3 +214,22 @@ def ragged_molecule(n_heavy: int, n_h: int, seed: int, counts=(1, 2, 4, 8)) -> M
 def small_molecule(n_heavy: int, n_h: int, seed: int, n_dm: int = 1) -> Molecule:
     """Extra parity cases between the named workloads (same recipe)."""
     return make_molecule(n_heavy, n_h, seed, None, name=f"m{n_heavy}_{n_h}_{seed}", n_dm=n_dm)
+
+
+def single_bin_molecule(n_h: int, seed: int) -> Molecule:
+    """Edge case for the launch schedule: the H atoms of make_molecule with only
+    their first s shell each, so that every shell pair has the same class and
+    primitive count and a build makes exactly one class launch.  The density
+    follows the same recipe (one occupied orbital per two functions)."""
+    base = make_molecule(0, n_h, seed, heavy_z=[])
+    keep = [s for s in range(base.n_shells)
+            if base.shell_l[s] == 0 and (s == 0 or base.shell_atom[s - 1] != base.shell_atom[s])]
+    keep = np.array(keep, dtype=np.int64)
+    rng = np.random.default_rng([seed, 91])
+    nbf = len(keep)
+    mol = Molecule(xyz=base.xyz, Z=base.Z, shell_atom=base.shell_atom[keep].astype(np.int32),
+                   shell_l=base.shell_l[keep].astype(np.int32),
+                   shell_nprim=base.shell_nprim[keep].astype(np.int32),
+                   shell_prim0=base.shell_prim0[keep].astype(np.int32),
+                   exps=base.exps, coefs=base.coefs, name=f"s{n_h}_{seed}")
+    return mol.with_D(density(nbf, max(1, nbf // 2), rng))

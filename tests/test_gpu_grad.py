@@ -96,3 +96,14 @@ def test_autograd_function():
         fd = float((Ep - Em) / (2 * eps))
         an = float((D.grad * P).sum())
         assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
+
+
+def test_single_launch_gradient():
+    """One gradient class launch (all shell pairs in one bin)."""
+    mol = molgen.single_bin_molecule(7, 13)
+    say(f"case grad single launch s7_13 ({mol.n_bf} functions, tol 0)")
+    G = gpu_grad(mol, 0.0)
+    Go = oracle.grad(mol, 0.0)
+    say("  max|dG| =", np.abs(G - Go).max())
+    assert np.abs(G - Go).max() <= 1e-9
+    np.testing.assert_allclose(G.sum(axis=1), 0.0, atol=1e-10)

@@ -133,3 +133,23 @@ def test_argument_errors_leave_outputs_untouched():
     with pytest.raises(jkb.JkError) as e:
         jkb.jk_build(ctx, b, D, J, K, 0.0, jkb.make_opts(max_scratch_bytes=1024))
     assert e.value.code == jkb.JK_ENOMEM
+
+
+def test_single_launch_build():
+    """Every shell pair in one bin: the build makes a single class launch, which
+    runs alone on the caller's stream with no fork to the internal streams."""
+    import torch
+    from paper_2406_11185_amd import jk as jkb
+    mol = molgen.single_bin_molecule(7, 13)
+    say(f"case single launch s7_13 ({mol.n_bf} functions, tol 0)")
+    ctx = jkb.Context(0)
+    D = torch.as_tensor(np.ascontiguousarray(mol.D), device="cuda")
+    J, K = jkb.jk(mol, D, 0.0, timing=True, ctx=ctx)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    assert sum(st.launches_fp64) + sum(st.launches_fp32) == 1
+    Jo, Ko, _ = oracle.jk(mol, 0.0)
+    dJ, dK = np.abs(J.cpu().numpy() - Jo).max(), np.abs(K.cpu().numpy() - Ko).max()
+    say("  max|dJ| =", dJ, " max|dK| =", dK)
+    assert dJ <= TOL_ABS and dK <= TOL_ABS
+    ctx.close()
