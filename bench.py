@@ -12,7 +12,7 @@ already resident in device memory.  The default workload is the 30-atom,
 Prints one JSON line.  `value` is screened quartets per second (unique shell
 quartets that pass the Schwarz screen, per build).  `roofline` describes the
 kernel with the most algorithmic work, which the library runs alone before
-spreading the other classes over two streams: algorithmic work per launch (flops
+spreading the other classes over three streams: algorithmic work per launch (flops
 of the generated recurrence, horizontal-recurrence and digestion code per
 quartet, plus a fixed count per primitive quartet for the Boys function and
 prefactors) divided by its mean launch time from HIP events recorded on the

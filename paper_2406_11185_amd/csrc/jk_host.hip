@@ -398,9 +398,11 @@ struct jk_ctx {
   void* host_pinned = nullptr;
   size_t host_pinned_bytes = 0;
 #ifndef JK_STREAMS
-#define JK_STREAMS 2
+#define JK_STREAMS 3
 #endif
-  static constexpr int kStreams = JK_STREAMS;   // class launches are spread over these
+  // class launches are spread over these (measured on gfx950 for the 270-function
+  // molecule: 1 stream 33.5 ms, 2 streams 29.1 ms, 3 streams 28.8 ms per build)
+  static constexpr int kStreams = JK_STREAMS;
   hipStream_t streams[kStreams] = {};
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kStreams] = {};
