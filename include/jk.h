@@ -89,9 +89,27 @@ typedef struct {
   double boys_fp64_T;         /* FP32 kernels evaluate F_m(T) in FP64 for T > this value;
                                  0 < value <= 30 (default 30)                            */
   int32_t n_dm;               /* densities in D/J/K (or dEdR), 1..JK_MAX_NDM (default 1) */
-  int32_t deterministic;      /* must be 0: results are summed with device atomics      */
+  int32_t deterministic;      /* 0 (default): J, K and dE/dR are summed with FP64 device
+                                 atomics, so the last bits can differ between runs.
+                                 1: every contribution is added as a two-word fixed-point
+                                 integer (order-independent sums); results are bitwise
+                                 reproducible and agree with mode 0 to ~1e-13 relative.
+                                 Every accumulated element and every single contribution
+                                 must stay below 2^31 in magnitude.                     */
   int32_t timing;             /* 1: time each integral kernel with HIP events (stats)    */
   uint64_t max_scratch_bytes; /* 0 = no limit; else JK_ENOMEM if more scratch is needed */
+  int32_t acc_copies;         /* jk_build: accumulator copies of J and K that the
+                                 integral kernels spread their atomic adds over; 0
+                                 (default) = the library's choice (up to 8 within 256 MB),
+                                 1..8 = exactly that many (1: J and K themselves)        */
+  int32_t serial;             /* 1: every class launch goes to the caller's stream in turn,
+                                 so each kernel runs alone (default 0: after the largest
+                                 launch, the rest are spread over three internal streams) */
+  double* energy;             /* jk_build, optional (NULL = not written): DEVICE pointer to
+                                 [n_dm][3] receiving E_J = 1/2 tr(D J), E_K = 1/4 tr(D K)
+                                 and E = E_J - E_K, summed in a fixed order             */
+  double* dEdD;               /* jk_build, optional (NULL = not written): DEVICE pointer to
+                                 [n_dm][n_bf][n_bf] receiving dE/dD = J - K/2            */
 } jk_opts;
 
 /* Counters of the last jk_build / jk_grad on a context. */
@@ -135,8 +153,10 @@ int jk_build(jk_ctx* ctx, const jk_basis* basis, const double* D, double* J, dou
              double tol, const jk_opts* opts, void* hip_stream);
 
 /* Nuclear gradient of E = 1/2 tr(D J) - 1/4 tr(D K) at fixed D (basis functions
- * move with their atoms), under the same screening rule as jk_build.  Writes
- * dEdR ([n_dm][n_atoms][3], device, hartree/bohr). */
+ * move with their atoms), under the same screening rule as jk_build: the
+ * two-electron part of the single-point force, one of the core tasks in the
+ * paper's "Tasks" section.  Writes dEdR ([n_dm][n_atoms][3], device,
+ * hartree/bohr).  opts->acc_copies, opts->energy and opts->dEdD are ignored. */
 int jk_grad(jk_ctx* ctx, const jk_basis* basis, const double* D, double* dEdR, double tol,
             const jk_opts* opts, void* hip_stream);
 

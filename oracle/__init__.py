@@ -6,7 +6,8 @@ arithmetic lives in md_oracle.cpp (McMurchie-Davidson integrals, own Boys
 function, plain digestion); this module only marshals numpy arrays.
 
 Parity status of each entry point (what pins it is listed in the tests):
-  boys, prim_eri, shell_quartet, schwarz, jk, jk_blocks, grad  -- pinned
+  boys, prim_eri, shell_quartet, schwarz, jk, jk_blocks, jk_bra_sample, grad,
+  screen_counts  -- pinned
 """
 from __future__ import annotations
 
@@ -45,7 +46,10 @@ def _load():
     lib.orc_jk_blocks.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_double,
                                   ctypes.c_int, _ip, _ip, _dp, _dp, ctypes.c_int]
     lib.orc_grad.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_double, _dp,
-                             ctypes.c_int, ctypes.c_longlong]
+                             ctypes.c_int, ctypes.c_longlong, _ip]
+    _llp = ctypes.POINTER(ctypes.c_longlong)
+    lib.orc_screen_counts.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, _llp,
+                                      _llp]
     lib.orc_jk_bra_sample.restype = ctypes.c_longlong
     lib.orc_jk_bra_sample.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_double,
                                       ctypes.c_int, _ip, _dp, _dp, ctypes.c_int]
@@ -163,12 +167,20 @@ def jk_blocks(mol, tol: float, pairs, D=None, nthreads: int = 0):
     return out
 
 
-def grad(mol, tol: float, D=None, nthreads: int = 0, bra_pairs: int = -1):
-    """dE/dR ([n_dm][n_atoms][3]) of E = 1/2 tr(DJ) - 1/4 tr(DK) at fixed D."""
+def grad(mol, tol: float, D=None, nthreads: int = 0, bra_pairs: int = -1, atoms=None):
+    """dE/dR ([n_dm][n_atoms][3]) of E = 1/2 tr(DJ) - 1/4 tr(DK) at fixed D.
+
+    atoms: optional list of atom indices; only their rows are computed (exactly),
+    the other rows are left zero."""
     b = Basis(mol)
     D = _dm(mol.D if D is None else D)
     G = np.zeros((D.shape[0], b.n_atoms, 3))
-    rc = _load().orc_grad(b.h, D.shape[0], _pd(D), float(tol), _pd(G), nthreads, bra_pairs)
+    sel = None
+    if atoms is not None:
+        sel = np.zeros(b.n_atoms, dtype=np.int32)
+        sel[np.asarray(atoms, dtype=np.int64)] = 1
+    rc = _load().orc_grad(b.h, D.shape[0], _pd(D), float(tol), _pd(G), nthreads, bra_pairs,
+                          _pi(sel) if sel is not None else None)
     if rc != 0:
         raise ValueError("oracle gradient: unsupported number of densities")
     return G
@@ -184,6 +196,21 @@ def jk_bra_sample(mol, tol: float, bra_idx, D=None, nthreads: int = 0):
     kept = _load().orc_jk_bra_sample(b.h, D.shape[0], _pd(D), float(tol), idx.shape[0],
                                      _pi(idx), _pd(J), _pd(K), nthreads)
     return J, K, int(kept)
+
+
+def screen_counts(mol, tol: float, thr: float = 0.0):
+    """Per quartet class (index X(X+1)/2 + Y over pair classes ss, ps, pp, ds, dp, dd):
+    counts [21][3] of double-precision (S >= thr), single-precision (tol <= S < thr)
+    and skipped (S < tol) unique quartets, and near [21], the quartets whose bound S
+    is within a relative 1e-12 of tol or thr.  thr = 0: every kept quartet counts
+    as double precision."""
+    b = Basis(mol)
+    counts = np.zeros((21, 3), dtype=np.int64)
+    near = np.zeros(21, dtype=np.int64)
+    llp = ctypes.POINTER(ctypes.c_longlong)
+    _load().orc_screen_counts(b.h, float(tol), float(thr), counts.ctypes.data_as(llp),
+                              near.ctypes.data_as(llp))
+    return counts, near
 
 
 def energy(J, K, D):

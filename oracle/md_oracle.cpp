@@ -459,9 +459,14 @@ int orc_jk_blocks(void* h, int n_dm, const double* D, double tol, int nblk, cons
 // and a primitive derivative d/dA_x [x_A^i e^{-a x_A^2}] = 2a x_A^{i+1} e - i x_A^{i-1} e.
 // All four centres are differentiated explicitly.  dEdR: [n_dm][n_atoms][3].
 // If bra_pairs >= 0, only the first bra_pairs unique bra pairs are visited
-// (a bounded sample used for timing).
+// (a bounded sample used for timing).  If atom_sel is not NULL ([n_atoms]
+// flags), only the derivatives with respect to the selected atoms are formed:
+// a quartet enters only if one of its shells sits on a selected atom, and only
+// the centres on selected atoms are differentiated (the other entries of dEdR
+// stay zero).  dE/dR_X only depends on the quartets with a shell on X, so the
+// selected entries equal those of the full gradient.
 int orc_grad(void* h, int n_dm, const double* D, double tol, double* dEdR, int nthreads,
-             long long bra_pairs) {
+             long long bra_pairs, const int* atom_sel) {
   const Basis& bs = *static_cast<Basis*>(h);
   if (n_dm < 1 || n_dm > 16) return -1;
   const int n = bs.n_bf, ns = bs.n_shells, na_ = bs.n_atoms;
@@ -483,6 +488,9 @@ int orc_grad(void* h, int n_dm, const double* D, double tol, double* dEdR, int n
       for (long long qi = 0; qi <= pi; ++qi) {
         const int C = pairs[qi].A, Dd = pairs[qi].B;
         if (Q[(size_t)A * ns + B] * Q[(size_t)C * ns + Dd] < tol) continue;
+        if (atom_sel && !atom_sel[bs.atom[A]] && !atom_sel[bs.atom[B]] && !atom_sel[bs.atom[C]] &&
+            !atom_sel[bs.atom[Dd]])
+          continue;
         double f = 8.0;
         if (A == B) f *= 0.5;
         if (C == Dd) f *= 0.5;
@@ -523,6 +531,7 @@ int orc_grad(void* h, int n_dm, const double* D, double tol, double* dEdR, int n
                         for (int cen = 0; cen < 4; ++cen) {
                           const double ex = bs.exps[ip[cen]];
                           const int atom = bs.atom[sh[cen]];
+                          if (atom_sel && !atom_sel[atom]) continue;
                           for (int x = 0; x < 3; ++x) {
                             int sp[4][3];
                             for (int k = 0; k < 4; ++k)
@@ -606,6 +615,54 @@ long long orc_jk_bra_sample(void* h, int n_dm, const double* D, double tol, int 
     for (size_t i = 0; i < aj.size(); ++i) { J[i] += aj[i]; K[i] += ak[i]; }
   }
   return kept;
+}
+
+// Screening and precision decisions of every symmetry-unique shell quartet
+// (pair AB >= pair CD, the pairs numbered as in orc_jk), from S = Q_AB Q_CD:
+// skipped if S < tol, single precision if tol <= S < thr, double precision if
+// S >= thr (paper, "Electron Repulsion Integrals" paragraph, third item).  The
+// counts are kept per quartet class: each pair has a class by its two angular
+// momenta (l1 >= l2 ordered as ss, ps, pp, ds, dp, dd = 0..5); a quartet's class
+// index is X (X+1)/2 + Y for its larger pair class X and smaller Y.
+// counts[21][3] = {double, single, skipped}; near[21] counts the quartets
+// whose S lies within a relative 1e-12 of tol or thr (where a different
+// rounding of Q could flip the decision).
+int orc_screen_counts(void* h, double tol, double thr, long long* counts, long long* near) {
+  const Basis& bs = *static_cast<Basis*>(h);
+  const int ns = bs.n_shells;
+  const std::vector<double> Q = schwarz(bs);
+  const std::vector<PairIdx> pairs = unique_pairs(ns);
+  const long long npair = (long long)pairs.size();
+  std::vector<int> pcls(npair);
+  std::vector<double> pq(npair);
+  for (long long i = 0; i < npair; ++i) {
+    const int l1 = std::max(bs.l[pairs[i].A], bs.l[pairs[i].B]);
+    const int l2 = std::min(bs.l[pairs[i].A], bs.l[pairs[i].B]);
+    pcls[i] = l1 * (l1 + 1) / 2 + l2;
+    pq[i] = Q[(size_t)pairs[i].A * ns + pairs[i].B];
+  }
+  std::fill(counts, counts + 21 * 3, 0LL);
+  std::fill(near, near + 21, 0LL);
+#pragma omp parallel
+  {
+    std::vector<long long> c(21 * 3, 0), nr(21, 0);
+#pragma omp for schedule(dynamic, 64)
+    for (long long i = 0; i < npair; ++i)
+      for (long long j = 0; j <= i; ++j) {
+        const int X = std::max(pcls[i], pcls[j]), Y = std::min(pcls[i], pcls[j]);
+        const int q = X * (X + 1) / 2 + Y;
+        const double S = pq[i] * pq[j];
+        const int k = S < tol ? 2 : (S < thr ? 1 : 0);
+        ++c[3 * q + k];
+        if (std::fabs(S - tol) <= 1e-12 * tol || std::fabs(S - thr) <= 1e-12 * thr) ++nr[q];
+      }
+#pragma omp critical
+    {
+      for (int t = 0; t < 63; ++t) counts[t] += c[t];
+      for (int t = 0; t < 21; ++t) near[t] += nr[t];
+    }
+  }
+  return 0;
 }
 
 const char* orc_last_error(void) { return g_err; }

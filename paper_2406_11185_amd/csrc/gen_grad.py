@@ -329,12 +329,12 @@ def wrapper(name, gmax, ws):
              f'#include "gcls_{name}.inc"',
              f"void launch_grad_{name}(const GradLaunch& a, int fp32, hipStream_t s) {{",
              "  const dim3 grid((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);",
-             "  const size_t lds = static_cast<size_t>(a.lds_doubles) * sizeof(double);"]
+             "  const size_t lds = a.lds_bytes;"]
     for j, gl in enumerate(opts):
         cond = "true" if j == len(opts) - 1 else f"a.e.lanes == {gl}"
         lines += [f"  {'if' if j == 0 else 'else if'} ({cond}) {{",
-                  f"    if (fp32) hipLaunchKernelGGL((grad_kernel<GCls_{name}, float, {gl}>), grid, block, lds, s, a);",
-                  f"    else hipLaunchKernelGGL((grad_kernel<GCls_{name}, double, {gl}>), grid, block, lds, s, a);",
+                  f"    if (fp32) launch_kernel(&grad_kernel<GCls_{name}, float, {gl}>, grid, block, lds, s, a.e.dry != 0, a);",
+                  f"    else launch_kernel(&grad_kernel<GCls_{name}, double, {gl}>, grid, block, lds, s, a.e.dry != 0, a);",
                   "  }"]
     lines += ["}", "}  // namespace jk", ""]
     return "\n".join(lines)

@@ -289,6 +289,22 @@ class HRR(Code):
         return name
 
 
+# Wavefronts per SIMD each class kernel is compiled for, per precision (FP64 / FP32
+# value size in bytes); classes not listed take 1 (all 512 registers of a lane).
+# JK_WAVES_OVERRIDE="size:waves" (e.g. "4:2") overrides one precision for every
+# class, for measurements.
+CLASS_WAVES = {}
+
+
+def class_waves(name, size):
+    ov = os.environ.get("JK_WAVES_OVERRIDE", "")
+    for item in filter(None, ov.split(",")):
+        sz, w = item.split(":")
+        if int(sz) == size:
+            return int(w)
+    return CLASS_WAVES.get((name, size), 1)
+
+
 def lanes_for(L, split):
     """Most lanes that share one shell quartet: light classes 1, mid classes 4, heavy 16."""
     if split:
@@ -361,6 +377,7 @@ def gen_class(la, lb, lc, ld):
     s.append(f"  static constexpr int NA = {na}, NB = {nb}, NC = {nc}, ND = {nd};")
     s.append(f"  static constexpr int NE = {ne}, NF = {nf}, NACC = {ne * nf};")
     s.append(f"  static constexpr int GMAX = {lanes_for(L, False)};  // most lanes per shell quartet")
+    s.append(f"  static constexpr int WAVES64 = {class_waves(name, 8)}, WAVES32 = {class_waves(name, 4)};")
     s.append(f"  static constexpr int VRR_FLOPS = {vrr_flops}, HRR_FLOPS = {hrr_flops}, "
              f"DIGEST_FLOPS = {dig_flops};")
     s.append("  template <typename T>")
@@ -516,6 +533,7 @@ def gen_split_class(la, lb, lc, ld):
     s.append(f"  static constexpr int NE = {ne}, NF = {nf}, NACC = {ne * nf};")
     s.append(f"  static constexpr int NPASS = {len(chunks)}, ECHUNK = {chunk};")
     s.append(f"  static constexpr int GMAX = {lanes_for(L, True)};  // most lanes per shell quartet")
+    s.append(f"  static constexpr int WAVES64 = {class_waves(name, 8)}, WAVES32 = {class_waves(name, 4)};")
     vrr_flops = 0
     for j, ch in enumerate(chunks):
         outs = [(ii * nf + jf, E[ie], f) for ii, ie in enumerate(ch) for jf, f in enumerate(Fs)]
@@ -589,7 +607,7 @@ def wrapper(info):
     kern = "eri_jk_split_kernel" if info["split"] else "eri_jk_kernel"
     skern = "schwarz_split_kernel" if info["split"] else "schwarz_kernel"
     w = [f"// generated by gen_hgp.py -- do not edit",
-         '#include "jk_device.hpp"',
+         '#include "jk_classes.hpp"',
          "namespace jk {",
          f'#include "cls_{n}.inc"',
          f"void launch_eri_{n}(const EriLaunch& a, int fp32, hipStream_t s) {{",
@@ -603,8 +621,8 @@ def wrapper(info):
             f"    per_cu[fp32] = nb > 0 ? nb : 1;",
             f"  }}",
             f"  const dim3 lgrid(std::min((a.nitems + NT / kWave - 1) / (NT / kWave), per_cu[fp32] * a.num_cu));",
-            f"  if (fp32) hipLaunchKernelGGL((eri_jk_lds_kernel<Cls_{n}, float, NT>), lgrid, dim3(NT), 0, s, a);",
-            f"  else hipLaunchKernelGGL((eri_jk_lds_kernel<Cls_{n}, double, NT>), lgrid, dim3(NT), 0, s, a);",
+            f"  if (fp32) launch_kernel(&eri_jk_lds_kernel<Cls_{n}, float, NT>, lgrid, dim3(NT), 0, s, a.dry != 0, a);",
+            f"  else launch_kernel(&eri_jk_lds_kernel<Cls_{n}, double, NT>, lgrid, dim3(NT), 0, s, a.dry != 0, a);",
             "}"] if info.get("lds") else []),
          *([] if info.get("lds") else [
          "  const int waves = " + ("a.nwaves" if info["split"] else "a.nitems") + ";",
@@ -612,16 +630,16 @@ def wrapper(info):
          *[ln for g_ in info["lane_options"] for ln in (
              f"  {'if' if g_ == info['lane_options'][0] else 'else if'} (a.lanes == {g_} || "
              f"{'true' if g_ == info['lane_options'][-1] else 'false'}) {{",
-             f"    if (fp32) hipLaunchKernelGGL(({kern}<Cls_{n}, float, {g_}>), grid, block, 0, s, a);",
-             f"    else hipLaunchKernelGGL(({kern}<Cls_{n}, double, {g_}>), grid, block, 0, s, a);",
+             f"    if (fp32) launch_kernel(&{kern}<Cls_{n}, float, {g_}>, grid, block, 0, s, a.dry != 0, a);",
+             f"    else launch_kernel(&{kern}<Cls_{n}, double, {g_}>, grid, block, 0, s, a.dry != 0, a);",
              "  }")],
          "}"])]
     if info["bra_class"] == info["ket_class"]:
         w += [f"void launch_schwarz_{n}(const EriLaunch& a, double* Q, hipStream_t s) {{",
-              (f"  hipLaunchKernelGGL(({skern}<Cls_{n}>), dim3((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock),"
-               " dim3(kBlock), 0, s, a, Q);") if info["split"] else
-              (f"  hipLaunchKernelGGL(({skern}<Cls_{n}>), dim3((a.bra.n * Cls_{n}::GMAX + kBlock - 1) / kBlock),"
-               " dim3(kBlock), 0, s, a, Q);"),
+              (f"  launch_kernel(&{skern}<Cls_{n}>, dim3((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock),"
+               " dim3(kBlock), 0, s, false, a, Q);") if info["split"] else
+              (f"  launch_kernel(&{skern}<Cls_{n}>, dim3((a.bra.n * Cls_{n}::GMAX + kBlock - 1) / kBlock),"
+               " dim3(kBlock), 0, s, false, a, Q);"),
               "}"]
     w.append("}  // namespace jk")
     return "\n".join(w) + "\n"

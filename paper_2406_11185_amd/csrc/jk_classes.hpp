@@ -3,6 +3,20 @@
 #include "jk_device.hpp"
 
 namespace jk {
+// Host check run before every kernel launch (jk_host.hip): 0 if the kernel's
+// scratch need fits jk_guard.hpp's budget, else nonzero, with the message kept
+// for the calling entry point (take_guard_error).
+int guard_launch(const void* kernel, unsigned grid_blocks, unsigned block_threads, size_t lds_bytes);
+
+// Launch `k` with `args` after the guard; dry: run the guard only.
+template <typename... P>
+inline void launch_kernel(void (*k)(P...), dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                          bool dry, P... args) {
+  if (guard_launch(reinterpret_cast<const void*>(k), grid.x, block.x, lds) != 0 || dry) return;
+  void* argv[] = {static_cast<void*>(&args)...};
+  (void)hipLaunchKernel(reinterpret_cast<const void*>(k), grid, block, argv, lds, s);
+}
+
 // Integral + digestion kernel of quartet class `cls` (0..20, bra class X >= ket
 // class Y, index X(X+1)/2 + Y over pair classes ss, ps, pp, ds, dp, dd).
 void launch_eri(int cls, int fp32, const EriLaunch& a, hipStream_t s);

@@ -36,6 +36,14 @@ constexpr int kTargetWaves = JK_TARGET_WAVES;   // aim for this many work items 
 // 2048; at 1024 (dp|dp) and (dd|ds) lose more than that)
 constexpr int kSplitTargetWaves = JK_SPLIT_TARGET_WAVES;
 
+// Wavefronts per SIMD a class kernel is compiled for (its register budget:
+// 512 / waves registers per lane), per precision; generated per class as
+// C::WAVES64 / C::WAVES32.
+template <class C, typename T>
+constexpr int class_waves() {
+  return sizeof(T) == 8 ? C::WAVES64 : C::WAVES32;
+}
+
 // primitive-pair fields
 enum : int { kP = 0, kOo2p = 1, kPAx = 2, kPAy = 3, kPAz = 4, kKt = 5, kTwoA = 6, kTwoB = 7,
              kPrimFields = 8 };
@@ -88,6 +96,9 @@ struct EriLaunch {
   int lanes;          // lanes sharing one shell quartet in this launch (1 or the class maximum)
   int* next;          // persistent kernels: next unclaimed work item (zero before the launch)
   int num_cu;         // compute units of the device (grid of the persistent kernels)
+  size_t det_lo;      // 0: J/K accumulate with FP64 atomics; else deterministic mode, the
+                      // accumulators are int64 fixed-point pairs (see atomic_add)
+  int dry;            // host only: 1 = check the launch (scratch guard) without launching
 };
 
 // Persistent kernels: each wavefront claims work items one at a time.
@@ -206,43 +217,32 @@ __device__ __forceinline__ void boys64_eval(double T, const BoysRow64& row, doub
 
 // F_m(T), m = 0..L, for the FP32 kernels.  T <= boys_fp64_T (<= 30): four-term
 // Taylor expansion in FP32 from the FP32 table and downward recursion in FP32.
-// Larger T: evaluated in FP64 (asymptotic F_0, upward recursion with the
-// e^{-T} term taken from the FP64 table) and rounded to FP32.
+// Larger T: the FP64 evaluation above (table Taylor step below T = 64,
+// asymptotic form beyond), rounded to FP32; it is exact to FP64 rounding at
+// any T, so every accepted boys_fp64_T gives FP32-accurate values.
 struct BoysRow32 {
   float4 q0;    // F_L(T_i) ... F_{L+3}(T_i)
   float e;      // exp(-T_i)
   float x;      // T_i - T
-  double e64;   // FP64 branch: exp(-T_j) of the FP64 table (0 beyond it)
-  double x64;   // FP64 branch: T_j - T
 };
 
-// rows: FP32 table of order L; rows64: FP64 table of order L (global).
+// rows: FP32 table of order L.
 template <int L>
-__device__ __forceinline__ BoysRow32 boys32_fetch(float T, float tcut, const float* __restrict__ rows,
-                                                  const double* __restrict__ rows64) {
+__device__ __forceinline__ BoysRow32 boys32_fetch(float T, float tcut, const float* __restrict__ rows) {
   BoysRow32 r;
-  const bool lo = T <= tcut;
-  const float Tl = lo ? T : 0.0f;
+  const float Tl = T <= tcut ? T : 0.0f;
   const int i = static_cast<int>(Tl * kBoys32InvStep + 0.5f);
   const float4* r4 = reinterpret_cast<const float4*>(rows + i * kBoys32Row);
   r.q0 = r4[0];
   r.e = r4[1].x;
   r.x = i * kBoys32Step - Tl;
-  r.e64 = 0.0;
-  r.x64 = 0.0;
-  if constexpr (L > 0) {
-    const double Td = static_cast<double>(T);
-    if (!lo && Td < kBoysTmax) {
-      const int j = static_cast<int>(Td * kBoysInvStep + 0.5);
-      r.x64 = j * kBoysStep - Td;
-      r.e64 = rows64[j * kBoysRow + 7];
-    }
-  }
   return r;
 }
 
+// rows64: FP64 table of order L (global), read only by lanes with T > tcut.
 template <int L>
-__device__ __forceinline__ void boys32_eval(float T, float tcut, const BoysRow32& row, float* F) {
+__device__ __forceinline__ void boys32_eval(float T, float tcut, const BoysRow32& row,
+                                            const double* __restrict__ rows64, float* F) {
   if (T <= tcut) {
     const float x = row.x;
     float s = row.q0.w;
@@ -262,26 +262,11 @@ __device__ __forceinline__ void boys32_eval(float T, float tcut, const BoysRow32
     }
   } else {
     const double Td = static_cast<double>(T);
-    const double rs = rsqrt_f64(Td);
-    double f = 0.88622692545275801364908374167057 * rs;
-    F[0] = static_cast<float>(f);
-    if constexpr (L > 0) {
-      // e^{-T}: table value times e^{x}, zero beyond the table
-      const double x = row.x64;
-      double ex = 1.0 + x * (1.0 / 6.0);
-      ex = 1.0 + x * 0.2 * ex;
-      ex = 1.0 + x * 0.25 * ex;
-      ex = 1.0 + x * (1.0 / 3.0) * ex;
-      ex = 1.0 + x * 0.5 * ex;
-      ex = 1.0 + x * ex;
-      const double e = ex * row.e64;
-      const double h = 0.5 * rs * rs;
+    const BoysRow64 r64 = boys64_fetch(Td, rows64, kBoysTmax);
+    double F64[L + 1];
+    boys64_eval<L>(Td, r64, kBoysTmax, F64);
 #pragma unroll
-      for (int m = 0; m < L; ++m) {
-        f = ((2 * m + 1) * f - e) * h;
-        F[m + 1] = static_cast<float>(f);
-      }
-    }
+    for (int m = 0; m <= L; ++m) F[m] = static_cast<float>(F64[m]);
   }
 }
 
@@ -330,11 +315,11 @@ template <int L>
 struct Boys<L, float> {
   using Row = BoysRow32;
   __device__ __forceinline__ static Row fetch(float T, const BoysTab<float>& t) {
-    return boys32_fetch<L>(T, t.tcut, t.rows, t.rows64);
+    return boys32_fetch<L>(T, t.tcut, t.rows);
   }
   __device__ __forceinline__ static void eval(float T, const Row& r, const BoysTab<float>& t,
                                               float* F) {
-    boys32_eval<L>(T, t.tcut, r, F);
+    boys32_eval<L>(T, t.tcut, r, t.rows64, F);
   }
 };
 
@@ -553,8 +538,27 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ void atomic_add(double* addr, double v) {
-  unsafeAtomicAdd(addr, v);
+// Accumulation into J, K (and dE/dR).  lo_off == 0: one FP64 atomic add, whose
+// rounding depends on the order in which the adds arrive.  lo_off > 0
+// (deterministic mode): the accumulator at addr is a pair of two's-complement
+// int64 words, hi at addr and lo at addr + lo_off elements, standing for
+// hi 2^-32 + lo 2^-62; v is split into those two words and both are added with
+// integer atomics, whose sums do not depend on the order (|v| and every
+// accumulated value below 2^31; per add the lo word loses at most 2^-63).
+constexpr double kFixHi = 4294967296.0;            // 2^32
+constexpr double kFixLo = 1073741824.0;            // 2^30: lo word = 2^62 x the remainder
+__device__ __forceinline__ void atomic_add(double* addr, double v, size_t lo_off) {
+  if (lo_off == 0) {
+    unsafeAtomicAdd(addr, v);
+    return;
+  }
+  const double s = v * kFixHi;
+  const double h = rint(s);
+  const long long hi = static_cast<long long>(h);
+  const long long lo = static_cast<long long>(rint((s - h) * kFixLo));
+  unsigned long long* w = reinterpret_cast<unsigned long long*>(addr);
+  if (hi != 0) atomicAdd(w, static_cast<unsigned long long>(hi));
+  if (lo != 0) atomicAdd(w + lo_off, static_cast<unsigned long long>(lo));
 }
 
 // Scatter of per-quartet integral blocks into J or K with few memory-side
@@ -579,10 +583,11 @@ struct Scatter {
 
 template <int NX, int NY, int Q>
 __device__ __forceinline__ void scatter_block(double* M, size_t n, int rx, int cy,
-                                              const double* blk, bool writer, double* stage) {
+                                              const double* blk, bool writer, double* stage,
+                                              size_t det_lo) {
   using Sc = Scatter<NX, NY, Q>;
   if constexpr (Sc::S == 1) {
-    if (writer && blk[0] != 0.0) atomic_add(&M[static_cast<size_t>(rx) * n + cy], blk[0]);
+    if (writer && blk[0] != 0.0) atomic_add(&M[static_cast<size_t>(rx) * n + cy], blk[0], det_lo);
   } else {
     constexpr int S = Sc::S, R = Sc::R, P = Sc::P, GW = Sc::GW;
     const int lane = threadIdx.x & (kWave - 1);
@@ -607,7 +612,7 @@ __device__ __forceinline__ void scatter_block(double* M, size_t n, int rx, int c
         const int q = q0 + g;
         if (e < S && q < Q) {
           const double v = vals[q * S + e];
-          if (v != 0.0) atomic_add(&M[__builtin_bit_cast(long long, base[q]) + e], v);
+          if (v != 0.0) atomic_add(&M[__builtin_bit_cast(long long, base[q]) + e], v, det_lo);
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -655,7 +660,8 @@ __device__ __forceinline__ void lanes_sync() {
 // value is the sum over its PARTS lanes.  rx and cy are read from the slot's
 // first lane; all lanes take part.
 template <int NX, int NY, int Q, int PARTS>
-__device__ __forceinline__ void scatter_ws(double* M, size_t n, int rx, int cy, const double* w0) {
+__device__ __forceinline__ void scatter_ws(double* M, size_t n, int rx, int cy, const double* w0,
+                                           size_t det_lo) {
   using Sc = Scatter<NX, NY, Q>;
   constexpr int S = Sc::S, R = Sc::R, P = Sc::P, GW = Sc::GW;
   constexpr int G = kWave / Q;
@@ -678,7 +684,7 @@ __device__ __forceinline__ void scatter_ws(double* M, size_t n, int rx, int cy, 
         for (int u = 0; u < PARTS; ++u) v += w0[t * STRIDE + (PARTS == 1 ? q : q * G + u)];
         const size_t at = Sc::TR ? static_cast<size_t>(cyq + r) * n + rxq + e
                                  : static_cast<size_t>(rxq + r) * n + cyq + e;
-        if (v != 0.0) atomic_add(&M[at], v);
+        if (v != 0.0) atomic_add(&M[at], v, det_lo);
       }
     }
   }
@@ -774,24 +780,26 @@ __device__ __forceinline__ void eri_item(const EriLaunch& a, const BoysTab<T>& b
       for (int t = 0; t < C::NA * C::NB; ++t) {
         const double s = wave_sum(jab[t]);
         if (lane == kWaveSumLane)
-          atomic_add(&Jm[(a0 + t / C::NB) * static_cast<size_t>(a.n) + b0 + t % C::NB], 2.0 * s);
+          atomic_add(&Jm[(a0 + t / C::NB) * static_cast<size_t>(a.n) + b0 + t % C::NB], 2.0 * s,
+                     a.det_lo);
       }
 #pragma unroll
       for (int t = 0; t < C::NC * C::ND; ++t) jcd[t] *= 2.0;
       const size_t n = static_cast<size_t>(a.n);
       // every quartet slot is written (out-of-range ones hold zeros, fq = 0)
       const bool writer = sub == 0;
-      scatter_block<C::NC, C::ND, QPW>(Jm, n, c0, d0, jcd, writer, stage);
-      scatter_block<C::NA, C::NC, QPW>(Km, n, a0, c0, kac, writer, stage);
-      scatter_block<C::NA, C::ND, QPW>(Km, n, a0, d0, kad, writer, stage);
-      scatter_block<C::NB, C::NC, QPW>(Km, n, b0, c0, kbc, writer, stage);
-      scatter_block<C::NB, C::ND, QPW>(Km, n, b0, d0, kbd, writer, stage);
+      scatter_block<C::NC, C::ND, QPW>(Jm, n, c0, d0, jcd, writer, stage, a.det_lo);
+      scatter_block<C::NA, C::NC, QPW>(Km, n, a0, c0, kac, writer, stage, a.det_lo);
+      scatter_block<C::NA, C::ND, QPW>(Km, n, a0, d0, kad, writer, stage, a.det_lo);
+      scatter_block<C::NB, C::NC, QPW>(Km, n, b0, c0, kbc, writer, stage, a.det_lo);
+      scatter_block<C::NB, C::ND, QPW>(Km, n, b0, d0, kbd, writer, stage, a.det_lo);
     }
   }
 }
 
 template <class C, typename T, int G>
-__global__ __launch_bounds__(kBlock) void eri_jk_kernel(const EriLaunch a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(class_waves<C, T>())))
+void eri_jk_kernel(const EriLaunch a) {
   constexpr int ST = stage_doubles<C, kWave / G>();
   __shared__ double stage[kWavesPerBlock * ST];
   const int item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
@@ -902,7 +910,8 @@ __device__ __forceinline__ void split_ket_hrr(A cacc, A X, int z, T CDx, T CDy, 
 }
 
 template <class C, typename T, int G>
-__global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(class_waves<C, T>())))
+void eri_jk_split_kernel(const EriLaunch a) {
   constexpr int NCD = C::NC * C::ND;
   constexpr int QPW = kWave / G;
   const int lane = threadIdx.x & (kWave - 1);
@@ -1033,15 +1042,16 @@ __global__ __launch_bounds__(kBlock) void eri_jk_split_kernel(const EriLaunch a)
 #pragma unroll
       for (int t = 0; t < C::NA * C::NB; ++t) {
         const double s = wave_sum(jab[t]);
-        if (lane == kWaveSumLane) atomic_add(&Jm[(a0 + t / C::NB) * n + b0 + t % C::NB], 2.0 * s);
+        if (lane == kWaveSumLane)
+          atomic_add(&Jm[(a0 + t / C::NB) * n + b0 + t % C::NB], 2.0 * s, a.det_lo);
       }
       // out-of-range slots hold zeros (fq = 0); K blocks are summed over the
       // G lanes of each slot
-      scatter_ws<C::NC, C::ND, QPW, 1>(Jm, n, c0, d0, jcd0);
-      scatter_ws<C::NA, C::NC, QPW, G>(Km, n, a0, c0, kac0);
-      scatter_ws<C::NA, C::ND, QPW, G>(Km, n, a0, d0, kad0);
-      scatter_ws<C::NB, C::NC, QPW, G>(Km, n, b0, c0, kbc0);
-      scatter_ws<C::NB, C::ND, QPW, G>(Km, n, b0, d0, kbd0);
+      scatter_ws<C::NC, C::ND, QPW, 1>(Jm, n, c0, d0, jcd0, a.det_lo);
+      scatter_ws<C::NA, C::NC, QPW, G>(Km, n, a0, c0, kac0, a.det_lo);
+      scatter_ws<C::NA, C::ND, QPW, G>(Km, n, a0, d0, kad0, a.det_lo);
+      scatter_ws<C::NB, C::NC, QPW, G>(Km, n, b0, c0, kbc0, a.det_lo);
+      scatter_ws<C::NB, C::ND, QPW, G>(Km, n, b0, d0, kbd0, a.det_lo);
     }
   }
   }

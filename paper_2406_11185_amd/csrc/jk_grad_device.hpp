@@ -2,7 +2,7 @@
 // fixed D, for gfx950.  Shares the pair data, Boys tables, screening and work
 // items of the J/K build; the per-class code comes from gen_grad.py.
 #pragma once
-#include "jk_device.hpp"
+#include "jk_classes.hpp"
 
 namespace jk {
 
@@ -12,17 +12,33 @@ struct GradLaunch {
   int n_atoms;
   void* ws;         // workspace: nwaves * 64 lanes * C::WS values of type T
   int nwaves;       // wavefronts of the launch; each claims items until none is left
-  int lds_doubles;  // n_dm * n_atoms * 3 when the workgroup accumulates dE/dR in LDS
-                    // (dynamic shared memory of that many doubles), else 0
+  int lds_doubles;  // n_dm * n_atoms * 3 when the workgroup accumulates dE/dR in LDS,
+                    // else 0; dynamic shared memory of lds_bytes (8 bytes per value, or
+                    // two int64 words per value in deterministic mode)
+  size_t lds_bytes;
 };
 
 // Gradient contributions go to a workgroup copy of dE/dR in LDS (the whole
 // gradient is a few hundred values, so direct global atomics from every
 // quartet would serialise on a handful of lines) and are added to global
 // memory once per workgroup at the end; without LDS room, directly.
-__device__ __forceinline__ void grad_add(double* lds, double* glob, int idx, double v) {
-  if (lds) atomicAdd(&lds[idx], v);
-  else atomic_add(&glob[idx], v);
+// Deterministic mode (det_lo > 0): dEdR points to int64 fixed-point pairs (see
+// atomic_add) and the LDS copy holds the same pairs, lo words nl values after
+// the hi words.
+__device__ __forceinline__ void grad_add(double* lds, double* glob, int idx, double v,
+                                         size_t det_lo, int nl) {
+  if (!lds) {
+    atomic_add(&glob[idx], v, det_lo);
+  } else if (det_lo == 0) {
+    atomicAdd(&lds[idx], v);
+  } else {
+    const double s = v * kFixHi;
+    const double h = rint(s);
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(lds);
+    atomicAdd(&w[idx], static_cast<unsigned long long>(static_cast<long long>(h)));
+    atomicAdd(&w[idx + nl],
+              static_cast<unsigned long long>(static_cast<long long>(rint((s - h) * kFixLo))));
+  }
 }
 
 
@@ -98,8 +114,10 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
   const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   extern __shared__ double gacc[];   // [n_dm][n_atoms][3] when g.lds_doubles > 0
   double* const lds = g.lds_doubles > 0 ? gacc : nullptr;
+  const size_t det = a.det_lo;
+  const int nl = g.lds_doubles;
   if (lds) {
-    for (int t = threadIdx.x; t < g.lds_doubles; t += kBlock) gacc[t] = 0.0;
+    for (int t = threadIdx.x; t < (det ? 2 : 1) * nl; t += kBlock) gacc[t] = 0.0;
     __syncthreads();
   }
   // waves past the launch's wavefront count only take part in the final flush
@@ -275,12 +293,12 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
         const double gd = -(group_sum<GL>(ga + gb) + gc);
         const double sa = wave_sum(ga), sb = wave_sum(gb);
         if (lane == kWaveSumLane) {
-          grad_add(lds, g.dEdR, o3 + atA * 3 + x, sa);
-          grad_add(lds, g.dEdR, o3 + atB * 3 + x, sb);
+          grad_add(lds, g.dEdR, o3 + atA * 3 + x, sa, det, nl);
+          grad_add(lds, g.dEdR, o3 + atB * 3 + x, sb, det, nl);
         }
         if (active) {
-          grad_add(lds, g.dEdR, o3 + atC * 3 + x, gc);
-          grad_add(lds, g.dEdR, o3 + atD * 3 + x, gd);
+          grad_add(lds, g.dEdR, o3 + atC * 3 + x, gc, det, nl);
+          grad_add(lds, g.dEdR, o3 + atD * 3 + x, gd, det, nl);
         }
       }
     }
@@ -288,8 +306,17 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradLaunch g) {
   }
   if (lds) {
     __syncthreads();
-    for (int t = threadIdx.x; t < g.lds_doubles; t += kBlock)
-      if (gacc[t] != 0.0) atomic_add(&g.dEdR[t], gacc[t]);
+    if (det == 0) {
+      for (int t = threadIdx.x; t < nl; t += kBlock)
+        if (gacc[t] != 0.0) atomic_add(&g.dEdR[t], gacc[t], 0);
+    } else {
+      const unsigned long long* wl = reinterpret_cast<const unsigned long long*>(gacc);
+      unsigned long long* wg = reinterpret_cast<unsigned long long*>(g.dEdR);
+      for (int t = threadIdx.x; t < nl; t += kBlock) {
+        if (wl[t] != 0) atomicAdd(&wg[t], wl[t]);
+        if (wl[t + nl] != 0) atomicAdd(&wg[t + det], wl[t + nl]);
+      }
+    }
   }
 }
 

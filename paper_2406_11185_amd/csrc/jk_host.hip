@@ -39,6 +39,7 @@
 #include "jk_device.hpp"
 #include "jk_classes.hpp"
 #include "jk_grad_device.hpp"
+#include "jk_guard.hpp"
 
 using namespace jk;
 
@@ -311,48 +312,123 @@ __global__ void fill_kernel(size_t n, T* a) {
   if (i < n) a[i] = T(0);
 }
 
-// J = sum over the accumulator copies of A + A^T (one thread per upper-triangle
-// element and density); the copies are [ncopy][n_dm][n][n].
-__global__ void finalize_copies_kernel(int n, int n_dm, int ncopy, const double* AJ,
-                                       const double* AK, double* J, double* K) {
-  const size_t nn = static_cast<size_t>(n) * n;
-  const size_t id = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (id >= nn * n_dm) return;
-  const int m = static_cast<int>(id / nn);
-  const size_t r = id % nn;
-  const int i = static_cast<int>(r / n), j = static_cast<int>(r % n);
-  if (j < i) return;
-  const size_t ij = m * nn + static_cast<size_t>(i) * n + j;
-  const size_t ji = m * nn + static_cast<size_t>(j) * n + i;
-  const size_t stride = nn * n_dm;
-  double sj = 0.0, sk = 0.0;
-  for (int c = 0; c < ncopy; ++c) {
-    sj += AJ[c * stride + ij] + AJ[c * stride + ji];
-    sk += AK[c * stride + ij] + AK[c * stride + ji];
+// Accumulator element idx: an FP64 value, or in deterministic mode the int64
+// fixed-point pair (hi at idx, lo at idx + det_lo) summed over the copies and
+// over idx, idx2 (the element and its transpose) before one conversion.
+__device__ __forceinline__ double acc_sum(const double* A, size_t idx, size_t idx2, int ncopy,
+                                          size_t stride, size_t det_lo) {
+  if (!det_lo) {
+    double v = 0.0;
+    for (int c = 0; c < ncopy; ++c) v += A[c * stride + idx] + A[c * stride + idx2];
+    return v;
   }
-  J[ij] = sj;
-  J[ji] = sj;
-  K[ij] = sk;
-  K[ji] = sk;
+  const unsigned long long* w = reinterpret_cast<const unsigned long long*>(A);
+  unsigned long long hi = 0, lo = 0;
+  for (int c = 0; c < ncopy; ++c) {
+    hi += w[c * stride + idx] + w[c * stride + idx2];
+    lo += w[c * stride + idx + det_lo] + w[c * stride + idx2 + det_lo];
+  }
+  return static_cast<double>(static_cast<long long>(hi)) * (1.0 / kFixHi) +
+         static_cast<double>(static_cast<long long>(lo)) * (1.0 / (kFixHi * kFixLo));
 }
 
-// J = A + A^T in place, per density (one thread per upper-triangle element).
-__global__ void finalize_kernel(int n, int n_dm, double* J, double* K) {
-  const size_t nn = static_cast<size_t>(n) * n;
-  const size_t id = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (id >= nn * n_dm) return;
-  const int m = static_cast<int>(id / nn);
-  const size_t r = id % nn;
-  const int i = static_cast<int>(r / n), j = static_cast<int>(r % n);
-  if (j < i) return;
-  double* Jm = J + m * nn;
-  double* Km = K + m * nn;
-  const double sj = Jm[static_cast<size_t>(i) * n + j] + Jm[static_cast<size_t>(j) * n + i];
-  const double sk = Km[static_cast<size_t>(i) * n + j] + Km[static_cast<size_t>(j) * n + i];
-  Jm[static_cast<size_t>(i) * n + j] = sj;
-  Jm[static_cast<size_t>(j) * n + i] = sj;
-  Km[static_cast<size_t>(i) * n + j] = sk;
-  Km[static_cast<size_t>(j) * n + i] = sk;
+// Step a7 (finalize): J = sum over the accumulator copies of A_J + A_J^T, K the
+// same from A_K; optionally dE/dD = J - K/2 and the per-block partial sums of
+// <D, J> and <D, K> (each symmetric pair (i, j), (j, i) once, weighted by
+// D_ij + D_ji).  One thread per element with j >= i; grid (blocks, n_dm).
+struct FinArgs {
+  int n, ncopy;
+  size_t stride;        // elements between accumulator copies
+  size_t det_lo;        // deterministic mode: offset of the lo words (else 0)
+  const double* AJ;     // accumulators [ncopy][n_dm][n][n] (== J, K in place when
+  const double* AK;     //   ncopy == 1 outside deterministic mode)
+  const double* D;
+  double* J;
+  double* K;
+  double* dEdD;         // optional [n_dm][n][n]
+  double* epart;        // optional [n_dm][gridDim.x][2]
+};
+
+constexpr int kFinBlock = 256;
+
+__global__ __launch_bounds__(kFinBlock) void finalize_kernel(FinArgs f) {
+  const size_t nn = static_cast<size_t>(f.n) * f.n;
+  const int m = blockIdx.y;
+  const size_t r = static_cast<size_t>(blockIdx.x) * kFinBlock + threadIdx.x;
+  double ej = 0.0, ek = 0.0;
+  if (r < nn) {
+    const int i = static_cast<int>(r / f.n), j = static_cast<int>(r % f.n);
+    if (j >= i) {
+      const size_t ij = m * nn + static_cast<size_t>(i) * f.n + j;
+      const size_t ji = m * nn + static_cast<size_t>(j) * f.n + i;
+      const double sj = acc_sum(f.AJ, ij, ji, f.ncopy, f.stride, f.det_lo);
+      const double sk = acc_sum(f.AK, ij, ji, f.ncopy, f.stride, f.det_lo);
+      f.J[ij] = sj;
+      f.J[ji] = sj;
+      f.K[ij] = sk;
+      f.K[ji] = sk;
+      if (f.dEdD) {
+        f.dEdD[ij] = sj - 0.5 * sk;
+        f.dEdD[ji] = sj - 0.5 * sk;
+      }
+      const double w = (i == j) ? f.D[ij] : f.D[ij] + f.D[ji];
+      ej = w * sj;
+      ek = w * sk;
+    }
+  }
+  if (!f.epart) return;
+  __shared__ double red[2][kFinBlock];
+  red[0][threadIdx.x] = ej;
+  red[1][threadIdx.x] = ek;
+  __syncthreads();
+  for (int h = kFinBlock / 2; h > 0; h >>= 1) {   // fixed pairing: same order every run
+    if (static_cast<int>(threadIdx.x) < h) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + h];
+      red[1][threadIdx.x] += red[1][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* p = f.epart + (static_cast<size_t>(m) * gridDim.x + blockIdx.x) * 2;
+    p[0] = red[0][0];
+    p[1] = red[1][0];
+  }
+}
+
+// E_J = 1/2 <D, J>, E_K = 1/4 <D, K>, E = E_J - E_K from the partial sums, one
+// workgroup per density, summed in a fixed order.
+__global__ __launch_bounds__(kFinBlock) void energy_kernel(int nblk, const double* epart, double* E) {
+  const int m = blockIdx.x;
+  __shared__ double red[2][kFinBlock];
+  double sj = 0.0, sk = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kFinBlock) {
+    sj += epart[(static_cast<size_t>(m) * nblk + b) * 2];
+    sk += epart[(static_cast<size_t>(m) * nblk + b) * 2 + 1];
+  }
+  red[0][threadIdx.x] = sj;
+  red[1][threadIdx.x] = sk;
+  __syncthreads();
+  for (int h = kFinBlock / 2; h > 0; h >>= 1) {
+    if (static_cast<int>(threadIdx.x) < h) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + h];
+      red[1][threadIdx.x] += red[1][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double ej = 0.5 * red[0][0], ek = 0.25 * red[1][0];
+    E[3 * m] = ej;
+    E[3 * m + 1] = ek;
+    E[3 * m + 2] = ej - ek;
+  }
+}
+
+// Deterministic gradient: dE/dR from its int64 fixed-point pairs.
+__global__ void fix_to_double_kernel(size_t n, const unsigned long long* w, size_t lo, double* out) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = static_cast<double>(static_cast<long long>(w[i])) * (1.0 / kFixHi) +
+           static_cast<double>(static_cast<long long>(w[i + lo])) * (1.0 / (kFixHi * kFixLo));
 }
 
 inline unsigned grid_of(size_t n, int block) { return static_cast<unsigned>((n + block - 1) / block); }
@@ -375,10 +451,77 @@ enum Slot {
   sShellXyz, sShellI, sExps, sCoefs, sPairS, sBinOff, sBinNpp, sBinPrim, sPrimTmp, sPrim, sPrimTmpT, sPrimT,
   sA, sAB, sBf, sAtoms, sFpair, sAtmp, sABtmp, sBftmp, sAtomstmp, sFpairtmp, sQtmp, sQ,
   sIdx, sIdxSorted, sPerm, sBp, sCnt, sOff, sRng, sQstat, sSeg, sItems, sCub, sChunk, sWs0, sWs1,
-  sWs2, sWs3, sWsSchwarz, sNext, sAcc, sNumSlots
+  sWs2, sWs3, sWsSchwarz, sNext, sAcc, sEpart, sGradAcc, sNumSlots
 };
 
 }  // namespace
+
+namespace jk {
+namespace {
+thread_local std::string g_guard_err;
+
+struct GuardKey {
+  const void* fn;
+  int device;
+  unsigned block;
+  size_t lds;
+  bool operator<(const GuardKey& o) const {
+    if (fn != o.fn) return fn < o.fn;
+    if (device != o.device) return device < o.device;
+    if (block != o.block) return block < o.block;
+    return lds < o.lds;
+  }
+};
+struct GuardInfo {
+  size_t private_per_lane;
+  int blocks_per_cu;
+  int num_cu;
+};
+std::map<GuardKey, GuardInfo> g_guard_cache;
+}  // namespace
+
+// Scratch guard of every kernel launch: the kernel's private-segment bytes
+// per lane (from the runtime's function attributes) times the lanes of its
+// resident wavefronts must fit kScratchBudget.  Attributes are read once per
+// (kernel, device, block, LDS) and cached.
+int guard_launch(const void* kernel, unsigned grid_blocks, unsigned block_threads, size_t lds_bytes) {
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) device = 0;
+  const GuardKey key{kernel, device, block_threads, lds_bytes};
+  auto it = g_guard_cache.find(key);
+  if (it == g_guard_cache.end()) {
+    hipFuncAttributes attr{};
+    GuardInfo gi{0, 1, 1};
+    if (hipFuncGetAttributes(&attr, kernel) == hipSuccess) gi.private_per_lane = attr.localSizeBytes;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, static_cast<int>(block_threads),
+                                                     lds_bytes) == hipSuccess && nb > 0)
+      gi.blocks_per_cu = nb;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        ncu > 0)
+      gi.num_cu = ncu;
+    (void)hipGetLastError();
+    it = g_guard_cache.emplace(key, gi).first;
+  }
+  const GuardInfo& gi = it->second;
+  const size_t wpb = (block_threads + kWave - 1) / kWave;
+  const size_t need = launch_scratch_bytes(gi.private_per_lane, size_t(grid_blocks) * wpb,
+                                           gi.num_cu, gi.blocks_per_cu, wpb);
+  if (launch_scratch_ok(need)) return 0;
+  g_guard_err = "a kernel launch would need " + std::to_string(need >> 20) +
+                " MiB of scratch (" + std::to_string(gi.private_per_lane) +
+                " bytes per lane), over the " + std::to_string(kScratchBudget >> 20) + " MiB limit";
+  return 1;
+}
+
+// The guard's message since the last call, cleared.
+std::string take_guard_error() {
+  std::string m;
+  m.swap(g_guard_err);
+  return m;
+}
+}  // namespace jk
 
 struct jk_ctx {
   int device = 0;
@@ -657,6 +800,8 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
       a.ws = dev<char>(c, sWsSchwarz, per_wave * a.nwaves);
     }
     launch_schwarz(P.bin_cls[bb], a, d_Qtmp + P.bin_off[bb], s);
+    const std::string gm = take_guard_error();
+    if (!gm.empty()) throw Fail{JK_EUNSUPPORTED, gm};
   }
   // step 4: segmented sort by Q, descending, then pair data in sorted order
   hipLaunchKernelGGL(iota_kernel, dim3(grid_of(np, 256)), dim3(256), 0, s, np, d_binoff, P.nbins, d_idx);
@@ -815,9 +960,15 @@ struct NoPrepare {
   void operator()(const std::vector<LaunchRec>&, const std::vector<int>&) const {}
 };
 
+void check_guard() {
+  const std::string m = take_guard_error();
+  if (!m.empty()) throw Fail{JK_EUNSUPPORTED, m};
+}
+
+// launch_one(rec, stream, stream index, work counter, dry): dry = check only.
 template <class Fn, class Prep = NoPrepare>
 void dispatch(jk_ctx* c, const Plan& P, const Setup& S, hipStream_t s, jk_stats& st, bool grad,
-              Fn&& launch_one, Prep&& prepare = Prep()) {
+              bool serial, Fn&& launch_one, Prep&& prepare = Prep()) {
   const int nbp = static_cast<int>(P.bp_x.size());
   std::vector<LaunchRec> recs;
   for (int bp = 0; bp < nbp; ++bp) {
@@ -839,9 +990,15 @@ void dispatch(jk_ctx* c, const Plan& P, const Setup& S, hipStream_t s, jk_stats&
   // others follow on the internal streams (largest first, each to the least
   // loaded), where launches of different classes share the GPU.  The first
   // launch uses stream 0's workspace, which stream 0 touches only after it.
+  // every launch passes the scratch guard before any of them (or any write
+  // to the outputs) is enqueued
+  (void)take_guard_error();
+  for (size_t q = 0; q < recs.size(); ++q) launch_one(recs[q], s, 0, nullptr, true);
+  check_guard();
   std::vector<int> where(recs.size(), 0);
   double load[jk_ctx::kStreams] = {};
-  const size_t q0 = recs.empty() ? 0 : 1;
+  // serial: every launch on the caller's stream
+  const size_t q0 = serial ? recs.size() : (recs.empty() ? 0 : 1);
   for (size_t q = q0; q < recs.size(); ++q) {
     int k = 0;
     for (int j = 1; j < jk_ctx::kStreams; ++j)
@@ -866,8 +1023,9 @@ void dispatch(jk_ctx* c, const Plan& P, const Setup& S, hipStream_t s, jk_stats&
     hipStream_t ls = q < q0 ? s : c->streams[k];
     size_t e0 = 0;
     if (c->timed) e0 = event(c, ls);
-    launch_one(r, ls, k, next + q);
+    launch_one(r, ls, k, next + q, false);
     HIP_OK(hipGetLastError());
+    check_guard();
     if (c->timed) {
       event(c, ls);
       c->timed_launches.push_back({r.cls, r.pr, e0});
@@ -888,8 +1046,10 @@ int check_opts(const jk_opts* o, jk_opts* out, std::string* msg) {
   if (!(out->fp32_below >= 0.0) || !std::isfinite(out->fp32_below)) { *msg = "opts.fp32_below"; return JK_EINVAL; }
   if (!(out->boys_fp64_T > 0.0 && out->boys_fp64_T <= 30.0)) { *msg = "opts.boys_fp64_T must be in (0, 30]"; return JK_EINVAL; }
   if (out->n_dm < 1 || out->n_dm > JK_MAX_NDM) { *msg = "opts.n_dm must be in 1..16"; return JK_EINVAL; }
-  if (out->deterministic != 0) { *msg = "deterministic mode is not implemented"; return JK_EUNSUPPORTED; }
+  if (out->deterministic != 0 && out->deterministic != 1) { *msg = "opts.deterministic must be 0 or 1"; return JK_EINVAL; }
   if (out->timing != 0 && out->timing != 1) { *msg = "opts.timing"; return JK_EINVAL; }
+  if (out->acc_copies < 0 || out->acc_copies > static_cast<int32_t>(kMaxCopies)) { *msg = "opts.acc_copies must be in 0..8"; return JK_EINVAL; }
+  if (out->serial != 0 && out->serial != 1) { *msg = "opts.serial must be 0 or 1"; return JK_EINVAL; }
   return JK_OK;
 }
 
@@ -906,6 +1066,10 @@ int jk_opts_default(jk_opts* o) {
   o->deterministic = 0;
   o->timing = 0;
   o->max_scratch_bytes = 0;
+  o->acc_copies = 0;
+  o->serial = 0;
+  o->energy = nullptr;
+  o->dEdD = nullptr;
   return JK_OK;
 }
 
@@ -990,25 +1154,32 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
     if (c->timed) c->ev_setup1 = event(c, s);
     const size_t nn = static_cast<size_t>(nbf) * nbf;
     const size_t mat = nn * o.n_dm;   // elements of J (and of K)
+    const bool det = o.deterministic == 1;
     // Atomic adds to one 64-byte line serialise at the memory side, and a small
     // J/K receives many adds per line: accumulate into up to kMaxCopies copies
     // (item % ncopy) within kAccBudget bytes, then sum them in the finalize.
-    int ncopy = static_cast<int>(std::min<size_t>(kMaxCopies, kAccBudget / (2 * mat * sizeof(double))));
-    if (c->scratch_limit)
-      ncopy = std::min<int>(ncopy, static_cast<int>(c->scratch_limit / 4 / (2 * mat * sizeof(double))));
+    // Deterministic mode keeps two int64 words per value.
+    const size_t words = det ? 2 : 1;
+    int ncopy = o.acc_copies;
+    if (ncopy == 0) {
+      ncopy = static_cast<int>(std::min<size_t>(kMaxCopies, kAccBudget / (2 * words * mat * sizeof(double))));
+      if (c->scratch_limit)
+        ncopy = std::min<int>(ncopy, static_cast<int>(c->scratch_limit / 4 / (2 * words * mat * sizeof(double))));
+      ncopy = std::max(ncopy, 1);
+    }
+    // in place (J, K are the accumulators) only with one FP64 copy
+    const bool inplace = ncopy == 1 && !det;
     double* AJ = J;
     double* AK = K;
-    if (ncopy > 1) {
-      AJ = dev<double>(c, sAcc, 2 * mat * ncopy);
+    size_t det_lo = 0;
+    if (!inplace) {
+      AJ = dev<double>(c, sAcc, 2 * words * mat * ncopy);
       AK = AJ + mat * ncopy;
-      hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(2 * mat * ncopy, 256)), dim3(256), 0, s,
-                         2 * mat * ncopy, AJ);
-    } else {
-      ncopy = 1;
-      hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(mat, 256)), dim3(256), 0, s, mat, J);
-      hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(mat, 256)), dim3(256), 0, s, mat, K);
+      if (det) det_lo = 2 * mat * ncopy;   // [AJ hi][AK hi][AJ lo][AK lo]
     }
-    HIP_OK(hipGetLastError());
+    const int fin_blocks = static_cast<int>(grid_of(nn, kFinBlock));
+    double* epart = o.energy ? dev<double>(c, sEpart, static_cast<size_t>(2) * fin_blocks * o.n_dm)
+                             : nullptr;
 
     jk_stats st = base_stats(P, S);
     auto waves_of = [&](const LaunchRec& r) {
@@ -1019,15 +1190,17 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
     };
     void* ws[jk_ctx::kStreams] = {};
     dispatch(
-        c, P, S, s, st, false,
-        [&](const LaunchRec& r, hipStream_t ls, int k, int* next) {
+        c, P, S, s, st, false, o.serial == 1,
+        [&](const LaunchRec& r, hipStream_t ls, int k, int* next, bool dry) {
           EriLaunch a = launch_args(c, P, S, r.X, r.Y, r.i0, r.i1, D, AJ, AK, nbf, o);
           a.ncopy = ncopy;
           a.copy_stride = mat;
+          a.det_lo = det_lo;
           a.lanes = r.lanes;
           a.next = next;
           a.ws = ws[k];
           a.nwaves = waves_of(r).first;
+          a.dry = dry ? 1 : 0;
           launch_eri(r.cls, r.pr, a, ls);
         },
         [&](const std::vector<LaunchRec>& recs, const std::vector<int>& where) {
@@ -1038,14 +1211,23 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
           }
           for (int k = 0; k < jk_ctx::kStreams; ++k)
             if (need[k]) ws[k] = dev<char>(c, static_cast<Slot>(sWs0 + k), need[k]);
+          // the outputs are first written here, after every check has passed
+          if (inplace) {
+            hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(mat, 256)), dim3(256), 0, s, mat, J);
+            hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(mat, 256)), dim3(256), 0, s, mat, K);
+          } else {
+            const size_t tot = 2 * words * mat * ncopy;
+            hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(tot, 256)), dim3(256), 0, s, tot, AJ);
+          }
+          HIP_OK(hipGetLastError());
         });
-    if (ncopy > 1)
-      hipLaunchKernelGGL(finalize_copies_kernel, dim3(grid_of(mat, 256)), dim3(256), 0, s, nbf,
-                         o.n_dm, ncopy, AJ, AK, J, K);
-    else
-      hipLaunchKernelGGL(finalize_kernel, dim3(grid_of(mat, 256)), dim3(256), 0, s, nbf, o.n_dm,
-                         J, K);
+    FinArgs f{nbf, inplace ? 1 : ncopy, mat, det_lo, AJ, AK, D, J, K, o.dEdD, epart};
+    hipLaunchKernelGGL(finalize_kernel, dim3(fin_blocks, o.n_dm), dim3(kFinBlock), 0, s, f);
     HIP_OK(hipGetLastError());
+    if (o.energy) {
+      hipLaunchKernelGGL(energy_kernel, dim3(o.n_dm), dim3(kFinBlock), 0, s, fin_blocks, epart, o.energy);
+      HIP_OK(hipGetLastError());
+    }
     if (c->timed) c->ev_end = event(c, s);
     c->stats = st;
   } catch (const Fail& f) {
@@ -1079,8 +1261,9 @@ int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, dou
     const Plan& P = S.P;
     if (c->timed) c->ev_setup1 = event(c, s);
     const size_t ng = static_cast<size_t>(o.n_dm) * basis->n_atoms * 3;
-    hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(ng, 256)), dim3(256), 0, s, ng, dEdR);
-    HIP_OK(hipGetLastError());
+    // deterministic mode: int64 fixed-point pairs [hi ng][lo ng], converted at the end
+    const bool det = o.deterministic == 1;
+    double* gacc = det ? dev<double>(c, sGradAcc, 2 * ng) : dEdR;
     jk_stats st = base_stats(P, S);
     // gradient work arrays live in a per-stream workspace; a launch uses at most
     // kWsBudget bytes and loops over its items with a fixed number of waves
@@ -1091,16 +1274,19 @@ int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, dou
     };
     void* ws[jk_ctx::kStreams] = {};
     dispatch(
-        c, P, S, s, st, true,
-        [&](const LaunchRec& r, hipStream_t ls, int k, int* next) {
+        c, P, S, s, st, true, o.serial == 1,
+        [&](const LaunchRec& r, hipStream_t ls, int k, int* next, bool dry) {
           GradLaunch g{};
           g.e = launch_args(c, P, S, r.X, r.Y, r.i0, r.i1, D, nullptr, nullptr, nbf, o);
           g.e.lanes = r.lanes;
           g.e.next = next;
-          g.dEdR = dEdR;
+          g.e.det_lo = det ? ng : 0;
+          g.e.dry = dry ? 1 : 0;
+          g.dEdR = gacc;
           g.n_atoms = basis->n_atoms;
-          const size_t ng = static_cast<size_t>(o.n_dm) * basis->n_atoms * 3;
-          g.lds_doubles = ng * sizeof(double) <= kGradLdsBytes ? static_cast<int>(ng) : 0;
+          const size_t per = (det ? 2 : 1) * sizeof(double);
+          g.lds_doubles = ng * per <= kGradLdsBytes ? static_cast<int>(ng) : 0;
+          g.lds_bytes = g.lds_doubles * per;
           g.ws = ws[k];
           g.nwaves = waves_of(r).first;
           launch_grad(r.cls, r.pr, g, ls);
@@ -1113,7 +1299,15 @@ int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, dou
           }
           for (int k = 0; k < jk_ctx::kStreams; ++k)
             if (need[k]) ws[k] = dev<char>(c, static_cast<Slot>(sWs0 + k), need[k]);
+          const size_t tot = (det ? 2 : 1) * ng;
+          hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_of(tot, 256)), dim3(256), 0, s, tot, gacc);
+          HIP_OK(hipGetLastError());
         });
+    if (det) {
+      hipLaunchKernelGGL(fix_to_double_kernel, dim3(grid_of(ng, 256)), dim3(256), 0, s, ng,
+                         reinterpret_cast<const unsigned long long*>(gacc), ng, dEdR);
+      HIP_OK(hipGetLastError());
+    }
     if (c->timed) c->ev_end = event(c, s);
     c->stats = st;
   } catch (const Fail& f) {

@@ -46,7 +46,9 @@ class jk_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("fp32_below", ctypes.c_double),
                 ("boys_fp64_T", ctypes.c_double), ("n_dm", ctypes.c_int32),
                 ("deterministic", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("max_scratch_bytes", ctypes.c_uint64)]
+                ("max_scratch_bytes", ctypes.c_uint64), ("acc_copies", ctypes.c_int32),
+                ("serial", ctypes.c_int32), ("energy", ctypes.c_void_p),
+                ("dEdD", ctypes.c_void_p)]
 
 
 class jk_stats(ctypes.Structure):
@@ -120,7 +122,9 @@ def jk_opts_default() -> jk_opts:
 
 
 def make_opts(precision="fp64", fp32_below=1e-4, n_dm=1, timing=False, boys_fp64_T=30.0,
-              max_scratch_bytes=0, deterministic=0) -> jk_opts:
+              max_scratch_bytes=0, deterministic=0, acc_copies=0, serial=False, energy=None,
+              dEdD=None) -> jk_opts:
+    """jk_opts from keywords; energy / dEdD are float64 device tensors (or None)."""
     o = jk_opts_default()
     o.precision = {"fp64": JK_FP64, "mixed": JK_MIXED}[precision] if isinstance(precision, str) \
         else int(precision)
@@ -130,6 +134,10 @@ def make_opts(precision="fp64", fp32_below=1e-4, n_dm=1, timing=False, boys_fp64
     o.boys_fp64_T = float(boys_fp64_T)
     o.max_scratch_bytes = int(max_scratch_bytes)
     o.deterministic = int(deterministic)
+    o.acc_copies = int(acc_copies)
+    o.serial = 1 if serial else 0
+    o.energy = energy.data_ptr() if energy is not None else None
+    o.dEdD = dEdD.data_ptr() if dEdD is not None else None
     return o
 
 
@@ -221,8 +229,13 @@ def jk_grad(ctx: Context, basis: Basis, D, dEdR, tol: float, opts: jk_opts | Non
 
 
 def jk(mol, D, tol: float, precision: str = "fp64", fp32_below: float = 1e-4,
-       timing: bool = False, ctx: Context | None = None):
-    """J, K for the densities D ([n][n] or [n_dm][n][n] float64 CUDA tensor)."""
+       timing: bool = False, ctx: Context | None = None, energies: bool = False,
+       dEdD: bool = False, **opt):
+    """J, K for the densities D ([n][n] or [n_dm][n][n] float64 CUDA tensor).
+
+    energies=True adds E ([n_dm][3]: E_J, E_K, E_J - E_K, from the library's
+    finalize step); dEdD=True adds dE/dD = J - K/2 (same shape as J).  Extra
+    keywords go to make_opts (deterministic, acc_copies, serial, ...)."""
     import torch
     basis = mol if isinstance(mol, Basis) else Basis(mol)
     squeeze = D.dim() == 2
@@ -233,15 +246,20 @@ def jk(mol, D, tol: float, precision: str = "fp64", fp32_below: float = 1e-4,
     ctx = ctx or default_context(Dd.device.index or 0)
     J = torch.empty_like(Dd)
     K = torch.empty_like(Dd)
-    opts = make_opts(precision, fp32_below, n_dm, timing)
+    E = torch.empty((n_dm, 3), dtype=torch.float64, device=Dd.device) if energies else None
+    G = torch.empty_like(Dd) if dEdD else None
+    opts = make_opts(precision, fp32_below, n_dm, timing, energy=E, dEdD=G, **opt)
     jk_build(ctx, basis, Dd, J, K, tol, opts)
-    if squeeze:
-        return J[0], K[0]
-    return J, K
+    out = [J[0], K[0]] if squeeze else [J, K]
+    if energies:
+        out.append(E[0] if squeeze else E)
+    if dEdD:
+        out.append(G[0] if squeeze else G)
+    return tuple(out)
 
 
 def grad(mol, D, tol: float, precision: str = "fp64", fp32_below: float = 1e-4,
-         ctx: Context | None = None):
+         ctx: Context | None = None, **opt):
     """dE/dR ([n_atoms][3] or [n_dm][n_atoms][3]) of E = 1/2 tr(DJ) - 1/4 tr(DK)."""
     import torch
     basis = mol if isinstance(mol, Basis) else Basis(mol)
@@ -251,7 +269,7 @@ def grad(mol, D, tol: float, precision: str = "fp64", fp32_below: float = 1e-4,
     _check_dev(Dd, (n_dm, n, n), "D")
     ctx = ctx or default_context(Dd.device.index or 0)
     G = torch.empty((n_dm, basis.n_atoms, 3), dtype=torch.float64, device=Dd.device)
-    opts = make_opts(precision, fp32_below, n_dm)
+    opts = make_opts(precision, fp32_below, n_dm, **opt)
     jk_grad(ctx, basis, Dd, G, tol, opts)
     return G[0] if squeeze else G
 
@@ -260,8 +278,9 @@ class JKEnergy:
     """E = 1/2 tr(DJ) - 1/4 tr(DK) as a torch.autograd.Function.
 
     JKEnergy.apply(xyz, D, mol, tol, precision) -> E (0-d tensor, or [n_dm]).
-    The backward pass calls jk_grad (derivative-integral kernels) for dE/dxyz
-    and returns dE/dD = J - K/2 from the forward build.
+    The forward pass takes E and dE/dD = J - K/2 from jk_build's finalize step;
+    the backward pass calls jk_grad (derivative-integral kernels) for dE/dxyz.
+    Only the upstream gradient's chain-rule scaling happens here.
     """
 
     _fn = None
@@ -281,27 +300,25 @@ def _make_jk_energy():
         def forward(ctx, xyz, D, mol, tol, precision):
             moved = mol.with_xyz(xyz.detach().cpu().double().numpy())
             basis = Basis(moved)
-            J, K = jk(basis, D, tol, precision=precision)
-            E = 0.5 * (D * J).sum(dim=(-1, -2)) - 0.25 * (D * K).sum(dim=(-1, -2))
-            ctx.save_for_backward(D, J, K)
+            _, _, E, dEdD = jk(basis, D, tol, precision=precision, energies=True, dEdD=True)
+            ctx.save_for_backward(D, dEdD)
             ctx.basis = basis
             ctx.tol = tol
             ctx.precision = precision
             ctx.xyz_dev = xyz.device
-            return E
+            return E[..., 2].clone()
 
         @staticmethod
         def backward(ctx, gE):
-            D, J, K = ctx.saved_tensors
+            D, dEdD = ctx.saved_tensors
             g_xyz = g_D = None
+            scale = gE.reshape(gE.shape + (1, 1)) if gE.dim() else gE
             if ctx.needs_input_grad[0]:
                 G = grad(ctx.basis, D, ctx.tol, precision=ctx.precision)
-                scale = gE.reshape(gE.shape + (1, 1)) if gE.dim() else gE
                 g_xyz = (G * scale).sum(dim=0) if G.dim() == 3 else G * scale
                 g_xyz = g_xyz.to(ctx.xyz_dev)
             if ctx.needs_input_grad[1]:
-                scale = gE.reshape(gE.shape + (1, 1)) if gE.dim() else gE
-                g_D = (J - 0.5 * K) * scale
+                g_D = dEdD * scale
             return g_xyz, g_D, None, None, None
 
     return _JKEnergy

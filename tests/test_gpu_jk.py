@@ -122,7 +122,9 @@ def test_argument_errors_leave_outputs_untouched():
     for opts, code in [(jkb.make_opts(n_dm=0), jkb.JK_EINVAL),
                        (jkb.make_opts(precision=5), jkb.JK_EINVAL),
                        (jkb.make_opts(boys_fp64_T=45.0), jkb.JK_EINVAL),
-                       (jkb.make_opts(deterministic=1), jkb.JK_EUNSUPPORTED)]:
+                       (jkb.make_opts(deterministic=2), jkb.JK_EINVAL),
+                       (jkb.make_opts(acc_copies=9), jkb.JK_EINVAL),
+                       (jkb.make_opts(serial=True, deterministic=-1), jkb.JK_EINVAL)]:
         with pytest.raises(jkb.JkError) as e:
             jkb.jk_build(ctx, b, D, J, K, 0.0, opts)
         assert e.value.code == code

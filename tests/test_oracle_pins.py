@@ -282,3 +282,154 @@ def test_gradient_translation_sum_and_s_only_rotation():
     Gs = oracle.grad(sub, 0.0)[0]
     torque = np.cross(sub.xyz, Gs).sum(axis=0)
     np.testing.assert_allclose(torque, 0.0, atol=1e-11)
+
+
+# --- contracted shell quartets against brute-force quadrature --------------------
+
+# Cartesian components in the order every interface here uses (descending powers
+# of x, then y), written out by hand
+CART = {0: [(0, 0, 0)],
+        1: [(1, 0, 0), (0, 1, 0), (0, 0, 1)],
+        2: [(2, 0, 0), (1, 1, 0), (1, 0, 1), (0, 2, 0), (0, 1, 1), (0, 0, 2)]}
+
+
+def _four_centre_basis(nprim, seed):
+    """Four atoms, each with one s, one p and one d shell of `nprim` primitives."""
+    rng = np.random.default_rng(seed)
+    xyz = rng.uniform(-1.2, 1.2, (4, 3))
+    shell_atom, shell_l, shell_nprim, shell_prim0, exps, coefs = [], [], [], [], [], []
+    for at in range(4):
+        for l in (0, 1, 2):
+            shell_atom.append(at)
+            shell_l.append(l)
+            shell_nprim.append(nprim)
+            shell_prim0.append(len(exps))
+            exps += list(rng.uniform(0.3, 1.6, nprim))
+            coefs += list(rng.uniform(0.2, 1.0, nprim))
+    i32 = lambda v: np.asarray(v, dtype=np.int32)  # noqa: E731
+    return molgen.Molecule(xyz, i32([8, 8, 8, 8]), i32(shell_atom), i32(shell_l),
+                           i32(shell_nprim), i32(shell_prim0), np.asarray(exps),
+                           np.asarray(coefs))
+
+
+def _contracted_by_quadrature(mol, shells, comps):
+    """sum over primitives of c c c c x (quadrature of the primitive integral)."""
+    tot = 0.0
+    ranges = [range(int(mol.shell_prim0[s]), int(mol.shell_prim0[s] + mol.shell_nprim[s]))
+              for s in shells]
+    cents = [mol.xyz[int(mol.shell_atom[s])] for s in shells]
+    for i in ranges[0]:
+        for j in ranges[1]:
+            for k in ranges[2]:
+                for m in ranges[3]:
+                    cc = mol.coefs[i] * mol.coefs[j] * mol.coefs[k] * mol.coefs[m]
+                    tot += cc * pins.eri_quadrature(comps[0], mol.exps[i], cents[0],
+                                                    comps[1], mol.exps[j], cents[1],
+                                                    comps[2], mol.exps[k], cents[2],
+                                                    comps[3], mol.exps[m], cents[3])
+    return tot
+
+
+@pytest.mark.parametrize("ls,ncomp", [((2, 0, 1, 0), 6), ((2, 2, 1, 1), 4), ((2, 2, 2, 2), 3)])
+def test_contracted_quartet_components(ls, ncomp):
+    """Contraction over primitives and the Cartesian component order of the
+    oracle's shell quartets: selected components of (ds|ps), (dd|pp), (dd|dd)
+    quartets of two-primitive shells on four centres."""
+    mol = _four_centre_basis(2, seed=sum(ls) + 40)
+    shells = [3 * at + l for at, l in enumerate(ls)]   # shell of angular momentum l on atom at
+    blk = oracle.shell_quartet(oracle.Basis(mol), *shells)
+    rng = np.random.default_rng(7 + sum(ls))
+    picks = {tuple(len(CART[l]) - 1 for l in ls), (0, 0, 0, 0)}
+    while len(picks) < ncomp:
+        picks.add(tuple(int(rng.integers(len(CART[l]))) for l in ls))
+    for idx in sorted(picks):
+        comps = [CART[l][i] for l, i in zip(ls, idx)]
+        ref = _contracted_by_quadrature(mol, shells, comps)
+        assert abs(blk[idx] - ref) <= 1e-11 * max(abs(ref), 1e-6), (idx, blk[idx], ref)
+
+
+@pytest.mark.parametrize("la,lb", [(2, 0), (1, 1)])
+def test_schwarz_factor_is_max_of_diagonal(la, lb):
+    """Q_AB^2 = max over components of (ab|ab), from quadrature values."""
+    mol = _four_centre_basis(1, seed=60 + la + lb)
+    A, B = 3 * 0 + la, 3 * 1 + lb
+    diag = []
+    for ca in CART[la]:
+        for cb in CART[lb]:
+            diag.append(_contracted_by_quadrature(mol, (A, B, A, B), (ca, cb, ca, cb)))
+    Q = oracle.schwarz(oracle.Basis(mol))
+    assert Q[A, B] ** 2 == pytest.approx(max(diag), rel=1e-11)
+    assert max(diag) < sum(diag)   # the max, not the sum, is what is pinned
+
+
+# --- timing-leg digestion and screening counts ---------------------------------------
+
+def test_bra_sample_over_all_pairs_equals_jk(w4):
+    """The timing leg over every unique bra pair gives orc_jk's accumulators:
+    its J + J^T equals the full J (and the same for K), with the same count."""
+    for tol in (0.0, 1e-6):
+        J, K, kept = oracle.jk(w4, tol)
+        npair = w4.n_shells * (w4.n_shells + 1) // 2
+        Js, Ks, ks = oracle.jk_bra_sample(w4, tol, np.arange(npair))
+        assert ks == kept
+        np.testing.assert_allclose(Js + Js.transpose(0, 2, 1), J, atol=1e-13, rtol=1e-13)
+        np.testing.assert_allclose(Ks + Ks.transpose(0, 2, 1), K, atol=1e-13, rtol=1e-13)
+        # disjoint samples add up to the whole
+        half = np.arange(0, npair, 2)
+        Ja, _, ka = oracle.jk_bra_sample(w4, tol, half)
+        Jb, _, kb = oracle.jk_bra_sample(w4, tol, np.arange(1, npair, 2))
+        assert ka + kb == kept
+        np.testing.assert_allclose(Ja + Jb, Js, atol=1e-14)
+
+
+def _pair_class_counts(mol):
+    ls = [int(x) for x in mol.shell_l]
+    n = np.zeros(6, dtype=np.int64)
+    for i in range(len(ls)):
+        for j in range(i + 1):
+            l1, l2 = max(ls[i], ls[j]), min(ls[i], ls[j])
+            n[l1 * (l1 + 1) // 2 + l2] += 1
+    return n
+
+
+def test_screen_counts_without_screening_are_combinatorial(w4):
+    counts, near = oracle.screen_counts(w4, 0.0, 0.0)
+    n = _pair_class_counts(w4)
+    for X in range(6):
+        for Y in range(X + 1):
+            q = X * (X + 1) // 2 + Y
+            want = n[X] * (n[X] + 1) // 2 if X == Y else n[X] * n[Y]
+            assert counts[q, 0] == want and counts[q, 1] == 0 and counts[q, 2] == 0
+    assert near.sum() == 0
+
+
+def test_screen_counts_match_a_direct_classification():
+    """Kept / single / skipped per class from the oracle's C++ loop against the
+    same rule applied in Python to its Schwarz matrix, and the kept total against
+    the quartets orc_jk computes."""
+    mol = molgen.make_molecule(3, 3, seed=21)
+    tol, thr = 1e-4, 3e-2
+    counts, _ = oracle.screen_counts(mol, tol, thr)
+    Q = oracle.schwarz(oracle.Basis(mol))
+    ls = [int(x) for x in mol.shell_l]
+    pairs = [(i, j) for i in range(len(ls)) for j in range(i + 1)]
+    pcls = [max(ls[i], ls[j]) * (max(ls[i], ls[j]) + 1) // 2 + min(ls[i], ls[j]) for i, j in pairs]
+    ref = np.zeros((21, 3), dtype=np.int64)
+    for a in range(len(pairs)):
+        for b in range(a + 1):
+            S = Q[pairs[a]] * Q[pairs[b]]
+            X, Y = max(pcls[a], pcls[b]), min(pcls[a], pcls[b])
+            ref[X * (X + 1) // 2 + Y, 2 if S < tol else (1 if S < thr else 0)] += 1
+    assert np.array_equal(counts, ref)
+    assert counts[:, 1].sum() > 0 and counts[:, 2].sum() > 0
+    _, _, kept = oracle.jk(mol, tol)
+    assert counts[:, 0].sum() + counts[:, 1].sum() == kept
+
+
+def test_gradient_rows_of_selected_atoms():
+    """The atom-restricted gradient gives exactly the selected rows of the full one."""
+    mol = molgen.make_molecule(2, 2, seed=11)
+    G = oracle.grad(mol, 1e-8)
+    Gs = oracle.grad(mol, 1e-8, atoms=[1, 3])
+    np.testing.assert_allclose(Gs[:, [1, 3]], G[:, [1, 3]], rtol=1e-12, atol=1e-14)
+    assert np.all(Gs[:, [0, 2]] == 0.0)
