@@ -1,23 +1,26 @@
 """Benchmark of the direct-SCF J/K build on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload w30] [--precision fp64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload w120] [--precision mixed]
                     [--no-cpu] [--no-extra]
 
 A step is one complete jk_build call: shell-pair data, Cauchy-Schwarz bounds,
-Q sort, screening and work lists, every integral+digestion kernel and the
-symmetrisation of J and K, on a seeded synthetic molecule whose density is
-already resident in device memory.  The default workload is the 30-atom,
-270-function molecule screened at 1e-10 in FP64.
+Q sort, screening and work lists, every integral+digestion kernel, the
+symmetrisation of J and K and the energies E_J, E_K, on a seeded synthetic
+molecule whose density is already resident in device memory.  The default
+workload is the 120-atom, 1080-function molecule screened at 1e-10 with the
+mixed-precision dispatch (FP32 integrals for Schwarz bounds below 1e-4); the
+same build in plain FP64 is timed beside it.
 
-Prints one JSON line.  `value` is screened quartets per second (unique shell
-quartets that pass the Schwarz screen, per build).  `roofline` describes the
-kernel with the most algorithmic work, which the library runs alone before
-spreading the other classes over three streams: algorithmic work per launch (flops
-of the generated recurrence, horizontal-recurrence and digestion code per
-quartet, plus a fixed count per primitive quartet for the Boys function and
-prefactors) divided by its mean launch time from HIP events recorded on the
-launch stream.  `cpu_baseline` is the CPU oracle timed on a bounded sample of
-bra pairs of the same molecule.
+Prints one JSON line.  `value` is screened quartets per second of the headline
+build (unique shell quartets that pass the Schwarz screen, per build).  The
+timed builds launch every class kernel on one stream in turn, so the HIP
+events the library records around each launch bracket that kernel's own run
+time; `roofline` describes the kernel with the largest share of the step time:
+its algorithmic work per launch (flops of the generated recurrence,
+horizontal-recurrence and digestion code per quartet, plus a fixed count per
+primitive quartet for the Boys function and prefactors) divided by its mean
+launch time.  `cpu_baseline` is the CPU oracle timed on a bounded, seeded
+sample of bra pairs of the same molecule.
 """
 from __future__ import annotations
 
@@ -30,8 +33,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP64_PEAK_TFLOPS = 78.6     # MI355X vector FP64 (256 CU x 2.4 GHz x 128 flop/clk)
-FP32_PEAK_TFLOPS = 157.3    # with packed FP32 (not used by these kernels: 78.6 unpacked)
+# MI355X vector peaks: 256 CU x 2.4 GHz x 64 lanes x 2 flop per FMA.  FP64 and
+# unpacked FP32 run one FMA per lane per clock; the FP32 vendor peak (157.3)
+# counts packed two-wide FP32 instructions, which these kernels do not use.
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 78.6
+FP32_PACKED_PEAK_TFLOPS = 157.3
 
 
 def prim_setup_flops(L: int) -> int:
@@ -54,9 +61,12 @@ def flops_per_quartet(info, npp_b=9, npp_k=9, n_dm=1):
             + info["hrr_flops"] + n_dm * info["digest_flops"])
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_w30_fp64.md")
 FINGERPRINT_SOURCES = ["paper_2406_11185_amd/csrc/gen_hgp.py", "paper_2406_11185_amd/csrc/jk_device.hpp",
                        "paper_2406_11185_amd/csrc/jk_host.hip", "paper_2406_11185_amd/csrc/jk_classes.hpp"]
+
+
+def traffic_file(workload, precision):
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{precision}.md")
 
 
 def source_fingerprint() -> str:
@@ -79,7 +89,8 @@ def kernel_key(name: str):
     return f"eri_jk {m.group(1)} {'fp64' if m.group(2) == 'double' else 'fp32'}"
 
 
-def pmc_summary(fetch_csv: str, write_csv: str, out: str, calib_mib: int, command: str) -> None:
+def pmc_summary(fetch_csv: str, write_csv: str, out: str, calib_mib: int, command: str,
+                title: str) -> None:
     """Per-dispatch HBM bytes of every J/K class kernel from two rocprofv3 --pmc
     runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), scaled by what the same
     counters read for the copy of calib_mib MiB made before the steps."""
@@ -105,7 +116,7 @@ def pmc_summary(fetch_csv: str, write_csv: str, out: str, calib_mib: int, comman
     write, wcopy = load(write_csv, "WRITE_SIZE")
     known = calib_mib * 1024.0
     fs, ws = known / fcopy, known / wcopy
-    lines = ["# HBM traffic per dispatch: J/K build, 30 atoms / 270 functions, tol 1e-10, FP64", "",
+    lines = [f"# HBM traffic per dispatch: J/K build, {title}", "",
              "Two rocprofv3 counter runs of the benchmark (kernels are serialised while counters "
              "are collected), from the repository root on the GPU box:", "", "```",
              command.replace("PMC", "FETCH_SIZE"), command.replace("PMC", "WRITE_SIZE"), "```", "",
@@ -129,11 +140,11 @@ def pmc_summary(fetch_csv: str, write_csv: str, out: str, calib_mib: int, comman
     print("\n".join(lines))
 
 
-def traffic_of(kernel: str):
+def traffic_of(kernel: str, workload: str, precision: str):
     """HBM bytes per dispatch of `kernel` from the committed counter summary, or
     None if there is none or the kernel sources changed since it was taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(workload, precision)) as fh:
             text = fh.read()
     except OSError:
         return None
@@ -146,8 +157,9 @@ def traffic_of(kernel: str):
     return None
 
 
-def cpu_baseline(mol, tol, seconds_target=15.0):
-    """Oracle timed on a growing sample of unique bra pairs (all their kets)."""
+def cpu_baseline(mol, tol, gpu_quartets, seconds_target=15.0):
+    """Oracle timed on a growing seeded sample of unique bra pairs (all their
+    kets), its rate extrapolated to the whole build by screened-quartet count."""
     import numpy as np
     import oracle
     npair = mol.n_shells * (mol.n_shells + 1) // 2
@@ -165,36 +177,141 @@ def cpu_baseline(mol, tol, seconds_target=15.0):
         kept_total += kept
         used += len(idx)
         take *= 2
-    return {"value": kept_total / spent, "unit": "quartets/s", "cores": nthreads,
-            "kind": "oracle",
+    rate = kept_total / spent
+    return {"value": rate, "unit": "quartets/s", "cores": nthreads, "kind": "oracle",
             "sample": f"{used} of {npair} unique bra shell pairs (seeded), all their ket pairs: "
-                      f"{kept_total} screened quartets in {spent:.1f} s"}
+                      f"{kept_total} screened quartets in {spent:.1f} s; extrapolated to the "
+                      f"{gpu_quartets} screened quartets of one build: {gpu_quartets / rate:.0f} s "
+                      f"per build (extrapolated)"}
 
 
 def run_steps(jkb, ctx, basis, D, J, K, tol, opts, steps, torch):
-    per_step = []
     stats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        ts = time.perf_counter()
         jkb.jk_build(ctx, basis, D, J, K, tol, opts)
-        st = ctx.stats()          # waits for this step's events
-        per_step.append(time.perf_counter() - ts)
-        stats.append(st)
+        stats.append(ctx.stats())     # waits for this step's events
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, per_step, stats
+    return time.perf_counter() - t0, stats
+
+
+def class_table(stats, infos, n_dm):
+    """Per (class, precision): summed event ms, launches and quartets over the steps."""
+    agg = {}
+    for s in stats:
+        for q in range(21):
+            for pr, ms_arr, n_arr, qa in ((0, s.ms_kernel_fp64, s.launches_fp64, s.quartets_fp64),
+                                          (1, s.ms_kernel_fp32, s.launches_fp32, s.quartets_fp32)):
+                if n_arr[q]:
+                    a = agg.setdefault((q, pr), [0.0, 0, 0])
+                    a[0] += ms_arr[q]
+                    a[1] += n_arr[q]
+                    a[2] += qa[q]
+    return agg
+
+
+def progress(msg):
+    print(f"[bench] {msg} ({time.strftime('%H:%M:%S')})", file=sys.stderr, flush=True)
+
+
+def extra_measurements(args, jkb, molgen, ctx, mol, basis, D, J, K, E_head, tol, precision,
+                       ms_per_step, torch):
+    """The same build in the other precision (time, speedup, energy differences),
+    the paper's own FP32 threshold (tolerance x 1e5), and the nuclear gradient:
+    of the 30-atom molecule, or of the workload itself (autograd through
+    JKEnergy) when it carries several densities."""
+    import numpy as np
+    dev = D.device
+    n_dm = int(D.shape[0])
+    ex = {}
+    other = "fp64" if precision == "mixed" else "mixed"
+    E2 = torch.empty((n_dm, 3), dtype=torch.float64, device=dev)
+    J_head, K_head = J.clone(), K.clone()
+    o2 = jkb.make_opts(other, n_dm=n_dm, timing=True, serial=True, energy=E2)
+    nrep = 2 if n_dm == 1 else 1
+    if n_dm == 1:
+        jkb.jk_build(ctx, basis, D, J, K, tol, o2)
+    t2, _ = run_steps(jkb, ctx, basis, D, J, K, tol, o2, nrep, torch)
+    progress(f"{other} builds done")
+    E_other = E2.cpu().numpy()
+    ex[f"{other}_ms"] = 1e3 * t2 / nrep
+    ex[f"{precision}_ms"] = ms_per_step
+    fp64_ms = ex["fp64_ms"]
+    ex["mixed_speedup_over_fp64"] = fp64_ms / ex["mixed_ms"]
+    E64 = E_other if other == "fp64" else E_head
+    Emx = E_head if other == "fp64" else E_other
+    ex["mixed_dEJ"] = float(np.abs(Emx[:, 0] - E64[:, 0]).max())
+    ex["mixed_dEK"] = float(np.abs(Emx[:, 1] - E64[:, 1]).max())
+    ex["mixed_max_abs_dJ"] = float((J - J_head).abs().max())
+    ex["mixed_max_abs_dK"] = float((K - K_head).abs().max())
+    del J_head, K_head
+    if n_dm == 1:
+        # the paper's own single-precision threshold, tolerance x 1e5
+        o3 = jkb.make_opts("mixed", fp32_below=tol * 1e5, n_dm=n_dm, timing=True, serial=True,
+                           energy=E2)
+        t3, s3 = run_steps(jkb, ctx, basis, D, J, K, tol, o3, 1, torch)
+        E3 = E2.cpu().numpy()
+        ex["mixed_paper_threshold"] = {
+            "fp32_below": tol * 1e5, "ms": 1e3 * t3, "speedup_over_fp64": fp64_ms / (1e3 * t3),
+            "quartets_fp32": int(sum(s3[-1].quartets_fp32)),
+            "dEJ": float(E3[0, 0] - E64[0, 0]), "dEK": float(E3[0, 1] - E64[0, 1])}
+    if n_dm == 1 and args.with_grad:
+        # nuclear gradient of the 30-atom molecule, FP64 and mixed
+        mg = molgen.workload("w30grad")
+        bg = jkb.Basis(mg)
+        tg_tol = molgen.WORKLOADS["w30grad"]["tol"]
+        Dg = torch.as_tensor(mg.D, device=dev).contiguous()
+        G = torch.empty((Dg.shape[0], mg.n_atoms, 3), dtype=torch.float64, device=dev)
+        for prec in ("fp64", "mixed"):
+            og = jkb.make_opts(prec, n_dm=int(Dg.shape[0]))
+            jkb.jk_grad(ctx, bg, Dg, G, tg_tol, og)
+            torch.cuda.synchronize()
+            tg = time.perf_counter()
+            for _ in range(2):
+                jkb.jk_grad(ctx, bg, Dg, G, tg_tol, og)
+            torch.cuda.synchronize()
+            ex[f"w30_grad_{prec}_ms"] = 1e3 * (time.perf_counter() - tg) / 2
+    elif args.with_grad:
+        # the workload's own gradient, mixed through autograd (forward build and
+        # backward derivative kernels), and the FP64 gradient for the error
+        xyz = torch.tensor(mol.xyz, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        Eg = jkb.JKEnergy.apply(xyz, D, mol, tol, "mixed")
+        torch.cuda.synchronize()
+        ex["autograd_forward_mixed_s"] = time.perf_counter() - t
+        progress("autograd forward done")
+        t = time.perf_counter()
+        Eg.sum().backward()
+        torch.cuda.synchronize()
+        ex["grad_mixed_s"] = time.perf_counter() - t
+        progress("autograd backward (mixed gradient) done")
+        Gm = xyz.grad.numpy().copy()
+        G = torch.empty((n_dm, mol.n_atoms, 3), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        jkb.jk_grad(ctx, basis, D, G, tol, jkb.make_opts("fp64", n_dm=n_dm))
+        torch.cuda.synchronize()
+        ex["grad_fp64_s"] = time.perf_counter() - t
+        progress("FP64 gradient done")
+        G64 = G.cpu().numpy().sum(axis=0)
+        ex["grad_mixed_max_abs_err_vs_fp64"] = float(np.abs(Gm - G64).max())
+    return ex
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="w30")
+    ap.add_argument("--workload", default="w120")
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--with-grad", action="store_true",
+                    help="also time the nuclear gradient (jk_grad), which is kept off the GPU "
+                         "by default while a fault in it is open")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB once (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -204,31 +321,32 @@ def main():
     ap.add_argument("--pmc-command", default="",
                     help="with --pmc-summary: the profiled command, PMC standing for the counter")
     args = ap.parse_args()
+    from paper_2406_11185_amd import molgen
+    w = molgen.WORKLOADS[args.workload]
+    precision = args.precision or w["precision"]
     if args.pmc_summary:
-        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], TRAFFIC_FILE,
-                    args.copy_calib_mib or 256, args.pmc_command)
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], traffic_file(args.workload, precision),
+                    args.copy_calib_mib or 256, args.pmc_command, f"{w['desc']}, {precision}")
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_2406_11185_amd import jk as jkb
-    from paper_2406_11185_amd import molgen
 
-    w = molgen.WORKLOADS[args.workload]
-    precision = args.precision or w["precision"]
     tol = w["tol"]
     mol = molgen.workload(args.workload)
     basis = jkb.Basis(mol)
     dev = torch.device("cuda:0")
     D = torch.as_tensor(mol.D, device=dev).contiguous()
+    n_dm = int(D.shape[0])
     J = torch.empty_like(D)
     K = torch.empty_like(D)
+    E = torch.empty((n_dm, 3), dtype=torch.float64, device=dev)
     ctx = jkb.Context(0)
-    opts = jkb.make_opts(precision, n_dm=D.shape[0], timing=True)
+    opts = jkb.make_opts(precision, n_dm=n_dm, timing=True, serial=True, energy=E)
 
     if args.copy_calib_mib:
         src = torch.ones(args.copy_calib_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
@@ -239,29 +357,20 @@ def main():
     for _ in range(args.warmup):
         jkb.jk_build(ctx, basis, D, J, K, tol, opts)
     torch.cuda.synchronize()
-    total, per_step, stats = run_steps(jkb, ctx, basis, D, J, K, tol, opts, args.steps, torch)
+    total, stats = run_steps(jkb, ctx, basis, D, J, K, tol, opts, args.steps, torch)
+    progress(f"{args.steps} timed {precision} builds done")
     ms_per_step = 1e3 * total / args.steps
     st = stats[-1]
     quartets = sum(st.quartets_fp64) + sum(st.quartets_fp32)
+    E_head = E.cpu().numpy().copy()
 
-    # dominant kernel: the class launch with the most algorithmic work per step
-    # (the library runs its largest launch alone, so its event interval is its
-    # own run time; launches that share the GPU have stretched intervals)
+    # dominant kernel: the class launch with the largest share of the step time
+    # (serial launches: each event interval is that kernel's own run time)
     infos = class_info()
-    agg = {}
-    for s in stats:
-        for q in range(jkb.JK_NCLASS):
-            for pr, ms_arr, n_arr, qa in ((0, s.ms_kernel_fp64, s.launches_fp64, s.quartets_fp64),
-                                          (1, s.ms_kernel_fp32, s.launches_fp32, s.quartets_fp32)):
-                if n_arr[q]:
-                    a = agg.setdefault((q, pr), [0.0, 0, 0])
-                    a[0] += ms_arr[q]
-                    a[1] += n_arr[q]
-                    a[2] += qa[q]
-    (qd, prd), (ms_sum, nlaunch, nq) = max(
-        agg.items(), key=lambda kv: flops_per_quartet(infos[kv[0][0]], n_dm=D.shape[0]) * kv[1][2])
+    agg = class_table(stats, infos, n_dm)
+    (qd, prd), (ms_sum, nlaunch, nq) = max(agg.items(), key=lambda kv: kv[1][0])
     info = infos[qd]
-    flops_launch = flops_per_quartet(info, n_dm=D.shape[0]) * nq / nlaunch
+    flops_launch = flops_per_quartet(info, n_dm=n_dm) * nq / nlaunch
     mean_s = ms_sum / nlaunch / 1e3
     achieved = flops_launch / mean_s / 1e12
     peak = FP64_PEAK_TFLOPS if prd == 0 else FP32_PEAK_TFLOPS
@@ -269,9 +378,17 @@ def main():
     total_kernel_ms = sum(a[0] for a in agg.values()) / len(stats)
     total_flops = 0.0
     for (q, pr), a in agg.items():
-        total_flops += flops_per_quartet(infos[q], n_dm=D.shape[0]) * a[2] / len(stats)
+        total_flops += flops_per_quartet(infos[q], n_dm=n_dm) * a[2] / len(stats)
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": traffic_of(kname, args.workload, precision),
+            "kernel": kname, "flops_per_launch": flops_launch, "mean_launch_ms": mean_s * 1e3,
+            "launches": nlaunch}
+    if prd == 1:
+        roof["peak_packed_fp32"] = FP32_PACKED_PEAK_TFLOPS
+        roof["frac_of_packed_fp32"] = achieved / FP32_PACKED_PEAK_TFLOPS
     result = {
-        "metric": "screened ERI quartets/s of the J+K build",
+        "metric": "J+K build: screened ERI quartets/s (FP64 vs mixed build seconds and gradient "
+                  "seconds in extra)",
         "value": quartets / (total / args.steps),
         "unit": "quartets/s",
         "n_gpus": 1,
@@ -281,63 +398,33 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if precision == "fp64" else "f64+f32",
+        "dtype": "f64" if precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {w['desc']}", "atoms": mol.n_atoms,
                    "basis_functions": mol.n_bf, "tol": tol, "precision": precision,
-                   "n_dm": int(D.shape[0]), "screened_quartets": int(quartets),
-                   "skipped_quartets": int(st.quartets_skipped)},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak,
-                     "traffic": traffic_of(kname) if args.workload == "w30" and precision == "fp64"
-                     else None,
-                     "kernel": kname,
-                     "flops_per_launch": flops_launch, "mean_launch_ms": mean_s * 1e3,
-                     "launches": nlaunch},
+                   "fp32_below": 1e-4 if precision == "mixed" else None,
+                   "n_dm": n_dm, "screened_quartets": int(quartets),
+                   "quartets_fp32": int(sum(st.quartets_fp32)),
+                   "skipped_quartets": int(st.quartets_skipped), "launches": "serial"},
+        "roofline": roof,
         "build_kernel_ms": total_kernel_ms,
         "classes": {f"{infos[q]['name']}_{'fp32' if pr else 'fp64'}":
                     {"ms": round(a[0] / len(stats), 3), "quartets": int(a[2] / len(stats)),
-                     "tflops": round(flops_per_quartet(infos[q], n_dm=D.shape[0]) * a[2]
+                     "tflops": round(flops_per_quartet(infos[q], n_dm=n_dm) * a[2]
                                      / (a[0] / 1e3) / 1e12, 3) if a[0] > 0 else None}
                     for (q, pr), a in sorted(agg.items())},
         # algorithmic flops of all class launches of a step over the step time
         "build_tflops": total_flops / (ms_per_step / 1e3) / 1e12,
         "setup_ms": st.ms_setup,
+        "energies": {"E_J": float(E_head[0, 0]), "E_K": float(E_head[0, 1])},
     }
 
-    if not args.no_extra and args.workload == "w30":
-        ex = {}
-        mol2 = molgen.workload("w120")
-        b2 = jkb.Basis(mol2)
-        D2 = torch.as_tensor(mol2.D, device=dev).contiguous()
-        J2, K2 = torch.empty_like(D2), torch.empty_like(D2)
-        res = {}
-        for prec in ("fp64", "mixed"):
-            o2 = jkb.make_opts(prec, timing=True)
-            jkb.jk_build(ctx, b2, D2, J2, K2, 1e-10, o2)
-            tt, _, sts = run_steps(jkb, ctx, b2, D2, J2, K2, 1e-10, o2, 2, torch)
-            res[prec] = (J2.double().cpu().numpy(), K2.double().cpu().numpy())
-            ex[f"w120_{prec}_ms"] = 1e3 * tt / 2
-            ex[f"w120_{prec}_quartets_fp32"] = int(sum(sts[-1].quartets_fp32))
-        EJ = {p: 0.5 * float(np.sum(mol2.D[0] * res[p][0][0])) for p in res}
-        EK = {p: 0.25 * float(np.sum(mol2.D[0] * res[p][1][0])) for p in res}
-        ex["w120_mixed_speedup"] = ex["w120_fp64_ms"] / ex["w120_mixed_ms"]
-        # nuclear gradient of the 30-atom molecule (same geometry and density)
-        G = torch.empty((D.shape[0], mol.n_atoms, 3), dtype=torch.float64, device=dev)
-        og = jkb.make_opts("fp64", n_dm=D.shape[0])
-        jkb.jk_grad(ctx, basis, D, G, tol, og)
-        torch.cuda.synchronize()
-        tg = time.perf_counter()
-        for _ in range(2):
-            jkb.jk_grad(ctx, basis, D, G, tol, og)
-        torch.cuda.synchronize()
-        ex["w30_grad_ms"] = 1e3 * (time.perf_counter() - tg) / 2
-        ex["w120_dEJ"] = EJ["mixed"] - EJ["fp64"]
-        ex["w120_dEK"] = EK["mixed"] - EK["fp64"]
-        result["extra"] = ex
+    if not args.no_extra:
+        result["extra"] = extra_measurements(args, jkb, molgen, ctx, mol, basis, D, J, K, E_head,
+                                             tol, precision, ms_per_step, torch)
 
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(mol, tol)
+        result["cpu_baseline"] = cpu_baseline(mol, tol, quartets)
     print(json.dumps(result), flush=True)
 
 

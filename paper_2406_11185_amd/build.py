@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import argparse
 import concurrent.futures as cf
+import fcntl
 import os
 import shutil
 import subprocess
@@ -55,20 +56,29 @@ def _deps_newer(src: str, obj: str) -> bool:
 def _compile(src: str, obj: str, verbose: bool, incremental: bool = False) -> tuple[str, float]:
     if incremental and not _deps_newer(src, obj):
         return src, 0.0
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-I", GEN, "-c", src, "-o",
-           obj + ".tmp"]
+    # the temporary object is private to this build process: a compile left over
+    # from an interrupted build can never be renamed into place by another one
+    tmp = f"{obj}.{os.getpid()}.tmp"
+    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-I", GEN, "-c", src, "-o", tmp]
     t = time.time()
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
-    os.replace(obj + ".tmp", obj)
+    os.replace(tmp, obj)
     return src, time.time() - t
 
 
 def build(jobs: int = 0, verbose: bool = False, incremental: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
+    # one build at a time in this tree (generated sources and objects are shared)
+    with open(os.path.join(BUILD, ".lock"), "w") as lock:
+        fcntl.flock(lock, fcntl.LOCK_EX)
+        return _build_locked(jobs, verbose, incremental)
+
+
+def _build_locked(jobs: int, verbose: bool, incremental: bool) -> str:
     sys.path.insert(0, CSRC)
     try:
         import gen_hgp  # noqa: E402
@@ -94,9 +104,10 @@ def build(jobs: int = 0, verbose: bool = False, incremental: bool = False) -> st
             src, dt = f.result()
             if verbose:
                 print(f"  {os.path.basename(src)}: {dt:.1f}s", flush=True)
-    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", LIB + ".tmp", *objs]
+    tmp = f"{LIB}.{os.getpid()}.tmp"
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(tmp, LIB)
     return LIB
 
 

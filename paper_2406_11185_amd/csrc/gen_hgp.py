@@ -291,16 +291,16 @@ class HRR(Code):
 
 # Wavefronts per SIMD each class kernel is compiled for, per precision (FP64 / FP32
 # value size in bytes); classes not listed take 1 (all 512 registers of a lane).
-# JK_WAVES_OVERRIDE="size:waves" (e.g. "4:2") overrides one precision for every
-# class, for measurements.
+# JK_WAVES_OVERRIDE="kind:size:waves,..." (kind = single or split) overrides the
+# listed kernels of one precision, for measurements.
 CLASS_WAVES = {}
 
 
-def class_waves(name, size):
+def class_waves(name, size, split=False):
     ov = os.environ.get("JK_WAVES_OVERRIDE", "")
     for item in filter(None, ov.split(",")):
-        sz, w = item.split(":")
-        if int(sz) == size:
+        kind, sz, w = item.split(":")
+        if int(sz) == size and kind == ("split" if split else "single"):
             return int(w)
     return CLASS_WAVES.get((name, size), 1)
 
@@ -313,6 +313,38 @@ def lanes_for(L, split):
 
 
 LDS_MAX_L = 3   # single-pass classes up to this order read the Boys rows from LDS
+ROWS_BLOCK = 512   # threads of the light-class kernel that keeps the bra's K rows in LDS
+# Light classes and precisions that use the rows kernel ("name:size"); JK_ROWS_OVERRIDE
+# = "all" or "none" for measurements.
+ROWS_CLASSES = None   # None: every light class in both precisions
+
+
+def uses_rows(name, size):
+    ov = os.environ.get("JK_ROWS_OVERRIDE", "")
+    if ov == "none":
+        return False
+    if ov == "all" or ROWS_CLASSES is None:
+        return True
+    return f"{name}:{size}" in ROWS_CLASSES
+
+
+def rows_call(name, t):
+    size = 8 if t == "double" else 4
+    if not uses_rows(name, size):
+        return "false"
+    return f"launch_rows<Cls_{name}, {t}, {ROWS_BLOCK}>(a, s)"
+
+# Single-pass classes whose kernels digest in five sweeps (one J/K block each).
+# JK_SWEEPS_OVERRIDE=1 turns sweeps on for every class above LDS_MAX_L, for
+# measurements.
+SWEEP_CLASSES = set()
+
+
+def uses_sweeps(name):
+    if os.environ.get("JK_SWEEPS_OVERRIDE") == "1":
+        L = sum("spd".index(ch) for ch in name)
+        return L > LDS_MAX_L
+    return name in SWEEP_CLASSES
 
 
 def uses_lds(L, split):
@@ -359,6 +391,33 @@ def gen_class(la, lb, lc, ld):
     hrr_flops = hrr.flops
     dig_flops = 13 * n_int
 
+    # The same horizontal recurrences split into five sweeps, each digesting into
+    # one block (J: jab and jcd; then kac, kad, kbc, kbd): a sweep holds only its
+    # own D block and accumulators live, at the price of recomputing the HRR.
+    sweeps = []
+    blocks = [("j", None), ("kac", ("Dbd", "ib * nd + id_", "ia * nc + ic")),
+              ("kad", ("Dbc", "ib * nc + ic", "ia * nd + id_")),
+              ("kbc", ("Dad", "ia * nd + id_", "ib * nc + ic")),
+              ("kbd", ("Dac", "ia * nc + ic", "ib * nd + id_"))]
+    for bname, spec in blocks:
+        hs = HRR(la, lb, lc, ld)
+        for ia, a in enumerate(A):
+            for ib, b in enumerate(B):
+                for ic, c in enumerate(C):
+                    for id_, d in enumerate(D):
+                        h = hs.node(a, b, c, d)
+                        if spec is None:
+                            hs.lines.append(
+                                f"{{ const double v = double({h}) * fq;"
+                                f" jab[{ia * nb + ib}] += Dcd[{ic * nd + id_}] * v;"
+                                f" jcd[{ic * nd + id_}] += Dab[{ia * nb + ib}] * v; }}")
+                        else:
+                            dn, di, oi = spec
+                            env = dict(ia=ia, ib=ib, ic=ic, id_=id_, na=na, nb=nb, nc=nc, nd=nd)
+                            hs.lines.append(f"{bname}[{eval(oi, env)}] += {dn}[{eval(di, env)}] * "
+                                            f"(double({h}) * fq);")
+        sweeps.append((bname, hs.lines))
+
     diag_code = None
     if (la, lb) == (lc, ld):
         dh = HRR(la, lb, lc, ld)
@@ -400,6 +459,17 @@ def gen_class(la, lb, lc, ld):
     s.append("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz;")
     s += ["    " + x for x in hrr.lines]
     s.append("  }")
+    s.append(f"  static constexpr int SWEEPS = {1 if uses_sweeps(name) else 0};  // digestion in five sweeps")
+    sig = {"j": "const double* Dab, const double* Dcd, double* jab, double* jcd",
+           "kac": "const double* Dbd, double* kac", "kad": "const double* Dbc, double* kad",
+           "kbc": "const double* Dad, double* kbc", "kbd": "const double* Dac, double* kbd"}
+    for bname, lines in sweeps:
+        s.append("  template <typename T>")
+        s.append(f"  __device__ __forceinline__ static void digest_{bname}(const T* __restrict__ acc, T ABx, T ABy,"
+                 f" T ABz, T CDx, T CDy, T CDz, double fq, {sig[bname]}) {{")
+        s.append("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz;")
+        s += ["    " + x for x in lines]
+        s.append("  }")
     if diag_code is not None:
         s.append("  template <typename T>")
         s.append("  __device__ __forceinline__ static double diag_max(const T* __restrict__ acc, T ABx, T ABy,"
@@ -533,7 +603,8 @@ def gen_split_class(la, lb, lc, ld):
     s.append(f"  static constexpr int NE = {ne}, NF = {nf}, NACC = {ne * nf};")
     s.append(f"  static constexpr int NPASS = {len(chunks)}, ECHUNK = {chunk};")
     s.append(f"  static constexpr int GMAX = {lanes_for(L, True)};  // most lanes per shell quartet")
-    s.append(f"  static constexpr int WAVES64 = {class_waves(name, 8)}, WAVES32 = {class_waves(name, 4)};")
+    s.append(f"  static constexpr int WAVES64 = {class_waves(name, 8, True)}, "
+             f"WAVES32 = {class_waves(name, 4, True)};")
     vrr_flops = 0
     for j, ch in enumerate(chunks):
         outs = [(ii * nf + jf, E[ie], f) for ii, ie in enumerate(ch) for jf, f in enumerate(Fs)]
@@ -611,7 +682,10 @@ def wrapper(info):
          "namespace jk {",
          f'#include "cls_{n}.inc"',
          f"void launch_eri_{n}(const EriLaunch& a, int fp32, hipStream_t s) {{",
-         *([f"  // Boys rows staged in LDS; as many workgroups as fit on the device claim the items",
+         *([f"  // the bra's exchange rows in LDS, where they fit",
+            f"  if (a.rows && (fp32 ? {rows_call(n, 'float')}",
+            f"                      : {rows_call(n, 'double')})) return;",
+            f"  // Boys rows staged in LDS; as many workgroups as fit on the device claim the items",
             f"  constexpr int NT = {info.get('lds_block', 0)};",
             f"  static int per_cu[2] = {{0, 0}};",
             f"  if (!per_cu[fp32]) {{",

@@ -17,6 +17,38 @@ inline void launch_kernel(void (*k)(P...), dim3 grid, dim3 block, size_t lds, hi
   (void)hipLaunchKernel(reinterpret_cast<const void*>(k), grid, block, argv, lds, s);
 }
 
+// Light class with the bra's exchange rows in LDS (eri_jk_rows_kernel): launched
+// if its static and dynamic LDS fit one workgroup on the device, else false and
+// nothing is launched.  The kernel attributes are read once per instantiation
+// (one device per process).
+template <class C, typename T, int NT>
+bool launch_rows(const EriLaunch& a, hipStream_t s) {
+  static size_t static_bytes = 0;
+  static int max_lds = -1;
+  const void* k = reinterpret_cast<const void*>(&eri_jk_rows_kernel<C, T, NT>);
+  if (max_lds < 0) {
+    hipFuncAttributes fa{};
+    int dev = 0, lds = 0;
+    if (hipFuncGetAttributes(&fa, k) == hipSuccess && hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) {
+      static_bytes = fa.sharedSizeBytes;
+      max_lds = lds;
+    } else {
+      max_lds = 0;
+    }
+    (void)hipGetLastError();
+  }
+  const size_t dyn = rows_lds_doubles<C>(a.n) * sizeof(double);
+  if (static_bytes + dyn > static_cast<size_t>(max_lds)) return false;
+  if (!a.dry) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn));
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, NT, dyn) != hipSuccess || nb < 1) nb = 1;
+  (void)hipGetLastError();
+  const dim3 grid(static_cast<unsigned>(std::min(a.nitems, nb * a.num_cu)));
+  launch_kernel(&eri_jk_rows_kernel<C, T, NT>, grid, dim3(NT), dyn, s, a.dry != 0, a);
+  return true;
+}
+
 // Integral + digestion kernel of quartet class `cls` (0..20, bra class X >= ket
 // class Y, index X(X+1)/2 + Y over pair classes ss, ps, pp, ds, dp, dd).
 void launch_eri(int cls, int fp32, const EriLaunch& a, hipStream_t s);

@@ -68,6 +68,8 @@ struct BinView {
   int n, npp;
   const double* prim;
   const double* primT;   // the same primitive-pair fields pair-major: [n][npp][kPrimFields]
+  const float* prim32;   // FP32 copies of prim and primT (the FP32 kernels read these)
+  const float* primT32;
   const double* A;
   const double* AB;
   const int* bf;
@@ -99,6 +101,8 @@ struct EriLaunch {
   size_t det_lo;      // 0: J/K accumulate with FP64 atomics; else deterministic mode, the
                       // accumulators are int64 fixed-point pairs (see atomic_add)
   int dry;            // host only: 1 = check the launch (scratch guard) without launching
+  int rows;           // light classes: 1 = the bra's exchange rows may be kept in LDS
+                      // (one density, atomic accumulation), if they fit
 };
 
 // Persistent kernels: each wavefront claims work items one at a time.
@@ -172,10 +176,7 @@ __device__ __forceinline__ BoysRow64 boys64_fetch(double T, const double* __rest
 }
 
 template <int L>
-__device__ __forceinline__ void boys64_eval(double T, const BoysRow64& row, double tmax, double* F) {
-  static_assert(L <= kBoysMaxL, "Boys table order");
-  const bool near = T < tmax;
-  const double Tt = near ? T : 0.0;
+__device__ __forceinline__ void boys64_taylor(double Tt, const BoysRow64& row, double* F) {
   const double x = row.x;
   const double r[8] = {row.q0.x, row.q0.y, row.q1.x, row.q1.y,
                        row.q2.x, row.q2.y, row.q3.x, row.q3.y};
@@ -189,8 +190,7 @@ __device__ __forceinline__ void boys64_eval(double T, const BoysRow64& row, doub
   s = r[2] + x3 * s;
   s = r[1] + x2 * s;
   s = r[0] + x * s;
-  double Ft[L + 1];
-  Ft[L] = s;
+  F[L] = s;
   if constexpr (L > 0) {
     double e = 1.0 + x6;
     e = 1.0 + x5 * e;
@@ -201,30 +201,61 @@ __device__ __forceinline__ void boys64_eval(double T, const BoysRow64& row, doub
     e *= r[7];
     const double T2 = 2.0 * Tt;
 #pragma unroll
-    for (int m = L - 1; m >= 0; --m) Ft[m] = (T2 * Ft[m + 1] + e) * kInvOdd[m];
+    for (int m = L - 1; m >= 0; --m) F[m] = (T2 * F[m + 1] + e) * kInvOdd[m];
   }
-  const double Ta = near ? tmax : T;
-  const double rs = rsqrt_f64(Ta);
+}
+
+template <int L>
+__device__ __forceinline__ void boys64_asym(double T, double* F) {
+  const double rs = rsqrt_f64(T);
   double fa = 0.88622692545275801364908374167057 * rs;  // sqrt(pi)/2 / sqrt(T)
   const double h = 0.5 * rs * rs;
-  F[0] = near ? Ft[0] : fa;
+  F[0] = fa;
 #pragma unroll
   for (int m = 0; m < L; ++m) {
     fa *= (2 * m + 1) * h;
-    F[m + 1] = near ? Ft[m + 1] : fa;
+    F[m + 1] = fa;
+  }
+}
+
+// The kets of a wavefront are neighbours in a Q-sorted list, so their T are
+// mostly all below or all above tmax: each form is evaluated only if some lane
+// of the wavefront needs it.
+template <int L>
+__device__ __forceinline__ void boys64_eval(double T, const BoysRow64& row, double tmax, double* F) {
+  static_assert(L <= kBoysMaxL, "Boys table order");
+  const bool near = T < tmax;
+  if (__all(near)) {
+    boys64_taylor<L>(T, row, F);
+  } else if (__all(!near)) {
+    boys64_asym<L>(T, F);
+  } else {
+    double Ft[L + 1], Fa[L + 1];
+    boys64_taylor<L>(near ? T : 0.0, row, Ft);
+    boys64_asym<L>(near ? tmax : T, Fa);
+#pragma unroll
+    for (int m = 0; m <= L; ++m) F[m] = near ? Ft[m] : Fa[m];
   }
 }
 
 // F_m(T), m = 0..L, for the FP32 kernels.  T <= boys_fp64_T (<= 30): four-term
 // Taylor expansion in FP32 from the FP32 table and downward recursion in FP32.
-// Larger T: the FP64 evaluation above (table Taylor step below T = 64,
-// asymptotic form beyond), rounded to FP32; it is exact to FP64 rounding at
-// any T, so every accepted boys_fp64_T gives FP32-accurate values.
+// T > 30: in FP64, the asymptotic F_0 = sqrt(pi/(4T)) (relative error
+// erfc(sqrt T) < 2e-14) and upward recursion F_{m+1} = ((2m+1) F_m - e^{-T})/(2T),
+// rounded to FP32.  e^{-T} itself enters only through that recursion, where at
+// T > 30 it changes F_m by less than 4e-6 of its value for every m <= 9, so
+// the FP32 exponential (relative error ~1e-7) leaves the result exact to FP32
+// rounding; the reciprocal square root takes one Newton step from the hardware
+// estimate (~1e-12 relative, below what the FP32 result keeps).
+// boys_fp64_T < T <= 30 (only when the switch-over is set below 30): the FP64
+// table evaluation above, exact to FP64 rounding at any T.
 struct BoysRow32 {
   float4 q0;    // F_L(T_i) ... F_{L+3}(T_i)
   float e;      // exp(-T_i)
   float x;      // T_i - T
 };
+
+constexpr float kBoys32Asym = 30.0f;   // FP64 asymptotic form above this T
 
 // rows: FP32 table of order L.
 template <int L>
@@ -239,7 +270,7 @@ __device__ __forceinline__ BoysRow32 boys32_fetch(float T, float tcut, const flo
   return r;
 }
 
-// rows64: FP64 table of order L (global), read only by lanes with T > tcut.
+// rows64: FP64 table of order L (global), read only for boys_fp64_T < T <= 30.
 template <int L>
 __device__ __forceinline__ void boys32_eval(float T, float tcut, const BoysRow32& row,
                                             const double* __restrict__ rows64, float* F) {
@@ -259,6 +290,21 @@ __device__ __forceinline__ void boys32_eval(float T, float tcut, const BoysRow32
       const float T2 = 2.0f * T;
 #pragma unroll
       for (int m = L - 1; m >= 0; --m) F[m] = (T2 * F[m + 1] + e) * static_cast<float>(kInvOdd[m]);
+    }
+  } else if (T > kBoys32Asym) {
+    const double Td = static_cast<double>(T);
+    double rs = __builtin_amdgcn_rsq(Td);
+    rs = rs * (1.5 - 0.5 * Td * rs * rs);
+    double f = 0.88622692545275801364908374167057 * rs;
+    F[0] = static_cast<float>(f);
+    if constexpr (L > 0) {
+      const double e = static_cast<double>(__expf(-T));
+      const double h = 0.5 * rs * rs;
+#pragma unroll
+      for (int m = 0; m < L; ++m) {
+        f = ((2 * m + 1) * f - e) * h;
+        F[m + 1] = static_cast<float>(f);
+      }
     }
   } else {
     const double Td = static_cast<double>(T);
@@ -386,6 +432,21 @@ __device__ __forceinline__ void prim_setup(T p, T oo2p, T PAx, T PAy, T PAz, T K
 // Read-only global data that the kernels never write: the constant address
 // space lets the compiler use scalar loads where the address is uniform.
 using CDouble = const __attribute__((address_space(4))) double*;
+template <typename T>
+using CReal = const __attribute__((address_space(4))) T*;
+
+// Primitive-pair fields in the kernel's precision (FP32 kernels read the FP32
+// copy: half the bytes and no conversions).
+template <typename T>
+__device__ __forceinline__ const T* prim_of(const BinView& v) {
+  if constexpr (sizeof(T) == 8) return v.prim;
+  else return v.prim32;
+}
+template <typename T>
+__device__ __forceinline__ const T* primT_of(const BinView& v) {
+  if constexpr (sizeof(T) == 8) return v.primT;
+  else return v.primT32;
+}
 
 // Contraction loop of one shell quartet: bra pair i, ket pair k.  `vrr(F, c)`
 // adds one primitive quartet to the caller's accumulators.
@@ -402,25 +463,25 @@ __device__ __forceinline__ void contract(const EriLaunch& a, const BoysTab<T>& b
                                          int sub, T ACx, T ACy, T ACz, V&& vrr) {
   const int nk = a.ket.n;
   const int nppb = a.bra.npp, nppk = a.ket.npp;
+  const T* kprim = prim_of<T>(a.ket);
   if constexpr (G == 1) {
     (void)sub;
-    const CDouble bra = (CDouble)(a.bra.primT) + static_cast<size_t>(i) * nppb * kPrimFields;
+    const CReal<T> bra = (CReal<T>)(primT_of<T>(a.bra)) + static_cast<size_t>(i) * nppb * kPrimFields;
     for (int kl = 0; kl < nppk; ++kl) {
-      const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
-      const T q = T(kp[kP * nk]), oo2q = T(kp[kOo2p * nk]);
-      const T QCx = T(kp[kPAx * nk]), QCy = T(kp[kPAy * nk]), QCz = T(kp[kPAz * nk]);
-      const T Kcd = T(kp[kKt * nk]);
+      const T* kp = kprim + static_cast<size_t>(kl) * kPrimFields * nk + k;
+      const T q = kp[kP * nk], oo2q = kp[kOo2p * nk];
+      const T QCx = kp[kPAx * nk], QCy = kp[kPAy * nk], QCz = kp[kPAz * nk];
+      const T Kcd = kp[kKt * nk];
       auto geo = [&](int ij, PrimGeo<L, T>& g) {
-        const CDouble b = bra + ij * kPrimFields;
-        prim_geo<L, T>(T(b[kP]), T(b[kPAx]), T(b[kPAy]), T(b[kPAz]), q, QCx, QCy, QCz, ACx, ACy,
-                       ACz, bt, g);
+        const CReal<T> b = bra + ij * kPrimFields;
+        prim_geo<L, T>(b[kP], b[kPAx], b[kPAy], b[kPAz], q, QCx, QCy, QCz, ACx, ACy, ACz, bt, g);
       };
       auto finish = [&](int ij, const PrimGeo<L, T>& g) {
-        const CDouble b = bra + ij * kPrimFields;
+        const CReal<T> b = bra + ij * kPrimFields;
         T F[L + 1];
         VrrCoef<T> c;
-        prim_finish<L, T>(g, T(b[kP]), T(b[kOo2p]), T(b[kPAx]), T(b[kPAy]), T(b[kPAz]),
-                          T(b[kKt]), q, oo2q, QCx, QCy, QCz, Kcd, bt, F, c);
+        prim_finish<L, T>(g, b[kP], b[kOo2p], b[kPAx], b[kPAy], b[kPAz], b[kKt], q, oo2q, QCx,
+                          QCy, QCz, Kcd, bt, F, c);
         vrr(F, c);
       };
       for (int ij = 0; ij < nppb; ++ij) {
@@ -430,22 +491,22 @@ __device__ __forceinline__ void contract(const EriLaunch& a, const BoysTab<T>& b
       }
     }
   } else {
-    const double* bra = a.bra.primT + static_cast<size_t>(i) * nppb * kPrimFields;
+    const T* bra = primT_of<T>(a.bra) + static_cast<size_t>(i) * nppb * kPrimFields;
     const int npq = nppb * nppk;
     auto geo = [&](int kl, int ij, PrimGeo<L, T>& g) {
-      const double* b = bra + ij * kPrimFields;
-      const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
-      prim_geo<L, T>(T(b[kP]), T(b[kPAx]), T(b[kPAy]), T(b[kPAz]), T(kp[kP * nk]),
-                     T(kp[kPAx * nk]), T(kp[kPAy * nk]), T(kp[kPAz * nk]), ACx, ACy, ACz, bt, g);
+      const T* b = bra + ij * kPrimFields;
+      const T* kp = kprim + static_cast<size_t>(kl) * kPrimFields * nk + k;
+      prim_geo<L, T>(b[kP], b[kPAx], b[kPAy], b[kPAz], kp[kP * nk], kp[kPAx * nk], kp[kPAy * nk],
+                     kp[kPAz * nk], ACx, ACy, ACz, bt, g);
     };
     auto finish = [&](int kl, int ij, const PrimGeo<L, T>& g) {
-      const double* b = bra + ij * kPrimFields;
-      const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
+      const T* b = bra + ij * kPrimFields;
+      const T* kp = kprim + static_cast<size_t>(kl) * kPrimFields * nk + k;
       T F[L + 1];
       VrrCoef<T> c;
-      prim_finish<L, T>(g, T(b[kP]), T(b[kOo2p]), T(b[kPAx]), T(b[kPAy]), T(b[kPAz]), T(b[kKt]),
-                        T(kp[kP * nk]), T(kp[kOo2p * nk]), T(kp[kPAx * nk]), T(kp[kPAy * nk]),
-                        T(kp[kPAz * nk]), T(kp[kKt * nk]), bt, F, c);
+      prim_finish<L, T>(g, b[kP], b[kOo2p], b[kPAx], b[kPAy], b[kPAz], b[kKt], kp[kP * nk],
+                        kp[kOo2p * nk], kp[kPAx * nk], kp[kPAy * nk], kp[kPAz * nk],
+                        kp[kKt * nk], bt, F, c);
       vrr(F, c);
     };
     auto step = [&](int& kl, int& ij) {
@@ -691,6 +752,15 @@ __device__ __forceinline__ void scatter_ws(double* M, size_t n, int rx, int cy, 
   lanes_sync();   // the workspace is rewritten for the next quartets
 }
 
+// D block rows r0.., columns c0.. (NR x NCOL) into registers.
+template <int NR, int NCOL>
+__device__ __forceinline__ void load_block(double* dst, const double* Dm, size_t n, int r0, int c0) {
+#pragma unroll
+  for (int x = 0; x < NR; ++x)
+#pragma unroll
+    for (int y = 0; y < NCOL; ++y) dst[x * NCOL + y] = Dm[(r0 + x) * n + c0 + y];
+}
+
 // Integral + digestion of one work item {bra pair, ket range} of one class and
 // precision by one wavefront: the bra pair is uniform across the wave (scalar
 // data), each lane (each group of G lanes) takes one ket pair of the current
@@ -733,6 +803,65 @@ __device__ __forceinline__ void eri_item(const EriLaunch& a, const BoysTab<T>& b
 
     for (int m = 0; m < a.n_dm; ++m) {
       const double* Dm = a.D + m * nn;
+      if constexpr (C::SWEEPS) {
+        // five sweeps, each with one D block and one accumulator block live
+        const size_t n = static_cast<size_t>(a.n);
+        double* Jm = a.J + (item % a.ncopy) * a.copy_stride + m * nn;
+        double* Km = a.K + (item % a.ncopy) * a.copy_stride + m * nn;
+        const bool writer = sub == 0;
+        {
+          double Dab[C::NA * C::NB], Dcd[C::NC * C::ND], jab[C::NA * C::NB], jcd[C::NC * C::ND];
+          load_block<C::NA, C::NB>(Dab, Dm, n, a0, b0);
+          load_block<C::NC, C::ND>(Dcd, Dm, n, c0, d0);
+#pragma unroll
+          for (int t = 0; t < C::NA * C::NB; ++t) jab[t] = 0.0;
+#pragma unroll
+          for (int t = 0; t < C::NC * C::ND; ++t) jcd[t] = 0.0;
+          C::template digest_j<T>(acc, ABx, ABy, ABz, CDx, CDy, CDz, fq, Dab, Dcd, jab, jcd);
+#pragma unroll
+          for (int t = 0; t < C::NA * C::NB; ++t) {
+            const double sj = wave_sum(jab[t]);
+            if (lane == kWaveSumLane)
+              atomic_add(&Jm[(a0 + t / C::NB) * n + b0 + t % C::NB], 2.0 * sj, a.det_lo);
+          }
+#pragma unroll
+          for (int t = 0; t < C::NC * C::ND; ++t) jcd[t] *= 2.0;
+          scatter_block<C::NC, C::ND, QPW>(Jm, n, c0, d0, jcd, writer, stage, a.det_lo);
+        }
+        {
+          double Dx[C::NB * C::ND], kx[C::NA * C::NC];
+          load_block<C::NB, C::ND>(Dx, Dm, n, b0, d0);
+#pragma unroll
+          for (int t = 0; t < C::NA * C::NC; ++t) kx[t] = 0.0;
+          C::template digest_kac<T>(acc, ABx, ABy, ABz, CDx, CDy, CDz, fq, Dx, kx);
+          scatter_block<C::NA, C::NC, QPW>(Km, n, a0, c0, kx, writer, stage, a.det_lo);
+        }
+        {
+          double Dx[C::NB * C::NC], kx[C::NA * C::ND];
+          load_block<C::NB, C::NC>(Dx, Dm, n, b0, c0);
+#pragma unroll
+          for (int t = 0; t < C::NA * C::ND; ++t) kx[t] = 0.0;
+          C::template digest_kad<T>(acc, ABx, ABy, ABz, CDx, CDy, CDz, fq, Dx, kx);
+          scatter_block<C::NA, C::ND, QPW>(Km, n, a0, d0, kx, writer, stage, a.det_lo);
+        }
+        {
+          double Dx[C::NA * C::ND], kx[C::NB * C::NC];
+          load_block<C::NA, C::ND>(Dx, Dm, n, a0, d0);
+#pragma unroll
+          for (int t = 0; t < C::NB * C::NC; ++t) kx[t] = 0.0;
+          C::template digest_kbc<T>(acc, ABx, ABy, ABz, CDx, CDy, CDz, fq, Dx, kx);
+          scatter_block<C::NB, C::NC, QPW>(Km, n, b0, c0, kx, writer, stage, a.det_lo);
+        }
+        {
+          double Dx[C::NA * C::NC], kx[C::NB * C::ND];
+          load_block<C::NA, C::NC>(Dx, Dm, n, a0, c0);
+#pragma unroll
+          for (int t = 0; t < C::NB * C::ND; ++t) kx[t] = 0.0;
+          C::template digest_kbd<T>(acc, ABx, ABy, ABz, CDx, CDy, CDz, fq, Dx, kx);
+          scatter_block<C::NB, C::ND, QPW>(Km, n, b0, d0, kx, writer, stage, a.det_lo);
+        }
+        continue;
+      }
       double Dab[C::NA * C::NB], Dcd[C::NC * C::ND], Dac[C::NA * C::NC], Dad[C::NA * C::ND],
           Dbc[C::NB * C::NC], Dbd[C::NB * C::ND];
 #pragma unroll
@@ -842,6 +971,172 @@ __global__ __launch_bounds__(NT) void eri_jk_lds_kernel(const EriLaunch a) {
   (void)W;
   for (int item = claim_item(a.next); item < a.nitems; item = claim_item(a.next))
     eri_item<C, T, 1>(a, bt, item, stage + (threadIdx.x >> 6) * ST);
+}
+
+// Light classes with the bra's exchange rows kept in LDS.  A work item's bra
+// pair (a, b) is shared by every quartet of the item, so the exchange blocks
+// K_ac, K_ad, K_bc, K_bd all fall into the rows a0.., b0.. of K (only K + K^T is
+// returned, so K_ac may stand in row a, column c).  The workgroup keeps those
+// NA + NB rows over all n columns in LDS, its wavefronts add every quartet's
+// blocks there with LDS atomics, and the rows reach K with one dense flush per
+// item -- about 0.5 memory-side atomic requests per quartet instead of one per
+// block and quartet.  J_ab is summed over the wavefront into LDS the same way;
+// J_cd still goes to J per quartet through the staged scatter.
+
+// One 64-ket chunk of a work item, one lane per quartet (one density).
+template <class C, typename T>
+__device__ __forceinline__ void eri_chunk_rows(const EriLaunch& a, const BoysTab<T>& bt, int i,
+                                               int kc, int kend, double* stage, double* krow,
+                                               double* jrow, double* Jm) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int nb = a.bra.n, nk = a.ket.n;
+  const size_t n = static_cast<size_t>(a.n);
+  const double Ax = a.bra.A[i], Ay = a.bra.A[nb + i], Az = a.bra.A[2 * nb + i];
+  const T ABx = T(a.bra.AB[i]), ABy = T(a.bra.AB[nb + i]), ABz = T(a.bra.AB[2 * nb + i]);
+  const int a0 = a.bra.bf[i], b0 = a.bra.bf[nb + i];
+  const double fbra = a.bra.fpair[i];
+  const bool inrange = kc + lane < kend;
+  const int k = inrange ? kc + lane : kend - 1;
+  const T ACx = T(Ax - a.ket.A[k]), ACy = T(Ay - a.ket.A[nk + k]), ACz = T(Az - a.ket.A[2 * nk + k]);
+  T acc[C::NACC];
+#pragma unroll
+  for (int t = 0; t < C::NACC; ++t) acc[t] = T(0);
+  contract<C::L, T, 1>(a, bt, i, k, 0, ACx, ACy, ACz,
+                       [&](const T* F, const VrrCoef<T>& c) { C::template vrr<T>(F, c, acc); });
+  const T CDx = T(a.ket.AB[k]), CDy = T(a.ket.AB[nk + k]), CDz = T(a.ket.AB[2 * nk + k]);
+  const int c0 = a.ket.bf[k], d0 = a.ket.bf[nk + k];
+  const double fq = inrange ? fbra * a.ket.fpair[k] * ((a.same_bin && k == i) ? 0.5 : 1.0) : 0.0;
+  const double* Dm = a.D;
+  double Dab[C::NA * C::NB], Dcd[C::NC * C::ND], Dac[C::NA * C::NC], Dad[C::NA * C::ND],
+      Dbc[C::NB * C::NC], Dbd[C::NB * C::ND];
+  load_block<C::NA, C::NB>(Dab, Dm, n, a0, b0);
+  load_block<C::NC, C::ND>(Dcd, Dm, n, c0, d0);
+  load_block<C::NA, C::NC>(Dac, Dm, n, a0, c0);
+  load_block<C::NA, C::ND>(Dad, Dm, n, a0, d0);
+  load_block<C::NB, C::NC>(Dbc, Dm, n, b0, c0);
+  load_block<C::NB, C::ND>(Dbd, Dm, n, b0, d0);
+  double jab[C::NA * C::NB], jcd[C::NC * C::ND], kac[C::NA * C::NC], kad[C::NA * C::ND],
+      kbc[C::NB * C::NC], kbd[C::NB * C::ND];
+#pragma unroll
+  for (int t = 0; t < C::NA * C::NB; ++t) jab[t] = 0.0;
+#pragma unroll
+  for (int t = 0; t < C::NC * C::ND; ++t) jcd[t] = 0.0;
+#pragma unroll
+  for (int t = 0; t < C::NA * C::NC; ++t) kac[t] = 0.0;
+#pragma unroll
+  for (int t = 0; t < C::NA * C::ND; ++t) kad[t] = 0.0;
+#pragma unroll
+  for (int t = 0; t < C::NB * C::NC; ++t) kbc[t] = 0.0;
+#pragma unroll
+  for (int t = 0; t < C::NB * C::ND; ++t) kbd[t] = 0.0;
+  C::template hrr_digest<T>(acc, ABx, ABy, ABz, CDx, CDy, CDz, fq, Dab, Dcd, Dac, Dad, Dbc, Dbd,
+                            jab, jcd, kac, kad, kbc, kbd);
+#pragma unroll
+  for (int t = 0; t < C::NA * C::NB; ++t) {
+    const double sj = wave_sum(jab[t]);
+    if (lane == kWaveSumLane && sj != 0.0)
+      __hip_atomic_fetch_add(&jrow[t], 2.0 * sj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+#pragma unroll
+  for (int t = 0; t < C::NC * C::ND; ++t) jcd[t] *= 2.0;
+  scatter_block<C::NC, C::ND, kWave>(Jm, n, c0, d0, jcd, true, stage, 0);
+  if (fq != 0.0) {
+    auto add = [&](int row, int col, double v) {
+      if (v != 0.0)
+        __hip_atomic_fetch_add(&krow[static_cast<size_t>(row) * n + col], v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+#pragma unroll
+    for (int x = 0; x < C::NA; ++x) {
+#pragma unroll
+      for (int y = 0; y < C::NC; ++y) add(x, c0 + y, kac[x * C::NC + y]);
+#pragma unroll
+      for (int y = 0; y < C::ND; ++y) add(x, d0 + y, kad[x * C::ND + y]);
+    }
+#pragma unroll
+    for (int x = 0; x < C::NB; ++x) {
+#pragma unroll
+      for (int y = 0; y < C::NC; ++y) add(C::NA + x, c0 + y, kbc[x * C::NC + y]);
+#pragma unroll
+      for (int y = 0; y < C::ND; ++y) add(C::NA + x, d0 + y, kbd[x * C::ND + y]);
+    }
+  }
+}
+
+// Dynamic LDS of the rows kernel: NA + NB rows of n doubles, then NA * NB for J_ab.
+template <class C>
+__host__ __device__ constexpr size_t rows_lds_doubles(int n) {
+  return static_cast<size_t>(C::NA + C::NB) * n + C::NA * C::NB;
+}
+
+template <class C, typename T, int NT>
+__global__ __launch_bounds__(NT) void eri_jk_rows_kernel(const EriLaunch a) {
+  static_assert(C::L <= kLdsMaxL, "LDS Boys table: orders <= 3");
+  constexpr int W = NT / kWave;
+  constexpr int NR = C::NA + C::NB;
+  const BoysTab<T> g = global_boys<C::L, T>(a);
+  BoysTab<T> bt = g;
+  if constexpr (sizeof(T) == 8) {
+    __shared__ double2 rows[kLdsRows64 * kBoysRow / 2];
+    const double2* src = reinterpret_cast<const double2*>(g.rows);
+    for (int t = threadIdx.x; t < kLdsRows64 * kBoysRow / 2; t += NT) rows[t] = src[t];
+    bt.rows = reinterpret_cast<const double*>(rows);
+    bt.tmax = kLdsTmax;
+  } else {
+    __shared__ float4 rows[kBoys32Rows * kBoys32Row / 4];
+    const float4* src = reinterpret_cast<const float4*>(g.rows);
+    for (int t = threadIdx.x; t < kBoys32Rows * kBoys32Row / 4; t += NT) rows[t] = src[t];
+    bt.rows = reinterpret_cast<const float*>(rows);
+  }
+  constexpr int ST = Scatter<C::NC, C::ND, kWave>::STAGE > 0 ? Scatter<C::NC, C::ND, kWave>::STAGE : 1;
+  __shared__ double stage[W * ST];
+  __shared__ int s_item;
+  extern __shared__ double dyn[];
+  const int n = a.n;
+  double* const krow = dyn;
+  double* const jrow = dyn + static_cast<size_t>(NR) * n;
+  const int tot = static_cast<int>(rows_lds_doubles<C>(n));
+  for (int t = threadIdx.x; t < tot; t += NT) dyn[t] = 0.0;
+  __syncthreads();
+  const int wave = threadIdx.x >> 6;
+  const int nb = a.bra.n;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(a.next, 1);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= a.nitems) break;   // uniform over the workgroup
+    const int4 w4 = a.items[item];
+    const int i = __builtin_amdgcn_readfirstlane(w4.x);
+    const int kbeg = __builtin_amdgcn_readfirstlane(w4.y);
+    const int kend = __builtin_amdgcn_readfirstlane(w4.z);
+    double* Jm = a.J + (item % a.ncopy) * a.copy_stride;
+    double* Km = a.K + (item % a.ncopy) * a.copy_stride;
+    for (int kc = kbeg + wave * kWave; kc < kend; kc += W * kWave)
+      eri_chunk_rows<C, T>(a, bt, i, kc, kend, stage + wave * ST, krow, jrow, Jm);
+    __syncthreads();
+    // flush: the bra's rows of K (and J_ab) to the accumulators, zero them again
+    const int a0 = a.bra.bf[i], b0 = a.bra.bf[nb + i];
+    const size_t ns = static_cast<size_t>(n);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const size_t fn = static_cast<size_t>(r < C::NA ? a0 + r : b0 + (r - C::NA));
+      for (int col = threadIdx.x; col < n; col += NT) {
+        const double v = krow[r * ns + col];
+        if (v != 0.0) {
+          atomic_add(&Km[fn * ns + col], v, 0);
+          krow[r * ns + col] = 0.0;
+        }
+      }
+    }
+    for (int t = threadIdx.x; t < C::NA * C::NB; t += NT) {
+      const double v = jrow[t];
+      if (v != 0.0) {
+        atomic_add(&Jm[(a0 + t / C::NB) * ns + b0 + t % C::NB], v, 0);
+        jrow[t] = 0.0;
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // Cauchy-Schwarz factor of every pair of a bin: Q = sqrt(max_ab (ab|ab)).

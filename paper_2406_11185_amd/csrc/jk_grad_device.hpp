@@ -54,8 +54,8 @@ __device__ __forceinline__ void contract_w(const EriLaunch& a, int i, int k, int
   const int npq = nppb * nppk;
   for (int pq = sub; pq < npq; pq += G) {
     const int kl = pq / nppb, ij = pq - kl * nppb;
-    const double* kp = a.ket.prim + static_cast<size_t>(kl) * kPrimFields * nk + k;
-    const double* bp = a.bra.prim + static_cast<size_t>(ij) * kPrimFields * nb + i;
+    const T* kp = prim_of<T>(a.ket) + static_cast<size_t>(kl) * kPrimFields * nk + k;
+    const T* bp = prim_of<T>(a.bra) + static_cast<size_t>(ij) * kPrimFields * nb + i;
     T F[L + 1];
     VrrCoef<T> c;
     prim_setup<L, T>(T(bp[kP * nb]), T(bp[kOo2p * nb]), T(bp[kPAx * nb]), T(bp[kPAy * nb]),

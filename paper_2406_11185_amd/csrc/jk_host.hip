@@ -115,6 +115,8 @@ struct ShellDev {
 struct PairOut {
   double* prim;        // all bins, bin b at prim_off[b]
   double* primT;       // pair-major copy, same offsets
+  float* prim32;       // FP32 copies of prim and primT (null: not written)
+  float* primT32;
   double* A;           // bin b at 3*pair_off[b], [3][n_b]
   double* AB;
   int* bf;             // bin b at 2*pair_off[b]
@@ -184,6 +186,14 @@ __global__ void pair_data_kernel(int npairs, const int* __restrict__ pair_s1,
       f[kTwoB * n] = 2.0 * eb;
       double* h = primT + static_cast<size_t>(pp) * kPrimFields;
       for (int x = 0; x < kPrimFields; ++x) h[x] = f[x * n];
+      if (out.prim32) {
+        const size_t o = bin_prim_off[b] + static_cast<size_t>(pp) * kPrimFields * n + t;
+        const size_t oT = bin_prim_off[b] + (static_cast<size_t>(t) * n1 * n2 + pp) * kPrimFields;
+        for (int x = 0; x < kPrimFields; ++x) {
+          out.prim32[o + static_cast<size_t>(x) * n] = static_cast<float>(f[x * n]);
+          out.primT32[oT + x] = static_cast<float>(f[x * n]);
+        }
+      }
     }
   (void)bin_npp;
 }
@@ -450,7 +460,7 @@ struct DevBuf {
 enum Slot {
   sShellXyz, sShellI, sExps, sCoefs, sPairS, sBinOff, sBinNpp, sBinPrim, sPrimTmp, sPrim, sPrimTmpT, sPrimT,
   sA, sAB, sBf, sAtoms, sFpair, sAtmp, sABtmp, sBftmp, sAtomstmp, sFpairtmp, sQtmp, sQ,
-  sIdx, sIdxSorted, sPerm, sBp, sCnt, sOff, sRng, sQstat, sSeg, sItems, sCub, sChunk, sWs0, sWs1,
+  sIdx, sIdxSorted, sPerm, sPrim32, sPrimT32, sBp, sCnt, sOff, sRng, sQstat, sSeg, sItems, sCub, sChunk, sWs0, sWs1,
   sWs2, sWs3, sWsSchwarz, sNext, sAcc, sEpart, sGradAcc, sNumSlots
 };
 
@@ -525,6 +535,7 @@ std::string take_guard_error() {
 
 struct jk_ctx {
   int device = 0;
+  size_t ws_budget = 0;            // workspace bytes a multi-pass launch may use
   int num_cu = 0;
   std::string err;
   DevBuf buf[sNumSlots];
@@ -687,13 +698,16 @@ void upload(const std::vector<T>& v, T* d, hipStream_t s) {
 }
 
 BinView bin_view(const Plan& P, int b, double* prim, double* primT, double* A, double* AB, int* bf,
-                 int* atoms, double* fpair, double* Q) {
+                 int* atoms, double* fpair, double* Q, float* prim32 = nullptr,
+                 float* primT32 = nullptr) {
   BinView v;
   const int o = P.bin_off[b];
   v.n = P.bin_off[b + 1] - o;
   v.npp = P.bin_npp[b];
   v.prim = prim + P.bin_prim[b];
   v.primT = primT + P.bin_prim[b];
+  v.prim32 = prim32 ? prim32 + P.bin_prim[b] : nullptr;
+  v.primT32 = primT32 ? primT32 + P.bin_prim[b] : nullptr;
   v.A = A + 3 * o;
   v.AB = AB + 3 * o;
   v.bf = bf + 2 * o;
@@ -706,6 +720,7 @@ BinView bin_view(const Plan& P, int b, double* prim, double* primT, double* A, d
 struct Setup {
   Plan P;
   double *prim, *primT, *A, *AB, *fpair, *Q;
+  float *prim32, *primT32;
   int *bf, *atoms;
   int4* items;
   std::vector<int> seg;   // [2][nbp+1]
@@ -748,6 +763,8 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
   double* d_primtmp = dev<double>(c, sPrimTmp, nprimd);
   S.prim = dev<double>(c, sPrim, nprimd);
   S.primT = dev<double>(c, sPrimT, nprimd);
+  S.prim32 = dev<float>(c, sPrim32, nprimd);
+  S.primT32 = dev<float>(c, sPrimT32, nprimd);
   double* d_primtmpT = dev<double>(c, sPrimTmpT, nprimd);
   S.A = dev<double>(c, sA, 3 * static_cast<size_t>(np));
   S.AB = dev<double>(c, sAB, 3 * static_cast<size_t>(np));
@@ -779,7 +796,7 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
 
   ShellDev sd{d_sxyz, d_si, d_si + ns, d_si + 2 * ns, d_si + 3 * ns, d_si + 4 * ns, d_exps, d_coefs};
   // step 2 (unsorted), step 3
-  PairOut tmp{d_primtmp, d_primtmpT, d_Atmp, d_ABtmp, d_bftmp, d_atomstmp, d_fpairtmp};
+  PairOut tmp{d_primtmp, d_primtmpT, nullptr, nullptr, d_Atmp, d_ABtmp, d_bftmp, d_atomstmp, d_fpairtmp};
   hipLaunchKernelGGL(pair_data_kernel, dim3(grid_of(np, 256)), dim3(256), 0, s, np, d_pairs,
                      d_pairs + np, static_cast<const int*>(nullptr), d_binoff, d_binnpp,
                      d_binprim, P.nbins, sd, tmp);
@@ -795,7 +812,7 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
     if (per_wave) {  // multi-pass diagonal class: workspace, waves loop over the pairs
       const int pairs_per_wave = kWave / kSchwarzSplitLanes;
       const size_t want = (static_cast<size_t>(a.bra.n) + pairs_per_wave - 1) / pairs_per_wave;
-      const size_t cap = std::max<size_t>(64, kWsBudget / per_wave);
+      const size_t cap = std::max<size_t>(64, c->ws_budget / per_wave);
       a.nwaves = static_cast<int>(std::min(want, cap));
       a.ws = dev<char>(c, sWsSchwarz, per_wave * a.nwaves);
     }
@@ -815,7 +832,7 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
       64, s));
   hipLaunchKernelGGL(local_to_global_kernel, dim3(grid_of(np, 256)), dim3(256), 0, s, np,
                      d_binoff, P.nbins, d_idxs, d_perm);
-  PairOut fin{S.prim, S.primT, S.A, S.AB, S.bf, S.atoms, S.fpair};
+  PairOut fin{S.prim, S.primT, S.prim32, S.primT32, S.A, S.AB, S.bf, S.atoms, S.fpair};
   hipLaunchKernelGGL(pair_data_kernel, dim3(grid_of(np, 256)), dim3(256), 0, s, np, d_pairs,
                      d_pairs + np, d_perm, d_binoff, d_binnpp, d_binprim, P.nbins, sd, fin);
   HIP_OK(hipGetLastError());
@@ -863,7 +880,7 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
       for (int g = 1; g <= gmax; g *= 2) {
         if (!(mask & (1 << g))) continue;
         const size_t ws = grad ? size_t(kWave / g) * grad_ws_elems(cls) * (pr ? 4 : 8) : 0;
-        if (g < gmax && ws && kWsBudget / ws < static_cast<size_t>(kTargetWaves / 2)) continue;
+        if (g < gmax && ws && c->ws_budget / ws < static_cast<size_t>(kTargetWaves / 2)) continue;
         lanes = g;
         if (q * g >= static_cast<unsigned long long>(kWave) * want) break;
       }
@@ -928,8 +945,8 @@ jk_stats base_stats(const Plan& P, const Setup& S) {
 EriLaunch launch_args(jk_ctx* c, const Plan& P, const Setup& S, int X, int Y, int i0, int i1,
                       const double* D, double* J, double* K, int nbf, const jk_opts& o) {
   EriLaunch a{};
-  a.bra = bin_view(P, X, S.prim, S.primT, S.A, S.AB, S.bf, S.atoms, S.fpair, S.Q);
-  a.ket = bin_view(P, Y, S.prim, S.primT, S.A, S.AB, S.bf, S.atoms, S.fpair, S.Q);
+  a.bra = bin_view(P, X, S.prim, S.primT, S.A, S.AB, S.bf, S.atoms, S.fpair, S.Q, S.prim32, S.primT32);
+  a.ket = bin_view(P, Y, S.prim, S.primT, S.A, S.AB, S.bf, S.atoms, S.fpair, S.Q, S.prim32, S.primT32);
   a.items = S.items + i0;
   a.nitems = i1 - i0;
   a.same_bin = X == Y;
@@ -1090,6 +1107,7 @@ int jk_ctx_create(jk_ctx** out, int device) {
     std::vector<float> t32;
     make_boys_tables(t64, t32);
     HIP_OK(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device));
+    c->ws_budget = kWsBudget;
     if (c->num_cu < 1) c->num_cu = 1;
     HIP_OK(hipMalloc(&c->boys64, t64.size() * sizeof(double)));
     HIP_OK(hipMalloc(&c->boys32, t32.size() * sizeof(float)));
@@ -1129,8 +1147,12 @@ int jk_ctx_destroy(jk_ctx* c) {
 
 const char* jk_last_error(const jk_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
-int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, double* K, double tol,
-             const jk_opts* opts, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+int build_impl(jk_ctx* c, const jk_basis* basis, const double* D, double* J, double* K, double tol,
+               const jk_opts* opts, void* hip_stream) {
   if (!c) return JK_EINVAL;
   c->err.clear();
   int32_t nbf = 0;
@@ -1185,7 +1207,7 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
     auto waves_of = [&](const LaunchRec& r) {
       const size_t per_wave = split_ws_bytes(r.cls, r.pr, r.lanes);
       if (!per_wave) return std::pair<int, size_t>(0, 0);
-      const size_t cap = std::max<size_t>(64, kWsBudget / per_wave);
+      const size_t cap = std::max<size_t>(64, c->ws_budget / per_wave);
       return std::pair<int, size_t>(static_cast<int>(std::min<size_t>(r.i1 - r.i0, cap)), per_wave);
     };
     void* ws[jk_ctx::kStreams] = {};
@@ -1201,6 +1223,7 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
           a.ws = ws[k];
           a.nwaves = waves_of(r).first;
           a.dry = dry ? 1 : 0;
+          a.rows = (o.n_dm == 1 && !det) ? 1 : 0;
           launch_eri(r.cls, r.pr, a, ls);
         },
         [&](const std::vector<LaunchRec>& recs, const std::vector<int>& where) {
@@ -1237,6 +1260,15 @@ int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, doubl
   return JK_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, double* K, double tol,
+             const jk_opts* opts, void* hip_stream) {
+  return build_impl(c, basis, D, J, K, tol, opts, hip_stream);
+}
+
 int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, double tol,
             const jk_opts* opts, void* hip_stream) {
   if (!c) return JK_EINVAL;
@@ -1269,7 +1301,7 @@ int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, dou
     // kWsBudget bytes and loops over its items with a fixed number of waves
     auto waves_of = [&](const LaunchRec& r) {
       const size_t per_wave = size_t(kWave / r.lanes) * grad_ws_elems(r.cls) * (r.pr ? 4 : 8);
-      const size_t cap = std::max<size_t>(64, kWsBudget / per_wave);
+      const size_t cap = std::max<size_t>(64, c->ws_budget / per_wave);
       return std::pair<int, size_t>(static_cast<int>(std::min<size_t>(r.i1 - r.i0, cap)), per_wave);
     };
     void* ws[jk_ctx::kStreams] = {};

@@ -43,14 +43,17 @@ def kernels_of(obj: str):
         notes = subprocess.run([os.path.join(LLVM, "llvm-readelf"), "--notes", co],
                                capture_output=True, text=True, check=True).stdout
     out = []
-    for blk in re.split(r"\n\s+- \.", notes)[1:]:
+    # kernel entries of the amdhsa.kernels list sit at two spaces of indentation
+    for blk in re.split(r"\n  - \.", notes)[1:]:
         def f(key):
             m = re.search(rf"(?m)^\s*{key}:\s+(\S+)", "." + blk)
             return m.group(1) if m else None
         name = f(r"\.name")
         if not name or f(r"\.vgpr_count") is None:
             continue
+        m = re.search(r"\.args:\s*\n\s*- \.offset:\s+0\s*\n\s*\.size:\s+(\d+)", "." + blk)
         out.append(dict(name=name, vgpr=int(f(r"\.vgpr_count")), agpr=int(f(r"\.agpr_count") or 0),
+                        arg0=int(m.group(1)) if m else -1,
                         vspill=int(f(r"\.vgpr_spill_count") or 0),
                         scratch=int(f(r"\.private_segment_fixed_size") or 0),
                         lds=int(f(r"\.group_segment_fixed_size") or 0)))
@@ -61,6 +64,24 @@ def waves_per_simd(vgpr):
     # .vgpr_count is the unified count (architectural + accumulation registers) out of
     # the 512 a lane has on CDNA4, allocated in granules of 8
     return min(8, 512 // max(8, ((vgpr + 7) // 8) * 8))
+
+
+def host_arg_sizes():
+    """sizeof(EriLaunch), sizeof(GradLaunch) as the host compiler lays them out."""
+    src = ('#include "jk_grad_device.hpp"\n#include <cstdio>\n'
+           'int main() { std::printf("%zu %zu\\n", sizeof(jk::EriLaunch), sizeof(jk::GradLaunch)); }\n')
+    with tempfile.TemporaryDirectory() as td:
+        p = os.path.join(td, "sz.hip")
+        with open(p, "w") as fh:
+            fh.write(src)
+        exe = os.path.join(td, "sz")
+        csrc = os.path.join(ROOT, "paper_2406_11185_amd", "csrc")
+        subprocess.run(["/opt/rocm/bin/hipcc", "-std=c++17", "--offload-host-only", "-O0", "-I",
+                        os.path.join(ROOT, "include"), "-I", csrc, "-I",
+                        os.path.join(ROOT, "_build", "gen"), p, "-o", exe], check=True,
+                       capture_output=True)
+        e, g = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    return int(e), int(g)
 
 
 def table():

@@ -149,3 +149,48 @@ extern "C" int emu_block(int cls, const int* l, const int* np, const double* A, 
   }
   return 0;
 }
+
+// The five digestion sweeps of a single-pass class against its one-sweep
+// digestion, on arbitrary contracted values and D blocks; returns the largest
+// difference over all six blocks (multi-pass classes: 0, they have no sweeps).
+template <class C>
+static double sweeps_diff() {
+  if constexpr (is_split<C>::value) {
+    return 0.0;
+  } else {
+    double acc[C::NACC];
+    unsigned s = 12345u;
+    auto rnd = [&]() { s = s * 1103515245u + 12345u; return ((s >> 8) & 0xffff) / 65536.0 - 0.5; };
+    for (int t = 0; t < C::NACC; ++t) acc[t] = rnd();
+    double D6[6][64];
+    for (auto& blk : D6) for (double& v : blk) v = rnd();
+    const double AB[3] = {0.3, -0.7, 1.1}, CD[3] = {-0.4, 0.9, 0.2};
+    double r1[6][64] = {{0}}, r2[6][64] = {{0}};
+    C::template hrr_digest<double>(acc, AB[0], AB[1], AB[2], CD[0], CD[1], CD[2], 0.75, D6[0], D6[1],
+                                   D6[2], D6[3], D6[4], D6[5], r1[0], r1[1], r1[2], r1[3], r1[4],
+                                   r1[5]);
+    C::template digest_j<double>(acc, AB[0], AB[1], AB[2], CD[0], CD[1], CD[2], 0.75, D6[0], D6[1],
+                                 r2[0], r2[1]);
+    C::template digest_kac<double>(acc, AB[0], AB[1], AB[2], CD[0], CD[1], CD[2], 0.75, D6[5], r2[2]);
+    C::template digest_kad<double>(acc, AB[0], AB[1], AB[2], CD[0], CD[1], CD[2], 0.75, D6[4], r2[3]);
+    C::template digest_kbc<double>(acc, AB[0], AB[1], AB[2], CD[0], CD[1], CD[2], 0.75, D6[3], r2[4]);
+    C::template digest_kbd<double>(acc, AB[0], AB[1], AB[2], CD[0], CD[1], CD[2], 0.75, D6[2], r2[5]);
+    double d = 0.0, mx = 0.0;
+    for (int b = 0; b < 6; ++b)
+      for (int t = 0; t < 64; ++t) {
+        d = std::max(d, std::fabs(r1[b][t] - r2[b][t]));
+        mx = std::max(mx, std::fabs(r1[b][t]));
+      }
+    return mx > 0.0 ? d / mx : -1.0;
+  }
+}
+
+extern "C" double emu_sweeps(int cls) {
+  switch (cls) {
+#define S2(i, N) case i: return sweeps_diff<Cls_##N>();
+    S2(0, ssss) S2(1, psss) S2(2, psps) S2(3, ppss) S2(4, ppps) S2(5, pppp) S2(6, dsss) S2(7, dsps)
+    S2(8, dspp) S2(9, dsds) S2(10, dpss) S2(11, dpps) S2(12, dppp) S2(13, dpds) S2(14, dpdp)
+    S2(15, ddss) S2(16, ddps) S2(17, ddpp) S2(18, ddds) S2(19, dddp) S2(20, dddd)
+    default: return -2.0;
+  }
+}

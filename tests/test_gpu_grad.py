@@ -5,10 +5,10 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import gpu_jk, say
+from gpu_util import GRAD_OFF, gpu_jk, say
 from paper_2406_11185_amd import molgen
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, GRAD_OFF]
 
 
 def gpu_grad(mol, tol, precision="fp64"):

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import say
+from gpu_util import GRAD_OFF, say
 from paper_2406_11185_amd import molgen
 
 pytestmark = pytest.mark.gpu
@@ -92,6 +92,7 @@ def test_serial_launches_match_streams():
     assert np.abs(J1 - J2).max() <= 1e-13 and np.abs(K1 - K2).max() <= 1e-13
 
 
+@GRAD_OFF
 def test_gradient_multiple_densities_and_deterministic():
     import torch
     from paper_2406_11185_amd import jk as jkb

@@ -431,5 +431,6 @@ def test_gradient_rows_of_selected_atoms():
     mol = molgen.make_molecule(2, 2, seed=11)
     G = oracle.grad(mol, 1e-8)
     Gs = oracle.grad(mol, 1e-8, atoms=[1, 3])
-    np.testing.assert_allclose(Gs[:, [1, 3]], G[:, [1, 3]], rtol=1e-12, atol=1e-14)
+    # same terms summed in another order (OpenMP partial sums): rounding only
+    np.testing.assert_allclose(Gs[:, [1, 3]], G[:, [1, 3]], rtol=0, atol=1e-12)
     assert np.all(Gs[:, [0, 2]] == 0.0)
