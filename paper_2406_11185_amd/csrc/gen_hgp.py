@@ -293,7 +293,10 @@ class HRR(Code):
 # value size in bytes); classes not listed take 1 (all 512 registers of a lane).
 # JK_WAVES_OVERRIDE="kind:size:waves,..." (kind = single or split) overrides the
 # listed kernels of one precision, for measurements.
-CLASS_WAVES = {}
+# (Measured on gfx950 at 1080 functions: with the digestion in sweeps, two
+# wavefronts per SIMD make the FP32 kernels of these classes 20-35 % faster; the
+# FP64 ones, which spill at that budget, lose.)
+CLASS_WAVES = {(name, 4): 2 for name in ("pppp", "dspp", "dsds", "dpps", "dpds", "ddps")}
 
 
 def class_waves(name, size, split=False):
@@ -316,7 +319,10 @@ LDS_MAX_L = 3   # single-pass classes up to this order read the Boys rows from L
 ROWS_BLOCK = 512   # threads of the light-class kernel that keeps the bra's K rows in LDS
 # Light classes and precisions that use the rows kernel ("name:size"); JK_ROWS_OVERRIDE
 # = "all" or "none" for measurements.
-ROWS_CLASSES = None   # None: every light class in both precisions
+# (Measured on gfx950 at 1080 functions: the row buffer halves the time of the
+# atomic-bound FP32 kernels of the lightest classes; the FP64 kernels of most light
+# classes are bound by arithmetic and run faster as 1024-thread workgroups without it.)
+ROWS_CLASSES = {"ssss:8", "ppps:8", "dsps:8", "ssss:4", "psss:4", "psps:4", "ppss:4", "dsss:4"}
 
 
 def uses_rows(name, size):
@@ -337,14 +343,16 @@ def rows_call(name, t):
 # Single-pass classes whose kernels digest in five sweeps (one J/K block each).
 # JK_SWEEPS_OVERRIDE=1 turns sweeps on for every class above LDS_MAX_L, for
 # measurements.
-SWEEP_CLASSES = set()
+# (Measured on gfx950 at 1080 functions: 10-40 % faster for these classes in both
+# precisions, no change for the others.)
+SWEEP_CLASSES = {"pppp", "dspp", "dsds", "dpps", "dpds", "ddps"}
 
 
-def uses_sweeps(name):
+def uses_sweeps(sname):
     if os.environ.get("JK_SWEEPS_OVERRIDE") == "1":
-        L = sum("spd".index(ch) for ch in name)
+        L = sum("spd".index(ch) for ch in sname[:4])
         return L > LDS_MAX_L
-    return name in SWEEP_CLASSES
+    return sname in SWEEP_CLASSES or sname.endswith("_f32")
 
 
 def uses_lds(L, split):
@@ -358,9 +366,10 @@ def lane_options(L, split):
     return [1] if uses_lds(L, split) else [1, 4]
 
 
-def gen_class(la, lb, lc, ld):
+def gen_class(la, lb, lc, ld, suffix=""):
     L = la + lb + lc + ld
     name = cls_name(la, lb, lc, ld)
+    sname = name + suffix   # struct Cls_<sname>
     E = e_set(la, lb)
     Fs = e_set(lc, ld)
     ne, nf = len(E), len(Fs)
@@ -431,12 +440,12 @@ def gen_class(la, lb, lc, ld):
     s = []
     s.append(f"// class ({LNAME[la]}{LNAME[lb]}|{LNAME[lc]}{LNAME[ld]}): L = {L}, "
              f"{ne}x{nf} contracted [e0|f0], {na * nb * nc * nd} integrals")
-    s.append(f"struct Cls_{name} {{")
+    s.append(f"struct Cls_{sname} {{")
     s.append(f"  static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld}, L = {L};")
     s.append(f"  static constexpr int NA = {na}, NB = {nb}, NC = {nc}, ND = {nd};")
     s.append(f"  static constexpr int NE = {ne}, NF = {nf}, NACC = {ne * nf};")
     s.append(f"  static constexpr int GMAX = {lanes_for(L, False)};  // most lanes per shell quartet")
-    s.append(f"  static constexpr int WAVES64 = {class_waves(name, 8)}, WAVES32 = {class_waves(name, 4)};")
+    s.append(f"  static constexpr int WAVES64 = {class_waves(sname, 8)}, WAVES32 = {class_waves(sname, 4)};")
     s.append(f"  static constexpr int VRR_FLOPS = {vrr_flops}, HRR_FLOPS = {hrr_flops}, "
              f"DIGEST_FLOPS = {dig_flops};")
     s.append("  template <typename T>")
@@ -459,7 +468,7 @@ def gen_class(la, lb, lc, ld):
     s.append("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz;")
     s += ["    " + x for x in hrr.lines]
     s.append("  }")
-    s.append(f"  static constexpr int SWEEPS = {1 if uses_sweeps(name) else 0};  // digestion in five sweeps")
+    s.append(f"  static constexpr int SWEEPS = {1 if uses_sweeps(sname) else 0};  // digestion in five sweeps")
     sig = {"j": "const double* Dab, const double* Dcd, double* jab, double* jcd",
            "kac": "const double* Dbd, double* kac", "kad": "const double* Dbc, double* kad",
            "kbc": "const double* Dad, double* kbc", "kbd": "const double* Dac, double* kbd"}
@@ -482,7 +491,7 @@ def gen_class(la, lb, lc, ld):
         s.append("    return mx;")
         s.append("  }")
     s.append("};")
-    info = dict(name=name, la=la, lb=lb, lc=lc, ld=ld, L=L, nacc=ne * nf,
+    info = dict(name=name, sname=sname, la=la, lb=lb, lc=lc, ld=ld, L=L, nacc=ne * nf,
                 nint=na * nb * nc * nd, vrr_flops=vrr_flops, hrr_flops=hrr_flops,
                 digest_flops=dig_flops, vrr_nodes=vrr.n, hrr_nodes=hrr.n, nf=nf,
                 vrr_flops_alg=vrr_flops, lanes=lanes_for(L, False),
@@ -519,14 +528,21 @@ def pass_chunks(ne, nf, cap=None):
 PASS_ACC_WIDE = 96
 PASS_LIVE = 140
 
+# FP32 values take one VGPR instead of two, so the FP32 kernels of these classes
+# get their own layout: single-pass up to SPLIT_NACC32 accumulators (digestion in
+# sweeps), else passes twice the FP64 sizes.
+SPLIT_NACC32 = 160
+PASS_ACC32, PASS_ACC_WIDE32, PASS_LIVE32 = 128, 192, 280
 
-def split_chunks(L, E, Fs):
-    wide = pass_chunks(len(E), len(Fs), PASS_ACC_WIDE)
+
+def split_chunks(L, E, Fs, pass_acc=None, pass_acc_wide=None, pass_live=None):
+    pass_acc = pass_acc or PASS_ACC
+    wide = pass_chunks(len(E), len(Fs), pass_acc_wide or PASS_ACC_WIDE)
     worst = 0
     for ch in wide:
         outs = [(ii * len(Fs) + jf, E[ie], f) for ii, ie in enumerate(ch) for jf, f in enumerate(Fs)]
         worst = max(worst, len(outs) + max_live(build_vrr(L, outs).lines))
-    return wide if worst <= PASS_LIVE else pass_chunks(len(E), len(Fs))
+    return wide if worst <= (pass_live or PASS_LIVE) else pass_chunks(len(E), len(Fs), pass_acc)
 
 
 class KetHRR(Code):
@@ -583,28 +599,30 @@ VRR_PROLOGUE = [
 ]
 
 
-def gen_split_class(la, lb, lc, ld):
+def gen_split_class(la, lb, lc, ld, suffix="", pass_acc=None, pass_acc_wide=None,
+                    pass_live=None):
     """Multi-pass form: each pass accumulates (a block of E) x F in registers."""
     L = la + lb + lc + ld
     name = cls_name(la, lb, lc, ld)
+    sname = name + suffix   # struct Cls_<sname>
     E = e_set(la, lb)
     Fs = e_set(lc, ld)
     ne, nf = len(E), len(Fs)
     na, nb, nc, nd = ncart(la), ncart(lb), ncart(lc), ncart(ld)
-    chunks = split_chunks(L, E, Fs)
+    chunks = split_chunks(L, E, Fs, pass_acc, pass_acc_wide, pass_live)
     chunk = len(chunks[0])
     s = []
     s.append(f"// class ({LNAME[la]}{LNAME[lb]}|{LNAME[lc]}{LNAME[ld]}): L = {L}, "
              f"{ne}x{nf} contracted [e0|f0] built in {len(chunks)} passes of "
              f"<= {len(chunks[0])} bra components, {na * nb * nc * nd} integrals")
-    s.append(f"struct Cls_{name} {{")
+    s.append(f"struct Cls_{sname} {{")
     s.append(f"  static constexpr int LA = {la}, LB = {lb}, LC = {lc}, LD = {ld}, L = {L};")
     s.append(f"  static constexpr int NA = {na}, NB = {nb}, NC = {nc}, ND = {nd};")
     s.append(f"  static constexpr int NE = {ne}, NF = {nf}, NACC = {ne * nf};")
     s.append(f"  static constexpr int NPASS = {len(chunks)}, ECHUNK = {chunk};")
     s.append(f"  static constexpr int GMAX = {lanes_for(L, True)};  // most lanes per shell quartet")
-    s.append(f"  static constexpr int WAVES64 = {class_waves(name, 8, True)}, "
-             f"WAVES32 = {class_waves(name, 4, True)};")
+    s.append(f"  static constexpr int WAVES64 = {class_waves(sname, 8, True)}, "
+             f"WAVES32 = {class_waves(sname, 4, True)};")
     vrr_flops = 0
     for j, ch in enumerate(chunks):
         outs = [(ii * nf + jf, E[ie], f) for ii, ie in enumerate(ch) for jf, f in enumerate(Fs)]
@@ -656,13 +674,13 @@ def gen_split_class(la, lb, lc, ld):
              f"DIGEST_FLOPS = {dig_flops};")
     s.append("};")
     for j, ch in enumerate(chunks):
-        s.append(f"template <> struct Cls_{name}::Pass<{j}> {{ static constexpr int E0 = {ch[0]}, "
+        s.append(f"template <> struct Cls_{sname}::Pass<{j}> {{ static constexpr int E0 = {ch[0]}, "
                  f"NE = {len(ch)}; }};")
     one = VRR(L)
     for e in E:
         for f in Fs:
             one.node(e, f, 0)
-    info = dict(name=name, la=la, lb=lb, lc=lc, ld=ld, L=L, nacc=ne * nf,
+    info = dict(name=name, sname=sname, la=la, lb=lb, lc=lc, ld=ld, L=L, nacc=ne * nf,
                 nint=na * nb * nc * nd, vrr_flops=vrr_flops, hrr_flops=hrr_flops,
                 digest_flops=dig_flops, npass=len(chunks), split=True, nf=nf,
                 vrr_flops_alg=one.flops + ne * nf, lanes=lanes_for(L, True),
@@ -677,6 +695,9 @@ def wrapper(info):
     n = info["name"]
     kern = "eri_jk_split_kernel" if info["split"] else "eri_jk_kernel"
     skern = "schwarz_split_kernel" if info["split"] else "schwarz_kernel"
+    i32 = info.get("f32", info)   # FP32 layout (the class itself unless it has its own)
+    n32 = i32["sname"]
+    kern32 = "eri_jk_split_kernel" if i32["split"] else "eri_jk_kernel"
     w = [f"// generated by gen_hgp.py -- do not edit",
          '#include "jk_classes.hpp"',
          "namespace jk {",
@@ -699,14 +720,22 @@ def wrapper(info):
             f"  else launch_kernel(&eri_jk_lds_kernel<Cls_{n}, double, NT>, lgrid, dim3(NT), 0, s, a.dry != 0, a);",
             "}"] if info.get("lds") else []),
          *([] if info.get("lds") else [
+         "  const dim3 block(kBlock);",
+         "  if (fp32) {",
+         "    const int waves = " + ("a.nwaves" if i32["split"] else "a.nitems") + ";",
+         "    const dim3 grid((waves + kWavesPerBlock - 1) / kWavesPerBlock);",
+         *[ln for g_ in i32["lane_options"] for ln in (
+             f"    {'if' if g_ == i32['lane_options'][0] else 'else if'} (a.lanes == {g_} || "
+             f"{'true' if g_ == i32['lane_options'][-1] else 'false'})",
+             f"      launch_kernel(&{kern32}<Cls_{n32}, float, {g_}>, grid, block, 0, s, a.dry != 0, a);")],
+         "    return;",
+         "  }",
          "  const int waves = " + ("a.nwaves" if info["split"] else "a.nitems") + ";",
-         "  const dim3 grid((waves + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);",
+         "  const dim3 grid((waves + kWavesPerBlock - 1) / kWavesPerBlock);",
          *[ln for g_ in info["lane_options"] for ln in (
              f"  {'if' if g_ == info['lane_options'][0] else 'else if'} (a.lanes == {g_} || "
-             f"{'true' if g_ == info['lane_options'][-1] else 'false'}) {{",
-             f"    if (fp32) launch_kernel(&{kern}<Cls_{n}, float, {g_}>, grid, block, 0, s, a.dry != 0, a);",
-             f"    else launch_kernel(&{kern}<Cls_{n}, double, {g_}>, grid, block, 0, s, a.dry != 0, a);",
-             "  }")],
+             f"{'true' if g_ == info['lane_options'][-1] else 'false'})",
+             f"    launch_kernel(&{kern}<Cls_{n}, double, {g_}>, grid, block, 0, s, a.dry != 0, a);")],
          "}"])]
     if info["bra_class"] == info["ket_class"]:
         w += [f"void launch_schwarz_{n}(const EriLaunch& a, double* Q, hipStream_t s) {{",
@@ -753,12 +782,16 @@ def table(infos):
         return ((i["nacc"] + ne * ncd) * tb + ncd * 8), 64 * (na * nc + na * nd + nb * nc + nb * nd) * 8
     t.append("// bytes of workspace per wavefront of the multi-pass classes with `lanes` lanes")
     t.append("// per quartet (0: not a multi-pass class); the kernels use split_wave_bytes")
+    f32 = [i.get("f32", i) for i in infos]
     t.append("size_t split_ws_bytes(int cls, int fp32, int lanes) {")
     t.append("  static const size_t s64[21] = {" + ", ".join(str(wsb(i, 8)[0]) if i["split"] else "0" for i in infos) + "};")
-    t.append("  static const size_t s32[21] = {" + ", ".join(str(wsb(i, 4)[0]) if i["split"] else "0" for i in infos) + "};")
-    t.append("  static const size_t k[21] = {" + ", ".join(str(wsb(i, 8)[1]) if i["split"] else "0" for i in infos) + "};")
-    t.append("  if (cls < 0 || cls >= 21 || lanes < 1 || !k[cls]) return 0;")
-    t.append("  return static_cast<size_t>(64 / lanes) * (fp32 ? s32[cls] : s64[cls]) + k[cls];")
+    t.append("  static const size_t s32[21] = {" + ", ".join(str(wsb(i, 4)[0]) if i["split"] else "0" for i in f32) + "};")
+    t.append("  static const size_t k64[21] = {" + ", ".join(str(wsb(i, 8)[1]) if i["split"] else "0" for i in infos) + "};")
+    t.append("  static const size_t k32[21] = {" + ", ".join(str(wsb(i, 8)[1]) if i["split"] else "0" for i in f32) + "};")
+    t.append("  if (cls < 0 || cls >= 21 || lanes < 1) return 0;")
+    t.append("  const size_t k = fp32 ? k32[cls] : k64[cls];")
+    t.append("  if (!k) return 0;")
+    t.append("  return static_cast<size_t>(64 / lanes) * (fp32 ? s32[cls] : s64[cls]) + k;")
     t.append("}")
     t.append("// bytes per wavefront of the multi-pass Schwarz kernel of a diagonal class (FP64)")
     t.append("size_t split_schwarz_ws_bytes(int cls) {")
@@ -768,13 +801,15 @@ def table(infos):
     t.append("  return (cls >= 0 && cls < 21) ? w[cls] : 0;")
     t.append("}")
     t.append("// bit g set: the class has a kernel with g lanes per shell quartet")
-    t.append("int class_lane_mask(int cls) {")
-    t.append("  static const int m[21] = {" + ", ".join(str(sum(1 << g_ for g_ in i["lane_options"])) for i in infos) + "};")
-    t.append("  return (cls >= 0 && cls < 21) ? m[cls] : 2;")
+    t.append("int class_lane_mask(int cls, int fp32) {")
+    t.append("  static const int m[2][21] = {{" + ", ".join(str(sum(1 << g_ for g_ in i["lane_options"])) for i in infos) + "}, {"
+             + ", ".join(str(sum(1 << g_ for g_ in i["lane_options"])) for i in f32) + "}};")
+    t.append("  return (cls >= 0 && cls < 21) ? m[fp32 ? 1 : 0][cls] : 2;")
     t.append("}")
-    t.append("int class_lanes(int cls) {")
-    t.append("  static const int g[21] = {" + ", ".join(str(i["lanes"]) for i in infos) + "};")
-    t.append("  return (cls >= 0 && cls < 21) ? g[cls] : 1;")
+    t.append("int class_lanes(int cls, int fp32) {")
+    t.append("  static const int g[2][21] = {{" + ", ".join(str(i["lanes"]) for i in infos) + "}, {"
+             + ", ".join(str(i["lanes"]) for i in f32) + "}};")
+    t.append("  return (cls >= 0 && cls < 21) ? g[fp32 ? 1 : 0][cls] : 1;")
     t.append("}")
     t.append("void launch_schwarz(int pair_class, const EriLaunch& a, double* Q, hipStream_t s) {")
     t.append("  switch (pair_class) {")
@@ -801,6 +836,14 @@ def main(outdir):
         ne, nf = len(e_set(la, lb)), len(e_set(lc, ld))
         if ne * nf > SPLIT_NACC:
             code, info = gen_split_class(la, lb, lc, ld)
+            if ne * nf <= SPLIT_NACC32:
+                code32, info32 = gen_class(la, lb, lc, ld, "_f32")
+                info32["split"] = False
+            else:
+                code32, info32 = gen_split_class(la, lb, lc, ld, "_f32", PASS_ACC32, PASS_ACC_WIDE32,
+                                                 PASS_LIVE32)
+            info["f32"] = info32
+            code += code32
         else:
             code, info = gen_class(la, lb, lc, ld)
             info["split"] = False

@@ -57,8 +57,8 @@ size_t split_ws_bytes(int cls, int fp32, int lanes);
 size_t split_schwarz_ws_bytes(int cls);
 // Lanes that share one shell quartet in the class's kernel (the most it has),
 // and the set of lane counts compiled for it (bit g for g lanes).
-int class_lanes(int cls);
-int class_lane_mask(int cls);
+int class_lanes(int cls, int fp32);
+int class_lane_mask(int cls, int fp32);
 // Relative cost per primitive quartet of class `cls` (energy, or gradient if grad).
 double class_cost(int cls, int grad);
 // Cauchy-Schwarz factors of the pairs of one bin of pair class 0..5.

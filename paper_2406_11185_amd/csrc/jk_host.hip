@@ -868,13 +868,13 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
   S.lanes.assign(2 * nbp, 1);
   for (int bp = 0; bp < nbp; ++bp) {
     const int cls = quartet_class(P.bin_cls[P.bp_x[bp]], P.bin_cls[P.bp_y[bp]]);
-    const int gmax = grad ? grad_lanes(cls) : class_lanes(cls);
     for (int pr = 0; pr < 2; ++pr) {
+      const int gmax = grad ? grad_lanes(cls) : class_lanes(cls, pr);
       // the fewest lanes per quartet that still give kTargetWaves/2 wavefronts
       const unsigned long long q = S.qstat[3 * bp + pr];
       // (gradient: and whose workspace still lets kTargetWaves/2 wavefronts run)
       int lanes = gmax;
-      const int mask = grad ? grad_lane_mask(cls) : class_lane_mask(cls);
+      const int mask = grad ? grad_lane_mask(cls) : class_lane_mask(cls, pr);
       const bool split = !grad && split_ws_bytes(cls, pr, 1) != 0;
       const unsigned long long want = split ? kSplitTargetWaves : kTargetWaves / 2;
       for (int g = 1; g <= gmax; g *= 2) {

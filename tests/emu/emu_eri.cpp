@@ -150,6 +150,24 @@ extern "C" int emu_block(int cls, const int* l, const int* np, const double* A, 
   return 0;
 }
 
+// The FP32 layouts of the multi-pass classes (their own pass sizes, or one
+// pass), evaluated here in double precision like the others.
+extern "C" int emu_block32(int cls, const int* l, const int* np, const double* A, const double* e,
+                           const double* c, double* out) {
+  Sh s[4];
+  for (int k = 0; k < 4; ++k) {
+    s[k].l = l[k]; s[k].np = np[k];
+    for (int x = 0; x < 3; ++x) s[k].A[x] = A[3 * k + x];
+    for (int i = 0; i < np[k]; ++i) { s[k].e[i] = e[8 * k + i]; s[k].c[i] = c[8 * k + i]; }
+  }
+  switch (cls) {
+#define S3(i, N) case i: block<Cls_##N##_f32>(s[0], s[1], s[2], s[3], out); break;
+    S3(12, dppp) S3(14, dpdp) S3(17, ddpp) S3(18, ddds) S3(19, dddp) S3(20, dddd)
+    default: return -1;
+  }
+  return 0;
+}
+
 // The five digestion sweeps of a single-pass class against its one-sweep
 // digestion, on arbitrary contracted values and D blocks; returns the largest
 // difference over all six blocks (multi-pass classes: 0, they have no sweeps).

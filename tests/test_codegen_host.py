@@ -50,8 +50,12 @@ def _p(a, t):
     return a.ctypes.data_as(t)
 
 
-def test_every_energy_class_matches_oracle(libs):
+@pytest.mark.parametrize("entry", ["emu_block", "emu_block32"])
+def test_every_energy_class_matches_oracle(libs, entry):
+    """Every class (emu_block32: the FP32 layouts of the multi-pass classes,
+    evaluated in double precision) against the oracle."""
     lib = libs["emu_eri"]
+    fn = getattr(lib, entry)
     mol = molgen.workload("w4")
     b = oracle.Basis(mol)
     ls = mol.shell_l
@@ -82,8 +86,11 @@ def test_every_energy_class_matches_oracle(libs):
                 c[8 * k:8 * k + 3] = mol.coefs[p0:p0 + 3]
             ref = oracle.shell_quartet(b, *sh).ravel()
             out = np.zeros(ref.size)
-            assert lib.emu_block(q, _p(l, ip), _p(npr, ip), _p(cen, dp), _p(e, dp), _p(c, dp),
-                                 _p(out, dp)) == 0
+            rc = fn(q, _p(l, ip), _p(npr, ip), _p(cen, dp), _p(e, dp), _p(c, dp), _p(out, dp))
+            if entry == "emu_block32" and rc == -1:   # no separate FP32 layout
+                q += 1
+                continue
+            assert rc == 0
             assert np.abs(out - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), (q, sh)
             q += 1
 
