@@ -83,7 +83,7 @@ def source_fingerprint() -> str:
 def kernel_key(name: str):
     """'eri_jk <class> fp64|fp32' for a J/K class kernel name, else None."""
     import re
-    m = re.search(r"jk::eri_jk(?:_lds|_split)?_kernel<jk::Cls_(\w+), (double|float)", name)
+    m = re.search(r"jk::eri_jk(?:_lds|_split|_rows)?_kernel<jk::Cls_([a-z]{4})\w*, (double|float)", name)
     if not m:
         return None
     return f"eri_jk {m.group(1)} {'fp64' if m.group(2) == 'double' else 'fp32'}"

@@ -7,11 +7,11 @@
 bench.py, with each J/K class kernel's algorithmic rate (flops of the generated
 code per quartet, from classes.json, times the quartets the benchmark line of
 the same run reports for that class, over the kernel's mean duration).
-`valu`: VALU instruction counters per J/K class kernel (one `--pmc` run) turned
+`valu`: VALU instruction counters per J/K class kernel (`--pmc` runs) turned
 into counter flops -- 64 lanes x (2 per FMA, 1 per add, multiply or
 transcendental) per wavefront instruction, an upper bound that counts inactive
 lanes -- next to the algorithmic flops, both over the kernel durations of the
-stats run.
+stats run, and the memory-side atomic requests of each kernel.
 """
 from __future__ import annotations
 
@@ -100,6 +100,7 @@ def stats(args):
 VALU = {"SQ_INSTS_VALU_FMA_F64": 2, "SQ_INSTS_VALU_ADD_F64": 1, "SQ_INSTS_VALU_MUL_F64": 1,
         "SQ_INSTS_VALU_TRANS_F64": 1, "SQ_INSTS_VALU_FMA_F32": 2, "SQ_INSTS_VALU_ADD_F32": 1,
         "SQ_INSTS_VALU_MUL_F32": 1, "SQ_INSTS_VALU_TRANS_F32": 1}
+ATOMIC = ("TCC_EA0_ATOMIC_sum", "TCC_ATOMIC_sum")
 
 
 def valu(args):
@@ -109,10 +110,10 @@ def valu(args):
         with open(path) as fh:
             for r in csv.DictReader(fh):
                 k = kernel_key(r["Kernel_Name"])
-                if not k or r["Counter_Name"] not in VALU:
+                if not k or (r["Counter_Name"] not in VALU and r["Counter_Name"] not in ATOMIC):
                     continue
                 per[k][r["Counter_Name"]] += float(r["Counter_Value"])
-                calls[k].add(r.get("Dispatch_Id", r.get("Correlation_Id", "")))
+                calls[(k, r["Counter_Name"])].add(r.get("Dispatch_Id", r.get("Correlation_Id", "")))
     st = read_stats(args.stats) if args.stats else {}
     avg = {}
     for name, (_, _, a) in st.items():
@@ -122,30 +123,37 @@ def valu(args):
     bench = load_bench(args.bench)
     infos = class_infos()
     n_dm = bench["config"]["n_dm"]
-    lines = [f"# VALU counters per class kernel: {args.title}", "", "Commands:", "", "```",
+    lines = [f"# VALU and atomic counters per class kernel: {args.title}", "", "Commands:", "", "```",
              *args.command.split(";;"), "```", "",
              "Counter flops = 64 x (2 FMA + ADD + MUL + TRANS) per wavefront instruction, FP64 and "
              "FP32 counted separately (an upper bound: inactive lanes are counted).  Algorithmic "
              "flops from the generated code.  Rates over the kernel's mean duration in the "
-             f"kernel-statistics run; fractions of {PEAK} TFLOP/s.", "",
+             f"kernel-statistics run; fractions of {PEAK} TFLOP/s.  Atomics: TCC_EA0_ATOMIC, the "
+             "atomic requests the L2 forwards to the memory side (device-scope atomics on this "
+             "chip are all executed there; TCC_ATOMIC reads the same), per screened quartet and "
+             "per second.", "",
              "| kernel | counter GFLOP fp64 | counter GFLOP fp32 | algorithmic GFLOP | "
-             "counter / algorithmic | counter TFLOP/s | algorithmic TFLOP/s | frac (counter) |",
-             "|---|---|---|---|---|---|---|---|"]
+             "counter / algorithmic | counter TFLOP/s | algorithmic TFLOP/s | frac (counter) | "
+             "atomics per quartet | atomic G/s |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
     rows = []
     for k, cnt in per.items():
-        ncall = max(1, len(calls[k]))
-        f64 = 64 * sum(VALU[c] * v for c, v in cnt.items() if c.endswith("F64")) / ncall / 1e9
-        f32 = 64 * sum(VALU[c] * v for c, v in cnt.items() if c.endswith("F32")) / ncall / 1e9
+        def pc(c):   # per dispatch
+            return cnt.get(c, 0.0) / max(1, len(calls.get((k, c), ())))
+        f64 = 64 * sum(VALU[c] * pc(c) for c in VALU if c.endswith("F64")) / 1e9
+        f32 = 64 * sum(VALU[c] * pc(c) for c in VALU if c.endswith("F32")) / 1e9
         c = bench["classes"].get(f"{k[0]}_{k[1]}")
-        alg = flops_per_quartet(infos[k[0]], n_dm=n_dm) * c["quartets"] / 1e9 if c else 0.0
+        nq = c["quartets"] if c else 0
+        alg = flops_per_quartet(infos[k[0]], n_dm=n_dm) * nq / 1e9
         a = avg.get(k)
-        ct = (f64 + f32) / a / 1e3 if a else None
-        at = alg / a / 1e3 if a else None
+        at = pc("TCC_EA0_ATOMIC_sum")
+        nan = float("nan")
+        ct = (f64 + f32) / a if a else nan   # GFLOP per ms = TFLOP/s
         rows.append((-(f64 + f32), f"| eri_jk {k[0]} {k[1]} ({k[2]}) | {f64:.2f} | {f32:.2f} | "
-                                   f"{alg:.2f} | {(f64 + f32) / alg if alg else float('nan'):.2f} | "
-                                   f"{ct if ct else float('nan'):.1f} | "
-                                   f"{at if at else float('nan'):.1f} | "
-                                   f"{ct / PEAK if ct else float('nan'):.3f} |"))
+                                   f"{alg:.2f} | {(f64 + f32) / alg if alg else nan:.2f} | "
+                                   f"{ct:.1f} | {alg / a if a else nan:.1f} | "
+                                   f"{ct / PEAK:.3f} | {at / nq if nq else nan:.2f} | "
+                                   f"{at / (a / 1e3) / 1e9 if a else nan:.1f} |"))
     lines += [r for _, r in sorted(rows)]
     with open(args.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
