@@ -105,6 +105,12 @@ typedef struct {
   int32_t serial;             /* 1: every class launch goes to the caller's stream in turn,
                                  so each kernel runs alone (default 0: after the largest
                                  launch, the rest are spread over three internal streams) */
+  int32_t reuse_setup;        /* 1: reuse the pair data, Schwarz factors, screening ranges
+                                 and work items of the previous call on this context when
+                                 the basis (every array element), tol, precision and
+                                 fp32_below are unchanged (D may change, as between SCF
+                                 iterations); any call that sets them up again replaces
+                                 the kept ones.  0 (default): set up on every call.      */
   double* energy;             /* jk_build, optional (NULL = not written): DEVICE pointer to
                                  [n_dm][3] receiving E_J = 1/2 tr(D J), E_K = 1/4 tr(D K)
                                  and E = E_J - E_K, summed in a fixed order             */
@@ -126,6 +132,7 @@ typedef struct {
   int32_t launches_fp64[JK_NCLASS];   /* integral kernel launches per class               */
   int32_t launches_fp32[JK_NCLASS];
   int32_t class_l[JK_NCLASS][4];      /* (la, lb, lc, ld) of each class index             */
+  int32_t setup_reused;               /* 1 if the call reused the kept setup (reuse_setup) */
 } jk_stats;
 
 /* Fill `opts` with the defaults.  Returns JK_EINVAL if opts is NULL. */

@@ -31,6 +31,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -533,9 +534,18 @@ std::string take_guard_error() {
 }
 }  // namespace jk
 
+namespace {
+struct Setup;
+}  // namespace
+
 struct jk_ctx {
   int device = 0;
   size_t ws_budget = 0;            // workspace bytes a multi-pass launch may use
+  // setup kept for jk_opts.reuse_setup: its key (basis arrays, tol and the
+  // options the setup depends on) and the setup itself, whose device arrays
+  // live in this context's buffers until a later setup replaces them
+  std::vector<char> setup_key;
+  std::shared_ptr<Setup> setup_kept;
   int num_cu = 0;
   std::string err;
   DevBuf buf[sNumSlots];
@@ -919,6 +929,55 @@ Setup setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStrea
   return S;
 }
 
+// Byte string that identifies a setup: the basis arrays element by element,
+// tol and the options and context state the setup reads.
+std::vector<char> setup_key(const jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o,
+                            bool grad) {
+  std::vector<char> k;
+  auto put = [&k](const void* p, size_t bytes) {
+    const char* q = static_cast<const char*>(p);
+    k.insert(k.end(), q, q + bytes);
+  };
+  int np = 0;
+  for (int s = 0; s < b->n_shells; ++s) np = std::max(np, b->shell_prim0[s] + b->shell_nprim[s]);
+  const int32_t head[4] = {b->n_atoms, b->n_shells, np, grad ? 1 : 0};
+  put(head, sizeof(head));
+  put(b->xyz, sizeof(double) * 3 * b->n_atoms);
+  put(b->shell_atom, sizeof(int32_t) * b->n_shells);
+  put(b->shell_l, sizeof(int32_t) * b->n_shells);
+  put(b->shell_nprim, sizeof(int32_t) * b->n_shells);
+  put(b->shell_prim0, sizeof(int32_t) * b->n_shells);
+  put(b->exps, sizeof(double) * np);
+  put(b->coefs, sizeof(double) * np);
+  const double f[2] = {tol, o.precision == JK_MIXED ? o.fp32_below : 0.0};
+  put(f, sizeof(f));
+  put(&o.precision, sizeof(o.precision));
+  put(&c->ws_budget, sizeof(c->ws_budget));
+  return k;
+}
+
+// Steps 1-6, or the kept setup of an earlier call when reuse_setup is set and
+// nothing it depends on has changed.
+Setup get_setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStream_t s,
+                bool grad, bool* reused) {
+  *reused = false;
+  std::vector<char> key;
+  if (o.reuse_setup == 1) {
+    key = setup_key(c, b, tol, o, grad);
+    if (c->setup_kept && key == c->setup_key) {
+      *reused = true;
+      return *c->setup_kept;
+    }
+  }
+  c->setup_kept.reset();   // the new setup overwrites the kept one's buffers
+  Setup S = setup(c, b, tol, o, s, grad);
+  if (o.reuse_setup == 1) {
+    c->setup_kept = std::make_shared<Setup>(S);
+    c->setup_key.swap(key);
+  }
+  return S;
+}
+
 jk_stats base_stats(const Plan& P, const Setup& S) {
   jk_stats st{};
   for (int q = 0; q < JK_NCLASS; ++q) {
@@ -1067,6 +1126,7 @@ int check_opts(const jk_opts* o, jk_opts* out, std::string* msg) {
   if (out->timing != 0 && out->timing != 1) { *msg = "opts.timing"; return JK_EINVAL; }
   if (out->acc_copies < 0 || out->acc_copies > static_cast<int32_t>(kMaxCopies)) { *msg = "opts.acc_copies must be in 0..8"; return JK_EINVAL; }
   if (out->serial != 0 && out->serial != 1) { *msg = "opts.serial must be 0 or 1"; return JK_EINVAL; }
+  if (out->reuse_setup != 0 && out->reuse_setup != 1) { *msg = "opts.reuse_setup must be 0 or 1"; return JK_EINVAL; }
   return JK_OK;
 }
 
@@ -1085,6 +1145,7 @@ int jk_opts_default(jk_opts* o) {
   o->max_scratch_bytes = 0;
   o->acc_copies = 0;
   o->serial = 0;
+  o->reuse_setup = 0;
   o->energy = nullptr;
   o->dEdD = nullptr;
   return JK_OK;
@@ -1171,7 +1232,8 @@ int build_impl(jk_ctx* c, const jk_basis* basis, const double* D, double* J, dou
     c->ev_used = 0;
     c->timed_launches.clear();
     if (c->timed) c->ev_setup0 = event(c, s);
-    Setup S = setup(c, basis, tol, o, s, false);
+    bool reused = false;
+    Setup S = get_setup(c, basis, tol, o, s, false, &reused);
     const Plan& P = S.P;
     if (c->timed) c->ev_setup1 = event(c, s);
     const size_t nn = static_cast<size_t>(nbf) * nbf;
@@ -1204,6 +1266,7 @@ int build_impl(jk_ctx* c, const jk_basis* basis, const double* D, double* J, dou
                              : nullptr;
 
     jk_stats st = base_stats(P, S);
+    st.setup_reused = reused ? 1 : 0;
     auto waves_of = [&](const LaunchRec& r) {
       const size_t per_wave = split_ws_bytes(r.cls, r.pr, r.lanes);
       if (!per_wave) return std::pair<int, size_t>(0, 0);
@@ -1289,7 +1352,8 @@ int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, dou
     c->ev_used = 0;
     c->timed_launches.clear();
     if (c->timed) c->ev_setup0 = event(c, s);
-    Setup S = setup(c, basis, tol, o, s, true);
+    bool reused = false;
+    Setup S = get_setup(c, basis, tol, o, s, true, &reused);
     const Plan& P = S.P;
     if (c->timed) c->ev_setup1 = event(c, s);
     const size_t ng = static_cast<size_t>(o.n_dm) * basis->n_atoms * 3;
@@ -1297,6 +1361,7 @@ int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, dou
     const bool det = o.deterministic == 1;
     double* gacc = det ? dev<double>(c, sGradAcc, 2 * ng) : dEdR;
     jk_stats st = base_stats(P, S);
+    st.setup_reused = reused ? 1 : 0;
     // gradient work arrays live in a per-stream workspace; a launch uses at most
     // kWsBudget bytes and loops over its items with a fixed number of waves
     auto waves_of = [&](const LaunchRec& r) {

@@ -47,7 +47,8 @@ class jk_opts(ctypes.Structure):
                 ("boys_fp64_T", ctypes.c_double), ("n_dm", ctypes.c_int32),
                 ("deterministic", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("max_scratch_bytes", ctypes.c_uint64), ("acc_copies", ctypes.c_int32),
-                ("serial", ctypes.c_int32), ("energy", ctypes.c_void_p),
+                ("serial", ctypes.c_int32), ("reuse_setup", ctypes.c_int32),
+                ("energy", ctypes.c_void_p),
                 ("dEdD", ctypes.c_void_p)]
 
 
@@ -61,7 +62,7 @@ class jk_stats(ctypes.Structure):
                 ("ms_setup", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("launches_fp64", ctypes.c_int32 * JK_NCLASS),
                 ("launches_fp32", ctypes.c_int32 * JK_NCLASS),
-                ("class_l", (ctypes.c_int32 * 4) * JK_NCLASS)]
+                ("class_l", (ctypes.c_int32 * 4) * JK_NCLASS), ("setup_reused", ctypes.c_int32)]
 
 
 _lib = None
@@ -123,7 +124,7 @@ def jk_opts_default() -> jk_opts:
 
 def make_opts(precision="fp64", fp32_below=1e-4, n_dm=1, timing=False, boys_fp64_T=30.0,
               max_scratch_bytes=0, deterministic=0, acc_copies=0, serial=False, energy=None,
-              dEdD=None) -> jk_opts:
+              dEdD=None, reuse_setup=False) -> jk_opts:
     """jk_opts from keywords; energy / dEdD are float64 device tensors (or None)."""
     o = jk_opts_default()
     o.precision = {"fp64": JK_FP64, "mixed": JK_MIXED}[precision] if isinstance(precision, str) \
@@ -136,6 +137,7 @@ def make_opts(precision="fp64", fp32_below=1e-4, n_dm=1, timing=False, boys_fp64
     o.deterministic = int(deterministic)
     o.acc_copies = int(acc_copies)
     o.serial = 1 if serial else 0
+    o.reuse_setup = 1 if reuse_setup else 0
     o.energy = energy.data_ptr() if energy is not None else None
     o.dEdD = dEdD.data_ptr() if dEdD is not None else None
     return o

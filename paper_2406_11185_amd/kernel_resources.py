@@ -106,10 +106,18 @@ def main():
              "| waves/SIMD |",
              "|---|---|---|---|---|---|---|"]
     for r in sorted(rows, key=lambda r: r["name"]):
+        if r["name"].startswith(("rocprim::", "hipcub::")):
+            continue   # the sort and scan kernels of the ROCm libraries
         lines.append(f"| `{r['name']}` | {r['vgpr']} | {r['agpr']} | {r['vspill']} | {r['scratch']} "
                      f"| {r['lds']} | {r['waves']} |")
     text = "\n".join(lines) + "\n"
     if a.md:
+        text = ("# Registers, spills, scratch and LDS of every kernel of libjk.so (gfx950)\n\n"
+                "From the code-object metadata of this repository's build, written by\n\n"
+                "```\npython -m paper_2406_11185_amd.build && "
+                f"python -m paper_2406_11185_amd.kernel_resources --md {os.path.relpath(a.md, ROOT)}\n```\n\n"
+                "waves/SIMD: the limit the unified register count alone sets (512 per lane).\n\n"
+                + text)
         with open(a.md, "w") as fh:
             fh.write(text)
     print(text)

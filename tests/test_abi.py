@@ -33,8 +33,34 @@ def test_opts_default():
     o = jkb.jk_opts_default()
     assert o.precision == jkb.JK_FP64 and o.n_dm == 1 and o.fp32_below == 1e-4
     assert o.boys_fp64_T == 30.0 and o.deterministic == 0 and o.max_scratch_bytes == 0
-    assert o.acc_copies == 0 and o.serial == 0 and not o.energy and not o.dEdD
+    assert o.acc_copies == 0 and o.serial == 0 and o.reuse_setup == 0
+    assert not o.energy and not o.dEdD
     assert jkb.load().jk_opts_default(None) == jkb.JK_EINVAL
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Size and field offsets of the binding's ctypes structures equal what a C
+    compiler makes of include/jk.h."""
+    import json
+    import subprocess
+    structs = (jkb.jk_basis, jkb.jk_opts, jkb.jk_stats)
+    body = []
+    for st in structs:
+        name = st.__name__
+        body.append(f'printf("\\"{name}\\": [%zu", sizeof({name}));')
+        for f, _ in st._fields_:
+            body.append(f'printf(", %zu", offsetof({name}, {f}));')
+        body.append('printf("]%s", ' + ('"\\n"' if st is structs[-1] else '", "') + ');')
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"jk.h\"\nint main(void) {\n"
+                   'printf("{");\n' + "\n".join(body) + '\nprintf("}\\n");\nreturn 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    got = json.loads(subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout)
+    for st in structs:
+        want = [ctypes.sizeof(st)] + [getattr(st, f).offset for f, _ in st._fields_]
+        assert got[st.__name__] == want, st.__name__
 
 
 def test_validate_basis_counts_functions():

@@ -37,7 +37,7 @@ def libs(tmp_path_factory):
     for name in ("emu_eri", "emu_grad"):
         so = os.path.join(gen, f"lib{name}.so")
         procs.append((name, so, subprocess.Popen(
-            ["g++", "-O0", "-std=c++17", "-fPIC", "-shared", "-D__device__=", "-I", gen, "-o", so,
+            ["g++", "-O0", "-std=c++17", "-fPIC", "-shared", "-D__device__=", "-D_GLIBCXX_ASSERTIONS", "-I", gen, "-o", so,
              os.path.join(HERE, "emu", f"{name}.cpp")], stderr=subprocess.PIPE)))
     for name, so, p in procs:
         _, err = p.communicate()

@@ -120,3 +120,43 @@ def test_fp32_boys_at_lowest_switch_over():
     say("  max|dJ| =", np.abs(J - Jo).max(), " max|dK| =", np.abs(K - Ko).max())
     assert np.abs(J - Jo).max() <= 1e-6 * np.abs(Jo).max()
     assert np.abs(K - Ko).max() <= 1e-6 * np.abs(Ko).max()
+
+
+def test_setup_reuse_across_calls():
+    """reuse_setup = 1: a second call with the same basis, tol and precision keeps
+    the pair data, bounds and work items of the first (stats.setup_reused) and,
+    with another D, gives J and K bit for bit equal to a fresh context's
+    (deterministic mode) and within the oracle bound; a changed tol or exponent,
+    or a call without the option, sets up again."""
+    import torch
+    from paper_2406_11185_amd import jk as jkb
+    mol = molgen.make_molecule(3, 3, 21, n_dm=1)
+    say(f"case setup reuse ({mol.n_bf} functions, tol 1e-8)")
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal(mol.D.shape[1:]) * 0.05
+    D2h = mol.D * 0.5 + (X + X.T)[None]
+    basis = jkb.Basis(mol)
+    D1, D2 = _dev(mol.D), _dev(D2h)
+    J, K = torch.empty_like(D1), torch.empty_like(D1)
+
+    def build(ctx, D, tol, reuse, b=basis):
+        o = jkb.make_opts("fp64", deterministic=1, reuse_setup=reuse)
+        jkb.jk_build(ctx, b, D, J, K, tol, o)
+        torch.cuda.synchronize()
+        return J.cpu().numpy(), K.cpu().numpy(), ctx.stats().setup_reused
+
+    ctx = jkb.Context(0)
+    assert build(ctx, D1, 1e-8, True)[2] == 0
+    J2, K2, reused = build(ctx, D2, 1e-8, True)
+    assert reused == 1
+    J2f, K2f, r = build(jkb.Context(0), D2, 1e-8, False)
+    assert r == 0 and np.array_equal(J2, J2f) and np.array_equal(K2, K2f)
+    mol2 = molgen.Molecule(**{**mol.__dict__, "D": D2h})
+    Jo, Ko, _ = oracle.jk(mol2, 1e-8)
+    assert np.abs(J2 - Jo).max() <= TOL_ABS and np.abs(K2 - Ko).max() <= TOL_ABS
+    assert build(ctx, D2, 1e-9, True)[2] == 0          # tol changed
+    assert build(ctx, D2, 1e-9, True)[2] == 1
+    mol3 = molgen.Molecule(**{**mol.__dict__, "exps": mol.exps * 1.01})
+    assert build(ctx, D2, 1e-9, True, jkb.Basis(mol3))[2] == 0   # an exponent changed
+    assert build(ctx, D2, 1e-9, False)[2] == 0         # no reuse asked: set up again
+    assert build(ctx, D2, 1e-9, True)[2] == 0          # ... which replaced the kept setup
