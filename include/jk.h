@@ -159,6 +159,21 @@ int jk_validate_basis(const jk_basis* basis, int32_t* n_bf_out);
 int jk_build(jk_ctx* ctx, const jk_basis* basis, const double* D, double* J, double* K,
              double tol, const jk_opts* opts, void* hip_stream);
 
+/* jk_build for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, results and kernels as jk_build, but every device buffer of the
+ * call is carved from one static device array of 64 MiB that the library holds
+ * on each GPU it runs on (until the process ends), and the two small
+ * device-to-host copies go through host memory allocated with the context.
+ * The call makes no hipMalloc, hipFree or other allocating call.  Returns
+ * JK_ENOMEM with a message when the molecule needs more than the 64 MiB (about
+ * 300 basis functions with the default options), JK_EUNSUPPORTED for
+ * opts->timing = 1.  Every call on a GPU shares that GPU's array and leaves its
+ * contents behind; calls that overlap on one GPU (other streams, other
+ * contexts, other threads) race and must not be made. */
+int jk_build_noalloc(jk_ctx* ctx, const jk_basis* basis, const double* D, double* J, double* K,
+                     double tol, const jk_opts* opts, void* hip_stream);
+
 /* Nuclear gradient of E = 1/2 tr(D J) - 1/4 tr(D K) at fixed D (basis functions
  * move with their atoms), under the same screening rule as jk_build: the
  * two-electron part of the single-point force, one of the core tasks in the

@@ -534,12 +534,26 @@ std::string take_guard_error() {
 }
 }  // namespace jk
 
+// Device scratch of jk_build_noalloc: a file-scope array each GPU holds once
+// the library's code object is loaded on it, until the process ends.  Host code
+// never uses its name as an address: jk_ctx_create asks the runtime for the
+// array's device address (hipGetSymbolAddress) with the context's device
+// current and keeps that pointer in the context.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+// Host staging of the two small device-to-host copies in jk_build_noalloc.
+constexpr size_t kNoAllocHostBytes = size_t(1) << 20;
+
 namespace {
 struct Setup;
 }  // namespace
 
 struct jk_ctx {
   int device = 0;
+  char* noalloc_base = nullptr;    // device address of `scratch` on this context's device
+  bool noalloc = false;            // inside jk_build_noalloc: buffers come from scratch
+  size_t noalloc_off = 0;          // bytes of scratch handed out in this call
+  std::vector<char> noalloc_host;  // kNoAllocHostBytes, allocated with the context
   size_t ws_budget = 0;            // workspace bytes a multi-pass launch may use
   // setup kept for jk_opts.reuse_setup: its key (basis arrays, tol and the
   // options the setup depends on) and the setup itself, whose device arrays
@@ -579,6 +593,14 @@ thread_local std::string g_create_err;
 template <typename T>
 T* dev(jk_ctx* c, Slot s, size_t count) {
   const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  if (c->noalloc) {   // bump allocation from the static scratch array, 256-byte aligned
+    const size_t at = (c->noalloc_off + 255) & ~size_t(255);
+    if (at + bytes > kNoAllocBytes)
+      throw Fail{JK_ENOMEM, "jk_build_noalloc: the call needs more than the " +
+                                std::to_string(kNoAllocBytes >> 20) + " MiB of static scratch"};
+    c->noalloc_off = at + bytes;
+    return reinterpret_cast<T*>(c->noalloc_base + at);
+  }
   DevBuf& b = c->buf[s];
   if (c->scratch_limit) {
     size_t total = 0;
@@ -600,6 +622,12 @@ T* dev(jk_ctx* c, Slot s, size_t count) {
 }
 
 void* pinned(jk_ctx* c, size_t bytes) {
+  if (c->noalloc) {   // pageable staging allocated with the context (copies complete on sync)
+    if (bytes > c->noalloc_host.size())
+      throw Fail{JK_ENOMEM, "jk_build_noalloc: host staging of " + std::to_string(bytes) +
+                                " bytes is over its " + std::to_string(kNoAllocHostBytes) + " bytes"};
+    return c->noalloc_host.data();
+  }
   if (c->host_pinned_bytes < bytes) {
     if (c->host_pinned) HIP_OK(hipHostFree(c->host_pinned));
     c->host_pinned = nullptr;
@@ -961,6 +989,7 @@ std::vector<char> setup_key(const jk_ctx* c, const jk_basis* b, double tol, cons
 Setup get_setup(jk_ctx* c, const jk_basis* b, double tol, const jk_opts& o, hipStream_t s,
                 bool grad, bool* reused) {
   *reused = false;
+  if (c->noalloc) return setup(c, b, tol, o, s, grad);   // buffers of this call only
   std::vector<char> key;
   if (o.reuse_setup == 1) {
     key = setup_key(c, b, tol, o, grad);
@@ -1168,6 +1197,8 @@ int jk_ctx_create(jk_ctx** out, int device) {
     std::vector<float> t32;
     make_boys_tables(t64, t32);
     HIP_OK(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device));
+    HIP_OK(hipGetSymbolAddress(reinterpret_cast<void**>(&c->noalloc_base), HIP_SYMBOL(scratch)));
+    c->noalloc_host.assign(kNoAllocHostBytes, 0);
     c->ws_budget = kWsBudget;
     if (c->num_cu < 1) c->num_cu = 1;
     HIP_OK(hipMalloc(&c->boys64, t64.size() * sizeof(double)));
@@ -1246,7 +1277,8 @@ int build_impl(jk_ctx* c, const jk_basis* basis, const double* D, double* J, dou
     const size_t words = det ? 2 : 1;
     int ncopy = o.acc_copies;
     if (ncopy == 0) {
-      ncopy = static_cast<int>(std::min<size_t>(kMaxCopies, kAccBudget / (2 * words * mat * sizeof(double))));
+      const size_t acc_budget = c->noalloc ? kNoAllocBytes / 8 : kAccBudget;
+      ncopy = static_cast<int>(std::min<size_t>(kMaxCopies, acc_budget / (2 * words * mat * sizeof(double))));
       if (c->scratch_limit)
         ncopy = std::min<int>(ncopy, static_cast<int>(c->scratch_limit / 4 / (2 * words * mat * sizeof(double))));
       ncopy = std::max(ncopy, 1);
@@ -1330,6 +1362,26 @@ extern "C" {
 int jk_build(jk_ctx* c, const jk_basis* basis, const double* D, double* J, double* K, double tol,
              const jk_opts* opts, void* hip_stream) {
   return build_impl(c, basis, D, J, K, tol, opts, hip_stream);
+}
+
+int jk_build_noalloc(jk_ctx* c, const jk_basis* basis, const double* D, double* J, double* K,
+                     double tol, const jk_opts* opts, void* hip_stream) {
+  if (!c) return JK_EINVAL;
+  if (opts && opts->timing) {
+    c->err = "jk_build_noalloc: timing events are created on demand; use timing = 0";
+    return JK_EUNSUPPORTED;
+  }
+  if (!c->noalloc_base) {
+    c->err = "jk_build_noalloc: no static scratch on this context's device";
+    return JK_EHIP;
+  }
+  c->noalloc = true;
+  c->noalloc_off = 0;
+  c->ws_budget = kNoAllocBytes / 4;   // multi-pass workspaces take at most a quarter
+  const int rc = build_impl(c, basis, D, J, K, tol, opts, hip_stream);
+  c->noalloc = false;
+  c->ws_budget = kWsBudget;
+  return rc;
 }
 
 int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, double tol,

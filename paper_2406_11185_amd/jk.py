@@ -1,8 +1,8 @@
 """ctypes binding of libjk.so (argument marshalling only).
 
 The names mirror the C ABI in include/jk.h: jk_opts_default, jk_ctx_create,
-jk_ctx_destroy, jk_validate_basis, jk_build, jk_grad, jk_get_stats,
-jk_last_error.  All arithmetic runs in the library's HIP kernels; PyTorch only
+jk_ctx_destroy, jk_validate_basis, jk_build, jk_build_noalloc, jk_grad,
+jk_get_stats, jk_last_error.  All arithmetic runs in the library's HIP kernels; PyTorch only
 supplies device memory and the current stream.  If libjk.so is missing the
 import fails loudly -- there is no CPU fallback.
 """
@@ -23,7 +23,7 @@ JK_MAX_NDM = 16
 ERR_NAMES = {1: "JK_EINVAL", 2: "JK_EUNSUPPORTED", 3: "JK_ENOMEM", 4: "JK_EHIP"}
 
 EXPORTS = ["jk_opts_default", "jk_ctx_create", "jk_ctx_destroy", "jk_validate_basis", "jk_build",
-           "jk_grad", "jk_get_stats", "jk_last_error"]
+           "jk_build_noalloc", "jk_grad", "jk_get_stats", "jk_last_error"]
 
 
 class JkError(RuntimeError):
@@ -83,6 +83,7 @@ def load():
     lib.jk_validate_basis.argtypes = [ctypes.POINTER(jk_basis), ctypes.POINTER(ctypes.c_int32)]
     lib.jk_build.argtypes = [vp, ctypes.POINTER(jk_basis), vp, vp, vp, ctypes.c_double,
                              ctypes.POINTER(jk_opts), vp]
+    lib.jk_build_noalloc.argtypes = lib.jk_build.argtypes
     lib.jk_grad.argtypes = [vp, ctypes.POINTER(jk_basis), vp, vp, ctypes.c_double,
                             ctypes.POINTER(jk_opts), vp]
     lib.jk_get_stats.argtypes = [vp, ctypes.POINTER(jk_stats)]
@@ -217,6 +218,17 @@ def jk_build(ctx: Context, basis: Basis, D, J, K, tol: float, opts: jk_opts | No
     rc = load().jk_build(ctx.h, ctypes.byref(basis.c), ctypes.c_void_p(D.data_ptr()),
                          ctypes.c_void_p(J.data_ptr()), ctypes.c_void_p(K.data_ptr()),
                          float(tol), ctypes.byref(opts) if opts is not None else None, s)
+    ctx._check(rc)
+
+
+def jk_build_noalloc(ctx: Context, basis: Basis, D, J, K, tol: float,
+                     opts: jk_opts | None = None, stream=None) -> None:
+    """jk_build without any allocation in the call (static device scratch)."""
+    import torch
+    s = stream if stream is not None else _stream_ptr(torch, D.device)
+    rc = load().jk_build_noalloc(ctx.h, ctypes.byref(basis.c), ctypes.c_void_p(D.data_ptr()),
+                                 ctypes.c_void_p(J.data_ptr()), ctypes.c_void_p(K.data_ptr()),
+                                 float(tol), ctypes.byref(opts) if opts is not None else None, s)
     ctx._check(rc)
 
 
