@@ -297,6 +297,10 @@ class HRR(Code):
 # wavefronts per SIMD make the FP32 kernels of these classes 20-35 % faster; the
 # FP64 ones, which spill at that budget, lose.)
 CLASS_WAVES = {(name, 4): 2 for name in ("pppp", "dspp", "dsds", "dpps", "dpds", "ddps")}
+# FP32 multi-pass kernels at two wavefronts per SIMD (256 registers; measured on
+# gfx950 at 1080 functions: (dp|dp) 134 -> 100 ms, (dd|pp) 61 -> 53 ms, (dd|dd)
+# 15 -> 13 ms; (dd|ds) and (dd|dp), which spill more at that budget, lose).
+CLASS_WAVES.update({(name, 4): 2 for name in ("dpdp_f32", "ddpp_f32", "dddd_f32")})
 
 
 def class_waves(name, size, split=False):

@@ -121,6 +121,15 @@ struct LaneArr {
   __device__ __forceinline__ T& operator[](int i) const { return p[static_cast<size_t>(i) * S]; }
 };
 
+// The same pointer, opaque to the optimiser: element addresses derived from it
+// are formed where they are used instead of being hoisted out of the loop and
+// held (or spilled) across it.
+template <typename T>
+__device__ __forceinline__ T* opaque(T* p) {
+  asm volatile("" : "+v"(p));
+  return p;
+}
+
 template <typename T>
 struct VrrCoef {
   T PAx, PAy, PAz, WPx, WPy, WPz, QCx, QCy, QCz, WQx, WQy, WQz;
@@ -1220,8 +1229,7 @@ void eri_jk_split_kernel(const EriLaunch a) {
   using AT = LaneArr<T, QPW>;
   using AD = LaneArr<double, kWave>;
   char* wbase = static_cast<char*>(a.ws) + static_cast<size_t>(wave) * split_wave_bytes<C, T>(G);
-  const AT cacc{reinterpret_cast<T*>(wbase) + ql};
-  const AT X{cacc.p + static_cast<size_t>(C::NACC) * QPW};
+  T* const cacc0 = reinterpret_cast<T*>(wbase) + ql;
   // FP64 K partial blocks of every lane (the G lanes of a quartet split its
   // (c, d) loop) and the J_cd block of every quartet slot
   double* const kw0 = reinterpret_cast<double*>(wbase + static_cast<size_t>(QPW) * NT * sizeof(T));
@@ -1230,8 +1238,6 @@ void eri_jk_split_kernel(const EriLaunch a) {
   double* const kbc0 = kad0 + C::NA * C::ND * kWave;
   double* const kbd0 = kbc0 + C::NB * C::NC * kWave;
   double* const jcd0 = kbd0 + C::NB * C::ND * kWave;
-  const AD kac{kac0 + lane}, kad{kad0 + lane}, kbc{kbc0 + lane}, kbd{kbd0 + lane};
-  const LaneArr<double, QPW> jcdw{jcd0 + ql};
   const int z = 0;
   const int nb = a.bra.n, nk = a.ket.n;
   const size_t n = static_cast<size_t>(a.n);
@@ -1247,6 +1253,14 @@ void eri_jk_split_kernel(const EriLaunch a) {
   const double fbra = a.bra.fpair[i];
 
   for (int kc = kbeg; kc < kend; kc += QPW) {
+    // the workspace arrays, re-derived per ket step through opaque(): their
+    // hundreds of element addresses are then formed at each use rather than
+    // kept live across the loop, which spilled them to scratch
+    const AT cacc{opaque(cacc0)};
+    const AT X{opaque(cacc0 + static_cast<size_t>(C::NACC) * QPW)};
+    const AD kac{opaque(kac0 + lane)}, kad{opaque(kad0 + lane)}, kbc{opaque(kbc0 + lane)},
+        kbd{opaque(kbd0 + lane)};
+    const LaneArr<double, QPW> jcdw{opaque(jcd0 + ql)};
     const bool inrange = kc + ql < kend;
     const bool active = inrange && sub == 0;
     const int k = inrange ? kc + ql : kend - 1;
