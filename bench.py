@@ -357,6 +357,8 @@ def main():
     for _ in range(args.warmup):
         jkb.jk_build(ctx, basis, D, J, K, tol, opts)
     torch.cuda.synchronize()
+    if args.warmup:
+        progress(f"{args.warmup} warmup {precision} builds done")
     total, stats = run_steps(jkb, ctx, basis, D, J, K, tol, opts, args.steps, torch)
     progress(f"{args.steps} timed {precision} builds done")
     ms_per_step = 1e3 * total / args.steps

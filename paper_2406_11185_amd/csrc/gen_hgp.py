@@ -338,11 +338,20 @@ def uses_rows(name, size):
     return f"{name}:{size}" in ROWS_CLASSES
 
 
+# Of those, the classes that also take the row buffer with several densities (one
+# launch per density, the integrals recomputed each time): FP32 classes whose
+# integrals cost less than the per-density scatter of the other kernel.  (Measured
+# on gfx950 at 1800 functions and 10 densities: (ss|ss) 2.76 -> 1.24 s, (ps|ss)
+# 8.65 -> 5.36 s, (ps|ps) 8.77 -> 7.47 s; (pp|ss) and (ds|ss) lose 9-12 %.)
+ROWS_MULTI_CLASSES = {"ssss:4", "psss:4", "psps:4"}
+
+
 def rows_call(name, t):
     size = 8 if t == "double" else 4
     if not uses_rows(name, size):
         return "false"
-    return f"launch_rows<Cls_{name}, {t}, {ROWS_BLOCK}>(a, s)"
+    multi = "true" if f"{name}:{size}" in ROWS_MULTI_CLASSES else "false"
+    return f"launch_rows<Cls_{name}, {t}, {ROWS_BLOCK}, {multi}>(a, s)"
 
 # Single-pass classes whose kernels digest in five sweeps (one J/K block each).
 # JK_SWEEPS_OVERRIDE=1 turns sweeps on for every class above LDS_MAX_L, for

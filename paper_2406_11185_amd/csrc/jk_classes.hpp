@@ -17,12 +17,21 @@ inline void launch_kernel(void (*k)(P...), dim3 grid, dim3 block, size_t lds, hi
   (void)hipLaunchKernel(reinterpret_cast<const void*>(k), grid, block, argv, lds, s);
 }
 
+// Work-item counter back to zero between launches that share it.
+template <int U>
+__global__ void zero_counter_kernel(int* p) {
+  if (threadIdx.x == 0) *p = U;
+}
+
 // Light class with the bra's exchange rows in LDS (eri_jk_rows_kernel): launched
 // if its static and dynamic LDS fit one workgroup on the device, else false and
 // nothing is launched.  The kernel attributes are read once per instantiation
-// (one device per process).
-template <class C, typename T, int NT>
+// (one device per process).  Several densities (MULTI): one launch per density,
+// each recomputing the integrals, since the LDS holds one density's rows; for
+// classes whose integrals cost less than the per-density scatter they replace.
+template <class C, typename T, int NT, bool MULTI>
 bool launch_rows(const EriLaunch& a, hipStream_t s) {
+  if (a.n_dm > 1 && !MULTI) return false;
   static size_t static_bytes = 0;
   static int max_lds = -1;
   const void* k = reinterpret_cast<const void*>(&eri_jk_rows_kernel<C, T, NT>);
@@ -45,7 +54,21 @@ bool launch_rows(const EriLaunch& a, hipStream_t s) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, NT, dyn) != hipSuccess || nb < 1) nb = 1;
   (void)hipGetLastError();
   const dim3 grid(static_cast<unsigned>(std::min(a.nitems, nb * a.num_cu)));
-  launch_kernel(&eri_jk_rows_kernel<C, T, NT>, grid, dim3(NT), dyn, s, a.dry != 0, a);
+  if (a.n_dm == 1) {
+    launch_kernel(&eri_jk_rows_kernel<C, T, NT>, grid, dim3(NT), dyn, s, a.dry != 0, a);
+    return true;
+  }
+  EriLaunch b = a;   // density m: D, J, K (and their accumulator copies) at m n^2
+  b.n_dm = 1;
+  const size_t nn = static_cast<size_t>(a.n) * a.n;
+  for (int m = 0; m < a.n_dm; ++m) {
+    b.D = a.D + m * nn;
+    b.J = a.J + m * nn;
+    b.K = a.K + m * nn;
+    if (m > 0 && !a.dry) hipLaunchKernelGGL(zero_counter_kernel<0>, dim3(1), dim3(kWave), 0, s, a.next);
+    launch_kernel(&eri_jk_rows_kernel<C, T, NT>, grid, dim3(NT), dyn, s, a.dry != 0, b);
+    if (a.dry) break;   // the guard's answer is the same for every density
+  }
   return true;
 }
 

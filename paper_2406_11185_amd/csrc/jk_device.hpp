@@ -102,7 +102,7 @@ struct EriLaunch {
                       // accumulators are int64 fixed-point pairs (see atomic_add)
   int dry;            // host only: 1 = check the launch (scratch guard) without launching
   int rows;           // light classes: 1 = the bra's exchange rows may be kept in LDS
-                      // (one density, atomic accumulation), if they fit
+                      // (atomic accumulation), if they fit
 };
 
 // Persistent kernels: each wavefront claims work items one at a time.

@@ -1318,7 +1318,7 @@ int build_impl(jk_ctx* c, const jk_basis* basis, const double* D, double* J, dou
           a.ws = ws[k];
           a.nwaves = waves_of(r).first;
           a.dry = dry ? 1 : 0;
-          a.rows = (o.n_dm == 1 && !det) ? 1 : 0;
+          a.rows = det ? 0 : 1;
           launch_eri(r.cls, r.pr, a, ls);
         },
         [&](const std::vector<LaunchRec>& recs, const std::vector<int>& where) {

@@ -55,3 +55,46 @@ def test_mixed_against_fp64(name):
     assert n32 > n64
     assert abs(EJm - EJ64) <= 1e-6 and abs(EKm - EK64) <= 1e-6
     np.testing.assert_allclose(Jm, Jm.transpose(0, 2, 1), atol=1e-13)
+
+
+def test_mixed_several_densities_match_one_at_a_time():
+    """Several densities in FP32: the light classes take the LDS row buffer once per
+    density (integrals recomputed for each); every density must equal its own
+    one-density build (up to the order of FP64 atomic adds) and the oracle within
+    the all-FP32 bounds above."""
+    import torch
+    from paper_2406_11185_amd import jk as jkb
+    mol = molgen.make_molecule(3, 3, 21, n_dm=3)
+    say(f"case mixed, 3 densities ({mol.n_bf} functions), all FP32")
+    D = torch.as_tensor(mol.D, device="cuda")
+    J, K = jkb.jk(mol, D, 0.0, precision="mixed", fp32_below=1e9)
+    J, K = J.cpu().numpy(), K.cpu().numpy()
+    Jo, Ko, _ = oracle.jk(mol, 0.0)
+    for m in range(3):
+        J1, K1 = jkb.jk(mol, D[m:m + 1].contiguous(), 0.0, precision="mixed", fp32_below=1e9)
+        J1, K1 = J1.cpu().numpy()[0], K1.cpu().numpy()[0]
+        say(f"  density {m}: max|J - J1|={np.abs(J[m] - J1).max():.2e} "
+            f"max|K - K1|={np.abs(K[m] - K1).max():.2e} max|dJ|={np.abs(J[m] - Jo[m]).max():.2e}")
+        assert np.abs(J[m] - J1).max() <= 1e-12 * np.abs(J1).max()
+        assert np.abs(K[m] - K1).max() <= 1e-12 * np.abs(K1).max()
+        assert np.abs(J[m] - Jo[m]).max() <= 1e-6 * np.abs(Jo[m]).max()
+        assert np.abs(K[m] - Ko[m]).max() <= 1e-6 * np.abs(Ko[m]).max()
+
+
+def test_ten_densities_mixed_against_fp64():
+    """The 30-atom molecule with ten seeded densities (the several-density form of the
+    1800-function workload, at a size that runs in a second): mixed against the GPU FP64
+    build, |dE_J|, |dE_K| <= 1e-6 hartree per density, J symmetric."""
+    import torch
+    from paper_2406_11185_amd import jk as jkb
+    w = molgen.WORKLOADS["w30"]
+    mol = molgen.make_molecule(w["n_heavy"], w["n_h"], w["seed"], w["heavy_z"], n_dm=10)
+    say(f"case mixed vs fp64, 10 densities ({mol.n_bf} functions, tol 1e-10)")
+    D = torch.as_tensor(mol.D, device="cuda")
+    J64, K64, E64 = [t.cpu().numpy() for t in jkb.jk(mol, D, 1e-10, energies=True)]
+    Jm, Km, Em = [t.cpu().numpy() for t in jkb.jk(mol, D, 1e-10, precision="mixed", energies=True)]
+    dEJ, dEK = np.abs(Em[:, 0] - E64[:, 0]).max(), np.abs(Em[:, 1] - E64[:, 1]).max()
+    say(f"  max dEJ={dEJ:.2e} dEK={dEK:.2e} max|dJ|={np.abs(Jm - J64).max():.2e} "
+        f"max|dK|={np.abs(Km - K64).max():.2e}")
+    assert dEJ <= 1e-6 and dEK <= 1e-6
+    np.testing.assert_allclose(Jm, Jm.transpose(0, 2, 1), atol=1e-13)
