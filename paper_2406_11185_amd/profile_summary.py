@@ -75,10 +75,12 @@ def stats(args):
              "Command (from the repository root on the GPU box):", "", "```", args.command, "```",
              "", f"Total kernel time over the profiled run: {total:.2f} ms ({len(st)} kernels).  "
              "Class kernels run one at a time (serial launches), so each duration is the "
-             "kernel's own.  Algorithmic TFLOP/s = generated-code flops per quartet x the "
-             "quartets of the class in one build (benchmark line of the same run) / mean "
-             f"duration; fraction of {PEAK} TFLOP/s.", "",
-             "| kernel | calls | total ms | avg ms | % | quartets per call | TFLOP/s | frac |",
+             "kernel's own.  Algorithmic TFLOP/s = generated-code flops per quartet (each "
+             "quartet's integrals once, its digestion once per density) x the quartets of the "
+             "class in one build (benchmark line of the same run) / the kernel's total time "
+             "(a class launched once per density, recomputing its integrals, shows that "
+             f"work as lost rate); fraction of {PEAK} TFLOP/s.", "",
+             "| kernel | calls | total ms | avg ms | % | quartets per build | TFLOP/s | frac |",
              "|---|---|---|---|---|---|---|---|"]
     for name, (calls, tot, avg) in sorted(st.items(), key=lambda kv: -kv[1][1]):
         k = kernel_key(name)
@@ -87,7 +89,7 @@ def stats(args):
             c = bench["classes"].get(f"{k[0]}_{k[1]}")
             if c:
                 qn = c["quartets"]
-                rate = flops_per_quartet(infos[k[0]], n_dm=n_dm) * qn / (avg / 1e3) / 1e12
+                rate = flops_per_quartet(infos[k[0]], n_dm=n_dm) * qn / (tot / 1e3) / 1e12
                 q, tf, fr = str(qn), f"{rate:.1f}", f"{rate / PEAK:.3f}"
         short = re.sub(r"\(.*\)$", "", name).replace("jk::", "").replace("void ", "")
         lines.append(f"| `{short[:90]}` | {calls} | {tot:.3f} | {avg:.4f} | "
