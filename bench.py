@@ -118,7 +118,7 @@ def pmc_summary(fetch_csv: str, write_csv: str, out: str, calib_mib: int, comman
     fs, ws = known / fcopy, known / wcopy
     lines = [f"# HBM traffic per dispatch: J/K build, {title}", "",
              "Two rocprofv3 counter runs of the benchmark (kernels are serialised while counters "
-             "are collected), from the repository root on the GPU box:", "", "```",
+             "are collected), from the repository root, on an MI355X:", "", "```",
              command.replace("PMC", "FETCH_SIZE"), command.replace("PMC", "WRITE_SIZE"), "```", "",
              f"Calibration: the {calib_mib} MiB device-to-device copy made before the steps reads "
              f"FETCH_SIZE = {fcopy:.1f} KiB and WRITE_SIZE = {wcopy:.1f} KiB for {known:.0f} KiB "

@@ -301,6 +301,10 @@ CLASS_WAVES = {(name, 4): 2 for name in ("pppp", "dspp", "dsds", "dpps", "dpds",
 # gfx950 at 1080 functions: (dp|dp) 134 -> 100 ms, (dd|pp) 61 -> 53 ms, (dd|dd)
 # 15 -> 13 ms; (dd|ds) and (dd|dp), which spill more at that budget, lose).
 CLASS_WAVES.update({(name, 4): 2 for name in ("dpdp_f32", "ddpp_f32", "dddd_f32")})
+# FP64 multi-pass (dp|pp) and (dp|dp) at two wavefronts per SIMD (measured on gfx950
+# at 1080 functions, FP64 build: 381 -> 365 ms and 265 -> 234 ms; the other FP64
+# multi-pass classes lose, up to 2.2x for (dd|ds)).
+CLASS_WAVES.update({(name, 8): 2 for name in ("dppp", "dpdp")})
 
 
 def class_waves(name, size, split=False):

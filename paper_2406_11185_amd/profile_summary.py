@@ -72,7 +72,7 @@ def stats(args):
     n_dm = bench["config"]["n_dm"]
     total = sum(v[1] for v in st.values())
     lines = [f"# rocprofv3 kernel statistics: {args.title}", "",
-             "Command (from the repository root on the GPU box):", "", "```", args.command, "```",
+             "Command (from the repository root, on an MI355X):", "", "```", args.command, "```",
              "", f"Total kernel time over the profiled run: {total:.2f} ms ({len(st)} kernels).  "
              "Class kernels run one at a time (serial launches), so each duration is the "
              "kernel's own.  Algorithmic TFLOP/s = generated-code flops per quartet (each "
