@@ -61,23 +61,19 @@ def flops_per_quartet(info, npp_b=9, npp_k=9, n_dm=1):
             + info["hrr_flops"] + n_dm * info["digest_flops"])
 
 
-FINGERPRINT_SOURCES = ["paper_2406_11185_amd/csrc/gen_hgp.py", "paper_2406_11185_amd/csrc/jk_device.hpp",
-                       "paper_2406_11185_amd/csrc/jk_host.hip", "paper_2406_11185_amd/csrc/jk_classes.hpp"]
-
-
 def traffic_file(workload, precision):
     return os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{precision}.md")
 
 
+def atomics_file(workload, precision):
+    return os.path.join(ROOT, "profiles", f"valu_atomics_{workload}_{precision}.md")
+
+
 def source_fingerprint() -> str:
-    """Hash of the sources that decide the J/K kernels' code: counter data taken
-    with another fingerprint describe other kernels."""
-    import hashlib
-    h = hashlib.sha256()
-    for rel in FINGERPRINT_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    """Hash of the sources that decide the J/K kernels' code (counter data taken
+    with another fingerprint describe other kernels)."""
+    from paper_2406_11185_amd.profile_summary import source_fingerprint as fp
+    return fp()
 
 
 def kernel_key(name: str):
@@ -154,6 +150,24 @@ def traffic_of(kernel: str, workload: str, precision: str):
         cells = [c.strip() for c in ln.strip().strip("|").split("|")]
         if len(cells) == 7 and cells[0] == kernel:
             return float(cells[6]) * 1e6
+    return None
+
+
+def counters_of(kernel: str, workload: str, precision: str):
+    """(memory-side atomics per screened quartet, counter VALU fraction of peak) of
+    `kernel` from the committed counter summary, or None if there is none or the
+    kernel sources changed since it was taken."""
+    try:
+        with open(atomics_file(workload, precision)) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    if f"source fingerprint: `{source_fingerprint()}`" not in text:
+        return None
+    for ln in text.splitlines():
+        cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+        if len(cells) == 10 and cells[0].split(" (")[0] == kernel:
+            return float(cells[8]), float(cells[7])
     return None
 
 
@@ -385,6 +399,11 @@ def main():
             "frac": achieved / peak, "traffic": traffic_of(kname, args.workload, precision),
             "kernel": kname, "flops_per_launch": flops_launch, "mean_launch_ms": mean_s * 1e3,
             "launches": nlaunch}
+    cn = counters_of(kname, args.workload, precision)
+    if cn:
+        # FETCH_SIZE / WRITE_SIZE of these kernels are mostly memory-side FP64 atomics
+        roof["memory_side_atomics_per_launch"] = cn[0] * nq / nlaunch
+        roof["counter_valu_frac"] = cn[1]
     if prd == 1:
         roof["peak_packed_fp32"] = FP32_PACKED_PEAK_TFLOPS
         roof["frac_of_packed_fp32"] = achieved / FP32_PACKED_PEAK_TFLOPS

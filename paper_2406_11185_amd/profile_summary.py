@@ -23,7 +23,20 @@ import re
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
 PEAK = 78.6   # TFLOP/s: FP64 vector, and FP32 without packed instructions
+FINGERPRINT_SOURCES = ["paper_2406_11185_amd/csrc/gen_hgp.py", "paper_2406_11185_amd/csrc/jk_device.hpp",
+                       "paper_2406_11185_amd/csrc/jk_host.hip", "paper_2406_11185_amd/csrc/jk_classes.hpp"]
+
+
+def source_fingerprint() -> str:
+    """Hash of the sources that decide the J/K kernels' code and launches."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in FINGERPRINT_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def class_infos():
@@ -133,7 +146,7 @@ def valu(args):
              f"kernel-statistics run; fractions of {PEAK} TFLOP/s.  Atomics: TCC_EA0_ATOMIC, the "
              "atomic requests the L2 forwards to the memory side (device-scope atomics on this "
              "chip are all executed there; TCC_ATOMIC reads the same), per screened quartet and "
-             "per second.", "",
+             "per second.", "", f"source fingerprint: `{source_fingerprint()}`", "",
              "| kernel | counter GFLOP fp64 | counter GFLOP fp32 | algorithmic GFLOP | "
              "counter / algorithmic | counter TFLOP/s | algorithmic TFLOP/s | frac (counter) | "
              "atomics per quartet | atomic G/s |",
