@@ -98,3 +98,27 @@ def test_ten_densities_mixed_against_fp64():
         f"max|dK|={np.abs(Km - K64).max():.2e}")
     assert dEJ <= 1e-6 and dEK <= 1e-6
     np.testing.assert_allclose(Jm, Jm.transpose(0, 2, 1), atol=1e-13)
+
+
+def test_ten_densities_in_place_mixed_against_oracle():
+    """The ten-density, one-accumulator-copy path the 1800-function workload takes
+    (J and K are the accumulators, finalized in place), mixed precision inside the
+    dispatcher's envelope, against the oracle: |dE_J|, |dE_K| <= 1e-6 hartree per
+    density and every element within 1e-6 of the largest."""
+    import torch
+    from paper_2406_11185_amd import jk as jkb
+    mol = molgen.make_molecule(6, 8, 21, n_dm=10)   # 130 functions, a quarter in FP32
+    say(f"case mixed, 10 densities, one accumulator copy ({mol.n_bf} functions, tol 1e-10)")
+    D = torch.as_tensor(mol.D, device="cuda")
+    J, K, E = [t.cpu().numpy() for t in
+               jkb.jk(mol, D, 1e-10, precision="mixed", energies=True, acc_copies=1)]
+    st = jkb.default_context(0).stats()
+    assert sum(st.quartets_fp32) > 0 and sum(st.quartets_fp64) > 0
+    Jo, Ko, _ = oracle.jk(mol, 1e-10)
+    EJo, EKo = oracle.energy(Jo, Ko, mol.D)
+    dEJ, dEK = np.abs(E[:, 0] - EJo).max(), np.abs(E[:, 1] - EKo).max()
+    say(f"  max dEJ={dEJ:.2e} dEK={dEK:.2e} max|dJ|={np.abs(J - Jo).max():.2e} "
+        f"max|dK|={np.abs(K - Ko).max():.2e}")
+    assert dEJ <= 1e-6 and dEK <= 1e-6
+    assert np.abs(J - Jo).max() <= 1e-6 * np.abs(Jo).max()
+    assert np.abs(K - Ko).max() <= 1e-6 * np.abs(Ko).max()
