@@ -56,6 +56,24 @@ def test_ragged_contraction_lengths(nh, nH, seed, tol):
     assert np.abs(K - Ko).max() <= TOL_ABS
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_single_atom_boys_at_zero(precision):
+    """Degenerate geometry: one atom carries every shell, so every Gaussian product
+    centre coincides (A = B = P = Q) and every Boys argument is exactly 0; all
+    classes, FP64 and (every quartet) FP32, against the oracle."""
+    mol = molgen.make_molecule(1, 0, 13)
+    say(f"case one atom ({mol.n_bf} functions, tol 0, {precision})")
+    import torch
+    from paper_2406_11185_amd import jk as jkb
+    D = torch.as_tensor(mol.D, device="cuda")
+    J, K = jkb.jk(mol, D, 0.0, precision=precision, fp32_below=1e9)
+    J, K = J.cpu().numpy(), K.cpu().numpy()
+    Jo, Ko, _ = oracle.jk(mol, 0.0)
+    say("  max|dJ| =", np.abs(J - Jo).max(), " max|dK| =", np.abs(K - Ko).max())
+    bound = TOL_ABS if precision == "fp64" else 1e-6 * max(np.abs(Jo).max(), np.abs(Ko).max())
+    assert np.abs(J - Jo).max() <= bound and np.abs(K - Ko).max() <= bound
+
+
 def test_multiple_densities_share_one_pass():
     mol = molgen.make_molecule(2, 2, 11, n_dm=3)
     say(f"case n_dm=3 ({mol.n_bf} functions)")
