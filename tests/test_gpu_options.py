@@ -160,3 +160,17 @@ def test_setup_reuse_across_calls():
     assert build(ctx, D2, 1e-9, True, jkb.Basis(mol3))[2] == 0   # an exponent changed
     assert build(ctx, D2, 1e-9, False)[2] == 0         # no reuse asked: set up again
     assert build(ctx, D2, 1e-9, True)[2] == 0          # ... which replaced the kept setup
+
+
+def test_largest_density_count():
+    """n_dm = 16, the most the library accepts (JK_MAX_NDM), against the oracle; the
+    mixed path with every quartet in FP32 takes the per-density row-buffer launches."""
+    mol = molgen.make_molecule(2, 2, 11, n_dm=16)
+    say(f"case 16 densities ({mol.n_bf} functions, tol 0)")
+    J, K = _run(mol, 0.0)
+    Jo, Ko, _ = oracle.jk(mol, 0.0)
+    say("  max|dJ| =", np.abs(J - Jo).max(), " max|dK| =", np.abs(K - Ko).max())
+    assert np.abs(J - Jo).max() <= TOL_ABS and np.abs(K - Ko).max() <= TOL_ABS
+    J, K = _run(mol, 0.0, precision="mixed", fp32_below=1e9)
+    assert np.abs(J - Jo).max() <= 1e-6 * np.abs(Jo).max()
+    assert np.abs(K - Ko).max() <= 1e-6 * np.abs(Ko).max()
