@@ -67,3 +67,26 @@ def test_noalloc_rejects_what_does_not_fit():
         jkb.jk_build_noalloc(ctx, b, D, J, K, 1e-10, jkb.make_opts(timing=True))
     assert e.value.code == jkb.JK_EUNSUPPORTED
     ctx.close()
+
+
+def test_noalloc_leaves_the_kept_setup_alone():
+    """A jk_build_noalloc call between two reuse_setup builds on one context sets up in
+    the static array only: the second build still reuses the kept setup, and all three
+    agree bit for bit (deterministic mode)."""
+    import torch
+    from paper_2406_11185_amd import jk as jkb
+    mol = molgen.make_molecule(4, 5, 5)
+    say(f"case noalloc between reuse_setup builds ({mol.n_bf} functions, tol 1e-8)")
+    ctx = jkb.Context(0)
+    b = jkb.Basis(mol)
+    D = torch.as_tensor(np.ascontiguousarray(mol.D), device="cuda")
+    outs = []
+    for call in (jkb.jk_build, jkb.jk_build_noalloc, jkb.jk_build):
+        J, K = torch.empty_like(D), torch.empty_like(D)
+        call(ctx, b, D, J, K, 1e-8, jkb.make_opts(deterministic=1, reuse_setup=True))
+        torch.cuda.synchronize()
+        outs.append((J.cpu().numpy(), K.cpu().numpy(), ctx.stats().setup_reused))
+    assert outs[0][2] == 0 and outs[2][2] == 1
+    for J, K, _ in outs[1:]:
+        assert np.array_equal(J, outs[0][0]) and np.array_equal(K, outs[0][1])
+    ctx.close()
