@@ -32,7 +32,8 @@ def test_oracle_under_address_and_undefined_sanitizers(tmp_path):
 
 HIPCC = "/opt/rocm/bin/hipcc"
 HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
-            "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+            "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer",
+            "-Xarch_host", "-fsanitize-ignorelist=" + os.path.join(HERE, "sanitize", "ubsan_ignore.txt")]
 
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="needs hipcc")
