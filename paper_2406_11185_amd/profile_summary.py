@@ -83,6 +83,7 @@ def stats(args):
     bench = load_bench(args.bench)
     infos = class_infos()
     n_dm = bench["config"]["n_dm"]
+    builds = bench["warmup"] + bench["steps"]   # builds in the profiled run (no extra legs)
     total = sum(v[1] for v in st.values())
     lines = [f"# rocprofv3 kernel statistics: {args.title}", "",
              "Command (from the repository root, on an MI355X):", "", "```", args.command, "```",
@@ -90,7 +91,8 @@ def stats(args):
              "Class kernels run one at a time (serial launches), so each duration is the "
              "kernel's own.  Algorithmic TFLOP/s = generated-code flops per quartet (each "
              "quartet's integrals once, its digestion once per density) x the quartets of the "
-             "class in one build (benchmark line of the same run) / the kernel's total time "
+             "class in one build (benchmark line of the same run) x the builds of the run / the "
+             "kernel's total time "
              "(a class launched once per density, recomputing its integrals, shows that "
              f"work as lost rate); fraction of {PEAK} TFLOP/s.", "",
              "| kernel | calls | total ms | avg ms | % | quartets per build | TFLOP/s | frac |",
@@ -102,7 +104,7 @@ def stats(args):
             c = bench["classes"].get(f"{k[0]}_{k[1]}")
             if c:
                 qn = c["quartets"]
-                rate = flops_per_quartet(infos[k[0]], n_dm=n_dm) * qn / (tot / 1e3) / 1e12
+                rate = flops_per_quartet(infos[k[0]], n_dm=n_dm) * qn * builds / (tot / 1e3) / 1e12
                 q, tf, fr = str(qn), f"{rate:.1f}", f"{rate / PEAK:.3f}"
         short = re.sub(r"\(.*\)$", "", name).replace("jk::", "").replace("void ", "")
         lines.append(f"| `{short[:90]}` | {calls} | {tot:.3f} | {avg:.4f} | "
