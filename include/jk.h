@@ -110,7 +110,10 @@ typedef struct {
                                  the basis (every array element), tol, precision and
                                  fp32_below are unchanged (D may change, as between SCF
                                  iterations); any call that sets them up again replaces
-                                 the kept ones.  0 (default): set up on every call.      */
+                                 the kept ones.  They are written on the stream of the
+                                 call that made them: a call on another stream must be
+                                 ordered after that call by the caller.  0 (default):
+                                 set up on every call.                                   */
   double* energy;             /* jk_build, optional (NULL = not written): DEVICE pointer to
                                  [n_dm][3] receiving E_J = 1/2 tr(D J), E_K = 1/4 tr(D K)
                                  and E = E_J - E_K, summed in a fixed order             */
