@@ -7,7 +7,8 @@ function, plain digestion); this module only marshals numpy arrays.
 
 Parity status of each entry point (what pins it is listed in the tests):
   boys, prim_eri, shell_quartet, schwarz, jk, jk_blocks, jk_bra_sample, grad,
-  screen_counts  -- pinned
+  screen_counts  -- pinned (the erf(omega r12)/r12 form of prim_eri, shell_quartet,
+  jk and jk_blocks as well)
 """
 from __future__ import annotations
 
@@ -38,6 +39,9 @@ def _load():
     lib.orc_boys.argtypes = [ctypes.c_int, ctypes.c_double, _dp]
     lib.orc_prim_eri.restype = ctypes.c_double
     lib.orc_prim_eri.argtypes = [_ip, ctypes.c_double, _dp] * 4
+    lib.orc_prim_eri_omega.restype = ctypes.c_double
+    lib.orc_prim_eri_omega.argtypes = [_ip, ctypes.c_double, _dp] * 4 + [ctypes.c_double]
+    lib.orc_basis_set_omega.argtypes = [ctypes.c_void_p, ctypes.c_double]
     lib.orc_shell_quartet.argtypes = [ctypes.c_void_p] + [ctypes.c_int] * 4 + [_dp]
     lib.orc_schwarz.argtypes = [ctypes.c_void_p, _dp]
     lib.orc_jk.restype = ctypes.c_longlong
@@ -78,9 +82,10 @@ def ncart(l):
 
 
 class Basis:
-    """Oracle-side copy of a basis (any object with the molgen.Molecule fields)."""
+    """Oracle-side copy of a basis (any object with the molgen.Molecule fields).
+    omega > 0: its integrals are those of erf(omega r12)/r12."""
 
-    def __init__(self, mol):
+    def __init__(self, mol, omega: float = 0.0):
         lib = _load()
         self._keep = [_d(mol.xyz), _i(mol.shell_atom), _i(mol.shell_l), _i(mol.shell_nprim),
                       _i(mol.shell_prim0), _d(mol.exps), _d(mol.coefs)]
@@ -90,6 +95,8 @@ class Basis:
         self.n_bf = int(sum(ncart(int(l)) for l in sl))
         self.h = lib.orc_basis_new(self.n_atoms, _pd(x), sl.shape[0], _pi(sa), _pi(sl), _pi(sn),
                                    _pi(sp), _pd(e), _pd(c))
+        if omega and lib.orc_basis_set_omega(self.h, float(omega)) != 0:
+            raise ValueError("omega must be finite and >= 0")
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -104,14 +111,17 @@ def boys(nmax: int, T: float) -> np.ndarray:
     return F
 
 
-def prim_eri(pa, a, A, pb, b, B, pc, c, C, pd, d, D) -> float:
-    """Primitive integral with unit coefficients for Cartesian powers pa..pd."""
+def prim_eri(pa, a, A, pb, b, B, pc, c, C, pd, d, D, omega: float = 0.0) -> float:
+    """Primitive integral with unit coefficients for Cartesian powers pa..pd
+    (omega > 0: of erf(omega r12)/r12)."""
     keep = []
     args = []
     for p, e, X in ((pa, a, A), (pb, b, B), (pc, c, C), (pd, d, D)):
         pp, XX = _i(p), _d(X)
         keep += [pp, XX]
         args += [_pi(pp), float(e), _pd(XX)]
+    if omega:
+        return float(_load().orc_prim_eri_omega(*args, float(omega)))
     return float(_load().orc_prim_eri(*args))
 
 
@@ -137,9 +147,10 @@ def _dm(D):
     return np.ascontiguousarray(D)
 
 
-def jk(mol, tol: float, D=None, nthreads: int = 0):
-    """Full J, K ([n_dm][n][n]) and the number of quartets kept by screening."""
-    b = Basis(mol)
+def jk(mol, tol: float, D=None, nthreads: int = 0, omega: float = 0.0):
+    """Full J, K ([n_dm][n][n]) and the number of quartets kept by screening
+    (omega > 0: of erf(omega r12)/r12, screened with the 1/r12 bounds)."""
+    b = Basis(mol, omega)
     D = _dm(mol.D if D is None else D)
     J = np.zeros_like(D)
     K = np.zeros_like(D)
@@ -147,9 +158,9 @@ def jk(mol, tol: float, D=None, nthreads: int = 0):
     return J, K, int(kept)
 
 
-def jk_blocks(mol, tol: float, pairs, D=None, nthreads: int = 0):
+def jk_blocks(mol, tol: float, pairs, D=None, nthreads: int = 0, omega: float = 0.0):
     """J and K blocks of the shell pairs (M, N) by the plain definitions."""
-    b = Basis(mol)
+    b = Basis(mol, omega)
     D = _dm(mol.D if D is None else D)
     sM = _i([p[0] for p in pairs])
     sN = _i([p[1] for p in pairs])
@@ -167,12 +178,14 @@ def jk_blocks(mol, tol: float, pairs, D=None, nthreads: int = 0):
     return out
 
 
-def grad(mol, tol: float, D=None, nthreads: int = 0, bra_pairs: int = -1, atoms=None):
+def grad(mol, tol: float, D=None, nthreads: int = 0, bra_pairs: int = -1, atoms=None,
+         omega: float = 0.0):
     """dE/dR ([n_dm][n_atoms][3]) of E = 1/2 tr(DJ) - 1/4 tr(DK) at fixed D.
 
     atoms: optional list of atom indices; only their rows are computed (exactly),
-    the other rows are left zero."""
-    b = Basis(mol)
+    the other rows are left zero.  Only the 1/r12 operator (omega = 0) has a
+    gradient here; omega > 0 raises ValueError."""
+    b = Basis(mol, omega)
     D = _dm(mol.D if D is None else D)
     G = np.zeros((D.shape[0], b.n_atoms, 3))
     sel = None
@@ -182,7 +195,7 @@ def grad(mol, tol: float, D=None, nthreads: int = 0, bra_pairs: int = -1, atoms=
     rc = _load().orc_grad(b.h, D.shape[0], _pd(D), float(tol), _pd(G), nthreads, bra_pairs,
                           _pi(sel) if sel is not None else None)
     if rc != 0:
-        raise ValueError("oracle gradient: unsupported number of densities")
+        raise ValueError("oracle gradient: unsupported number of densities or omega")
     return G
 
 

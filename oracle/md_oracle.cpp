@@ -138,8 +138,12 @@ struct PrimQuartet {
   Herm1D Eb[3], Ek[3];
   HermR R;
   double pref;
+  // omega > 0: the long-range operator erf(omega r12)/r12 instead of 1/r12.  Its
+  // Hermite integrals are those of 1/r12 with rho replaced by
+  // rho_w = rho omega^2/(omega^2 + rho), times sqrt(rho_w/rho) (the Fourier
+  // transform of erf(omega r)/r is that of 1/r times exp(-k^2/(4 omega^2))).
   void build(const int lmax[4], double a, const double* A, double b, const double* B,
-             double c, const double* C, double d, const double* D) {
+             double c, const double* C, double d, const double* D, double omega = 0.0) {
     const double p = a + b, q = c + d;
     double P[3], Q[3];
     for (int k = 0; k < 3; ++k) {
@@ -149,8 +153,10 @@ struct PrimQuartet {
       Ek[k].build(lmax[2], lmax[3], c, d, C[k], D[k]);
     }
     const double rho = p * q / (p + q);
-    R.build(lmax[0] + lmax[1] + lmax[2] + lmax[3], rho, P[0] - Q[0], P[1] - Q[1], P[2] - Q[2]);
-    pref = 2.0 * std::pow(kPi, 2.5) / (p * q * std::sqrt(p + q));
+    const double s = omega > 0.0 ? omega * omega / (omega * omega + rho) : 1.0;
+    R.build(lmax[0] + lmax[1] + lmax[2] + lmax[3], rho * s, P[0] - Q[0], P[1] - Q[1],
+            P[2] - Q[2]);
+    pref = 2.0 * std::pow(kPi, 2.5) / (p * q * std::sqrt(p + q)) * std::sqrt(s);
   }
   // (a b | c d) for Cartesian powers pa..pd (each [3]); negative power -> 0.
   double eri(const int* pa, const int* pb, const int* pc, const int* pd) {
@@ -185,6 +191,7 @@ struct PrimQuartet {
 
 struct Basis {
   int n_atoms = 0, n_shells = 0, n_bf = 0;
+  double omega = 0.0;   // > 0: integrals of erf(omega r12)/r12 (screening stays Coulomb)
   std::vector<double> xyz;
   std::vector<int> atom, l, nprim, prim0, bf0;
   std::vector<double> exps, coefs;
@@ -193,7 +200,7 @@ struct Basis {
 
 // Contracted Cartesian block (AB|CD), out[((a*nb+b)*nc+c)*nd+d].
 void shell_quartet(const Basis& bs, int sA, int sB, int sC, int sD, double* out,
-                   PrimQuartet& pq) {
+                   PrimQuartet& pq, double omega) {
   const int sh[4] = {sA, sB, sC, sD};
   int n[4], lmax[4];
   for (int k = 0; k < 4; ++k) { lmax[k] = bs.l[sh[k]]; n[k] = ncart(lmax[k]); }
@@ -209,7 +216,7 @@ void shell_quartet(const Basis& bs, int sA, int sB, int sC, int sD, double* out,
           const int ia = bs.prim0[sA] + i, ib = bs.prim0[sB] + j;
           const int ic = bs.prim0[sC] + k, id = bs.prim0[sD] + m;
           pq.build(lmax, bs.exps[ia], bs.center(sA), bs.exps[ib], bs.center(sB),
-                   bs.exps[ic], bs.center(sC), bs.exps[id], bs.center(sD));
+                   bs.exps[ic], bs.center(sC), bs.exps[id], bs.center(sD), omega);
           const double cc = bs.coefs[ia] * bs.coefs[ib] * bs.coefs[ic] * bs.coefs[id];
           int idx = 0;
           for (int a = 0; a < n[0]; ++a)
@@ -232,7 +239,7 @@ std::vector<double> schwarz(const Basis& bs) {
 #pragma omp for schedule(dynamic)
     for (int A = 0; A < ns; ++A)
       for (int B = 0; B <= A; ++B) {
-        shell_quartet(bs, A, B, A, B, blk.data(), pq);
+        shell_quartet(bs, A, B, A, B, blk.data(), pq, 0.0);   // Coulomb bound
         const int na = ncart(bs.l[A]), nb = ncart(bs.l[B]);
         double mx = 0.0;
         for (int a = 0; a < na; ++a)
@@ -304,10 +311,29 @@ double orc_prim_eri(const int* pa, double a, const double* A, const int* pb, dou
   return pq.eri(pa, pb, pc, pd);
 }
 
+// The same for erf(omega r12)/r12 (omega > 0).
+double orc_prim_eri_omega(const int* pa, double a, const double* A, const int* pb, double b,
+                          const double* B, const int* pc, double c, const double* C,
+                          const int* pd, double d, const double* D, double omega) {
+  const int lmax[4] = {pa[0] + pa[1] + pa[2], pb[0] + pb[1] + pb[2], pc[0] + pc[1] + pc[2],
+                       pd[0] + pd[1] + pd[2]};
+  PrimQuartet pq;
+  pq.build(lmax, a, A, b, B, c, C, d, D, omega);
+  return pq.eri(pa, pb, pc, pd);
+}
+
+// Integrals of this basis handle use erf(omega r12)/r12 from here on (omega > 0), or
+// 1/r12 (omega = 0); the Schwarz bounds stay those of 1/r12, which bound both.
+int orc_basis_set_omega(void* h, double omega) {
+  if (!(omega >= 0.0) || !std::isfinite(omega)) return -1;
+  static_cast<Basis*>(h)->omega = omega;
+  return 0;
+}
+
 int orc_shell_quartet(void* h, int A, int B, int C, int D, double* out) {
   const Basis& bs = *static_cast<Basis*>(h);
   PrimQuartet pq;
-  shell_quartet(bs, A, B, C, D, out, pq);
+  shell_quartet(bs, A, B, C, D, out, pq, bs.omega);
   return 0;
 }
 
@@ -345,7 +371,7 @@ long long orc_jk(void* h, int n_dm, const double* D, double tol, double* J, doub
         const int C = pairs[qi].A, Dd = pairs[qi].B;
         if (Q[(size_t)A * ns + B] * Q[(size_t)C * ns + Dd] < tol) continue;
         ++kept;
-        shell_quartet(bs, A, B, C, Dd, blk.data(), pq);
+        shell_quartet(bs, A, B, C, Dd, blk.data(), pq, bs.omega);
         double f = 1.0;
         if (A == B) f *= 0.5;
         if (C == Dd) f *= 0.5;
@@ -418,7 +444,7 @@ int orc_jk_blocks(void* h, int n_dm, const double* D, double tol, int nblk, cons
           const int nl = ncart(bs.l[L]), nsg = ncart(bs.l[S]);
           const int l0 = bs.bf0[L], s0 = bs.bf0[S];
           if (Q[(size_t)M * ns + N] * Q[(size_t)L * ns + S] >= tol) {
-            shell_quartet(bs, M, N, L, S, blk.data(), pq);
+            shell_quartet(bs, M, N, L, S, blk.data(), pq, bs.omega);
             for (int m = 0; m < n_dm; ++m)
               for (int a = 0; a < nm; ++a)
                 for (int b = 0; b < nnb; ++b) {
@@ -431,7 +457,7 @@ int orc_jk_blocks(void* h, int n_dm, const double* D, double tol, int nblk, cons
                 }
           }
           if (Q[(size_t)M * ns + L] * Q[(size_t)N * ns + S] >= tol) {
-            shell_quartet(bs, M, L, N, S, blk.data(), pq);
+            shell_quartet(bs, M, L, N, S, blk.data(), pq, bs.omega);
             for (int m = 0; m < n_dm; ++m)
               for (int a = 0; a < nm; ++a)
                 for (int b = 0; b < nnb; ++b) {
@@ -468,7 +494,7 @@ int orc_jk_blocks(void* h, int n_dm, const double* D, double tol, int nblk, cons
 int orc_grad(void* h, int n_dm, const double* D, double tol, double* dEdR, int nthreads,
              long long bra_pairs, const int* atom_sel) {
   const Basis& bs = *static_cast<Basis*>(h);
-  if (n_dm < 1 || n_dm > 16) return -1;
+  if (n_dm < 1 || n_dm > 16 || bs.omega != 0.0) return -1;
   const int n = bs.n_bf, ns = bs.n_shells, na_ = bs.n_atoms;
   const size_t nn = (size_t)n * n;
   const std::vector<double> Q = schwarz(bs);
@@ -583,7 +609,7 @@ long long orc_jk_bra_sample(void* h, int n_dm, const double* D, double tol, int 
         const int C = pairs[qi].A, Dd = pairs[qi].B;
         if (Q[(size_t)A * ns + B] * Q[(size_t)C * ns + Dd] < tol) continue;
         ++kept;
-        shell_quartet(bs, A, B, C, Dd, blk.data(), pq);
+        shell_quartet(bs, A, B, C, Dd, blk.data(), pq, bs.omega);
         double f = 1.0;
         if (A == B) f *= 0.5;
         if (C == Dd) f *= 0.5;

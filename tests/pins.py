@@ -9,7 +9,9 @@
                 fixed u the six-dimensional integral factorises over x, y, z into
                 two-dimensional polynomial x Gaussian integrals, each exact by
                 tensor Gauss-Hermite quadrature after whitening the quadratic form;
-                the u integral is done adaptively (scipy.integrate.quad).
+                the u integral is done adaptively (scipy.integrate.quad).  The
+                erf-attenuated operator erf(omega r12)/r12 is the same integral cut
+                at u = omega (omega > 0 passed as `omega`).
 """
 from __future__ import annotations
 
@@ -135,7 +137,7 @@ def _dim_integral(u, ea, Ax, ia, eb, Bx, ib, ec, Cx, ic, ed, Dx, id_, gh):
     return pre * math.exp(-const) * jac * float(W.ravel() @ poly)
 
 
-def eri_quadrature(pa, a, A, pb, b, B, pc, c, C, pd, d, D, epsrel=1e-13):
+def eri_quadrature(pa, a, A, pb, b, B, pc, c, C, pd, d, D, epsrel=1e-13, omega=None):
     npts = 1 + (sum(pa) + sum(pb) + sum(pc) + sum(pd)) // 2 + 4
     gh = _gh_2d(npts)
 
@@ -149,6 +151,8 @@ def eri_quadrature(pa, a, A, pb, b, B, pc, c, C, pd, d, D, epsrel=1e-13):
     # split the range: most weight sits at u of order sqrt(rho)
     val = 0.0
     edges = [0.0, 0.5, 2.0, 8.0, 32.0, np.inf]
+    if omega is not None:
+        edges = [e for e in edges if e < omega] + [float(omega)]
     for lo, hi in zip(edges[:-1], edges[1:]):
         r, _ = integrate.quad(integrand, lo, hi, epsabs=0.0, epsrel=epsrel, limit=400)
         val += r

@@ -23,6 +23,10 @@ int orc_grad(void*, int, const double*, double, double*, int, long long, const i
 long long orc_jk_bra_sample(void*, int, const double*, double, int, const int*, double*, double*,
                             int);
 int orc_screen_counts(void*, double, double, long long*, long long*);
+double orc_prim_eri_omega(const int*, double, const double*, const int*, double, const double*,
+                          const int*, double, const double*, const int*, double, const double*,
+                          double);
+int orc_basis_set_omega(void*, double);
 }
 
 static int fail(const char* what) {
@@ -109,6 +113,16 @@ int main() {
     }
   const int sel[3] = {0, 1, 0};   // atom 1 only
   if (orc_grad(b, 1, D.data(), 1e-10, g.data(), 1, -1, sel) != 0) return fail("grad (one atom)");
+  // erf(omega r12)/r12: a build at omega and the gradient's refusal of it
+  if (!std::isfinite(orc_prim_eri_omega(pa, 0.5, xyz, pb, 0.9, xyz + 3, pc, 1.3, xyz + 6, pd, 0.4,
+                                        xyz, 0.3)))
+    return fail("prim_eri_omega");
+  if (orc_basis_set_omega(b, -1.0) == 0 || orc_basis_set_omega(b, 0.3) != 0)
+    return fail("basis_set_omega");
+  if (orc_jk(b, n_dm, D.data(), 1e-10, J.data(), K.data(), 2) <= 0) return fail("jk at omega");
+  if (orc_grad(b, n_dm, D.data(), 1e-10, g.data(), 2, -1, nullptr) == 0)
+    return fail("grad must refuse omega > 0");
+  if (orc_basis_set_omega(b, 0.0) != 0) return fail("basis_set_omega");
   long long counts[63], near[21];
   if (orc_screen_counts(b, 1e-10, 1e-4, counts, near) != 0) return fail("screen_counts");
   long long tot = 0;

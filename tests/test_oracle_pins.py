@@ -312,7 +312,7 @@ def _four_centre_basis(nprim, seed):
                            np.asarray(coefs))
 
 
-def _contracted_by_quadrature(mol, shells, comps):
+def _contracted_by_quadrature(mol, shells, comps, omega=None):
     """sum over primitives of c c c c x (quadrature of the primitive integral)."""
     tot = 0.0
     ranges = [range(int(mol.shell_prim0[s]), int(mol.shell_prim0[s] + mol.shell_nprim[s]))
@@ -326,7 +326,8 @@ def _contracted_by_quadrature(mol, shells, comps):
                     tot += cc * pins.eri_quadrature(comps[0], mol.exps[i], cents[0],
                                                     comps[1], mol.exps[j], cents[1],
                                                     comps[2], mol.exps[k], cents[2],
-                                                    comps[3], mol.exps[m], cents[3])
+                                                    comps[3], mol.exps[m], cents[3],
+                                                    omega=omega)
     return tot
 
 
@@ -434,3 +435,106 @@ def test_gradient_rows_of_selected_atoms():
     # same terms summed in another order (OpenMP partial sums): rounding only
     np.testing.assert_allclose(Gs[:, [1, 3]], G[:, [1, 3]], rtol=0, atol=1e-12)
     assert np.all(Gs[:, [0, 2]] == 0.0)
+
+
+# --- erf-attenuated operator erf(omega r12)/r12 ----------------------------------
+
+OMEGA_QUAD_CASES = [QUAD_CASES[0], QUAD_CASES[2], QUAD_CASES[4], QUAD_CASES[5]]
+
+
+@pytest.mark.parametrize("omega", [0.15, 0.6, 2.5])
+@pytest.mark.parametrize("pows", OMEGA_QUAD_CASES)
+def test_prim_eri_omega_by_quadrature(pows, omega):
+    """The long-range integral is the Coulomb u integral cut at u = omega."""
+    rng = np.random.default_rng(sum(sum(p) * (i + 5) for i, p in enumerate(pows)))
+    args = _rand_prims(rng, list(pows))
+    o = oracle.prim_eri(*args, omega=omega)
+    ref = pins.eri_quadrature(*args, omega=omega)
+    assert abs(o - ref) <= 1e-11 * max(abs(ref), 1e-6), (o, ref)
+
+
+def test_prim_eri_omega_limits():
+    """omega -> infinity gives 1/r12; omega -> 0 gives (2 omega/sqrt(pi)) S_ab S_cd."""
+    rng = np.random.default_rng(31)
+    for pows in QUAD_CASES:
+        args = _rand_prims(rng, list(pows))
+        coul = oracle.prim_eri(*args)
+        big = oracle.prim_eri(*args, omega=1e7)
+        assert big == pytest.approx(coul, rel=1e-12, abs=1e-15)
+        omega = 1e-5
+        small = oracle.prim_eri(*args, omega=omega)
+        (pa, a, A, pb, b, B, pc, c, C, pd, d, D) = args
+        gh = pins._gh_2d(8)
+        ovl = 1.0
+        for k in range(3):   # u = 0: the bra and ket factors decouple into overlaps
+            ovl *= pins._dim_integral(0.0, a, A[k], pa[k], b, B[k], pb[k], c, C[k], pc[k],
+                                      d, D[k], pd[k], gh)
+        ref = 2.0 * omega / math.sqrt(math.pi) * ovl
+        assert small == pytest.approx(ref, rel=1e-8, abs=1e-14 * abs(coul))
+
+
+def test_omega_quartets_bounded_by_coulomb_schwarz(w4):
+    """erf(omega r)/r and erfc(omega r)/r are both positive definite kernels, so
+    |(ab|cd)_omega| <= sqrt((ab|ab)_omega (cd|cd)_omega) <= Q_ab Q_cd (the 1/r12
+    bounds used for screening), and (ab|ab)_omega grows with omega."""
+    b0 = oracle.Basis(w4)
+    b1 = oracle.Basis(w4, omega=0.4)
+    b2 = oracle.Basis(w4, omega=1.3)
+    Q = oracle.schwarz(b0)
+    rng = np.random.default_rng(13)
+    for _ in range(150):
+        A, B, C, D = (int(x) for x in rng.integers(0, w4.n_shells, 4))
+        blk = oracle.shell_quartet(b1, A, B, C, D)
+        assert np.abs(blk).max() <= Q[A, B] * Q[C, D] * (1 + 1e-12) + 1e-18
+    for A in range(0, w4.n_shells, 3):
+        B = (A * 5 + 1) % w4.n_shells
+        d1 = oracle.shell_quartet(b1, A, B, A, B)
+        d2 = oracle.shell_quartet(b2, A, B, A, B)
+        d0 = oracle.shell_quartet(b0, A, B, A, B)
+        n = d1.shape[0] * d1.shape[1]
+        M1, M2, M0 = (x.reshape(n, n) for x in (d1, d2, d0))
+        assert np.linalg.eigvalsh(0.5 * (M1 + M1.T)).min() > -1e-12
+        assert np.linalg.eigvalsh(0.5 * ((M2 - M1) + (M2 - M1).T)).min() > -1e-12
+        assert np.linalg.eigvalsh(0.5 * ((M0 - M2) + (M0 - M2).T)).min() > -1e-12
+
+
+def test_contracted_omega_quartet_components():
+    """Contraction and component order at omega: (dd|pp) of two-primitive shells."""
+    ls, omega = (2, 2, 1, 1), 0.45
+    mol = _four_centre_basis(2, seed=61)
+    shells = [3 * at + l for at, l in enumerate(ls)]
+    blk = oracle.shell_quartet(oracle.Basis(mol, omega=omega), *shells)
+    for idx in [(0, 0, 0, 0), (5, 3, 2, 1), (1, 4, 0, 2)]:
+        comps = [CART[l][i] for l, i in zip(ls, idx)]
+        ref = _contracted_by_quadrature(mol, shells, comps, omega=omega)
+        assert abs(blk[idx] - ref) <= 1e-11 * max(abs(ref), 1e-6), (idx, blk[idx], ref)
+
+
+def test_omega_jk_full_tensor_brute_force():
+    """Tiny molecule at omega: n^4 tensor from ordered quartets, J/K by einsum,
+    screening with the 1/r12 bounds removed by tol = 0."""
+    mol = molgen.make_molecule(1, 1, seed=9)
+    omega = 0.33
+    b = oracle.Basis(mol, omega=omega)
+    n, ns = mol.n_bf, mol.n_shells
+    bf0 = mol.shell_bf0
+    nc = [molgen.ncart(int(l)) for l in mol.shell_l]
+    eri = np.zeros((n, n, n, n))
+    for A in range(ns):
+        for B in range(ns):
+            for C in range(ns):
+                for D in range(ns):
+                    eri[bf0[A]:bf0[A] + nc[A], bf0[B]:bf0[B] + nc[B], bf0[C]:bf0[C] + nc[C],
+                        bf0[D]:bf0[D] + nc[D]] = oracle.shell_quartet(b, A, B, C, D)
+    Dm = mol.D[0]
+    J, K, _ = oracle.jk(mol, 0.0, omega=omega)
+    np.testing.assert_allclose(J[0], np.einsum("ijkl,kl->ij", eri, Dm), atol=1e-13, rtol=1e-12)
+    np.testing.assert_allclose(K[0], np.einsum("ikjl,kl->ij", eri, Dm), atol=1e-13, rtol=1e-12)
+    J0, _, _ = oracle.jk(mol, 0.0)
+    assert np.abs(J[0]).max() < np.abs(J0[0]).max()
+
+
+def test_omega_rejected_by_gradient():
+    mol = molgen.make_molecule(1, 1, seed=7)
+    with pytest.raises(ValueError, match="omega"):
+        oracle.grad(mol, 0.0, omega=0.3)
