@@ -232,7 +232,8 @@ def progress(msg):
 def extra_measurements(args, jkb, molgen, ctx, mol, basis, D, J, K, E_head, tol, precision,
                        ms_per_step, torch):
     """The same build in the other precision (time, speedup, energy differences),
-    the paper's own FP32 threshold (tolerance x 1e5), and the nuclear gradient:
+    the paper's own FP32 threshold (tolerance x 1e5), the long-range build of a
+    range-separated hybrid (omega = 0.3), and the nuclear gradient:
     of the 30-atom molecule, or of the workload itself (autograd through
     JKEnergy) when it carries several densities."""
     import numpy as np
@@ -270,6 +271,18 @@ def extra_measurements(args, jkb, molgen, ctx, mol, basis, D, J, K, E_head, tol,
             "fp32_below": tol * 1e5, "ms": 1e3 * t3, "speedup_over_fp64": fp64_ms / (1e3 * t3),
             "quartets_fp32": int(sum(s3[-1].quartets_fp32)),
             "dEJ": float(E3[0, 0] - E64[0, 0]), "dEK": float(E3[0, 1] - E64[0, 1])}
+    if n_dm == 1:
+        # the long-range exchange integrals of a range-separated hybrid:
+        # erf(omega r12)/r12 at omega = 0.3 bohr^-1 (the omegaB97X value), same
+        # screening and precision as the headline build
+        o4 = jkb.make_opts(precision, n_dm=n_dm, timing=True, serial=True, energy=E2, omega=0.3)
+        jkb.jk_build(ctx, basis, D, J, K, tol, o4)
+        t4, _ = run_steps(jkb, ctx, basis, D, J, K, tol, o4, 1, torch)
+        E4 = E2.cpu().numpy()
+        ex["long_range_omega_0.3"] = {
+            "precision": precision, "ms": 1e3 * t4, "time_over_1_r12_build": 1e3 * t4 / ms_per_step,
+            "E_J": float(E4[0, 0]), "E_K": float(E4[0, 1])}
+        progress("long-range (omega 0.3) build done")
     if n_dm == 1 and args.with_grad:
         # nuclear gradient of the 30-atom molecule, FP64 and mixed
         mg = molgen.workload("w30grad")

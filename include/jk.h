@@ -119,6 +119,13 @@ typedef struct {
                                  and E = E_J - E_K, summed in a fixed order             */
   double* dEdD;               /* jk_build, optional (NULL = not written): DEVICE pointer to
                                  [n_dm][n_bf][n_bf] receiving dE/dD = J - K/2            */
+  double omega;               /* jk_build: 0 (default) = the 1/r12 integrals; omega > 0 =
+                                 those of erf(omega r12)/r12 (bohr^-1, finite), the
+                                 long-range exchange of range-separated hybrids such as
+                                 the paper's omegaB97x runs (section "Benchmarks").
+                                 Screening keeps the 1/r12 bounds Q_AB (valid, as
+                                 |(ab|cd)_omega| <= Q_AB Q_CD); the setup does not
+                                 depend on omega.  jk_grad: JK_EUNSUPPORTED if != 0.  */
 } jk_opts;
 
 /* Counters of the last jk_build / jk_grad on a context. */

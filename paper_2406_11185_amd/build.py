@@ -43,11 +43,17 @@ def hipcc() -> str:
     return "hipcc"
 
 
+def _inc_of(src: str) -> str:
+    """Generated class code of a class translation unit (cls_X.hip and its
+    erf(omega r12)/r12 twin cls_X_att.hip both include cls_X.inc)."""
+    return src.replace("_att.hip", ".hip").replace(".hip", ".inc")
+
+
 def _deps_newer(src: str, obj: str) -> bool:
     if not os.path.exists(obj):
         return True
     t = os.path.getmtime(obj)
-    deps = [src, src.replace(".hip", ".inc"), os.path.join(CSRC, "jk_device.hpp"),
+    deps = [src, _inc_of(src), os.path.join(CSRC, "jk_device.hpp"),
             os.path.join(CSRC, "jk_grad_device.hpp"), os.path.join(CSRC, "jk_classes.hpp"),
             os.path.join(INCLUDE, "jk.h")]
     return any(os.path.exists(d) and os.path.getmtime(d) > t for d in deps)
@@ -94,8 +100,7 @@ def _build_locked(jobs: int, verbose: bool, incremental: bool) -> str:
     sources += sorted(os.path.join(GEN, f) for f in os.listdir(GEN)
                       if (f.startswith("cls_") or f.startswith("gcls_")) and f.endswith(".hip"))
     # largest classes first so the long compiles start early
-    sources.sort(key=lambda p: -os.path.getsize(p.replace(".hip", ".inc"))
-                 if os.path.exists(p.replace(".hip", ".inc")) else 0)
+    sources.sort(key=lambda p: -os.path.getsize(_inc_of(p)) if os.path.exists(_inc_of(p)) else 0)
     objs = [os.path.join(OBJ, os.path.basename(s).replace(".hip", ".o")) for s in sources]
     jobs = jobs or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

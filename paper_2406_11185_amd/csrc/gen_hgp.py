@@ -350,12 +350,12 @@ def uses_rows(name, size):
 ROWS_MULTI_CLASSES = {"ssss:4", "psss:4", "psps:4"}
 
 
-def rows_call(name, t):
+def rows_call(name, t, att=False):
     size = 8 if t == "double" else 4
     if not uses_rows(name, size):
         return "false"
     multi = "true" if f"{name}:{size}" in ROWS_MULTI_CLASSES else "false"
-    return f"launch_rows<Cls_{name}, {t}, {ROWS_BLOCK}, {multi}>(a, s)"
+    return f"launch_rows<Cls_{name}, {t}, {ROWS_BLOCK}, {multi}, {'true' if att else 'false'}>(a, s)"
 
 # Single-pass classes whose kernels digest in five sweeps (one J/K block each).
 # JK_SWEEPS_OVERRIDE=1 turns sweeps on for every class above LDS_MAX_L, for
@@ -710,8 +710,13 @@ def gen_split_class(la, lb, lc, ld, suffix="", pass_acc=None, pass_acc_wide=None
 PAIR_NAME = {pc: LNAME[pc[0]] + LNAME[pc[1]] for pc in PAIR_CLASSES}
 
 
-def wrapper(info):
+def wrapper(info, att=False):
+    """Launch function of one class: launch_eri_<name> for the 1/r12 kernels, or
+    (att) launch_eri_att_<name> for those of erf(omega r12)/r12, which take the
+    same launch shapes; each goes to a translation unit of its own."""
     n = info["name"]
+    fn = f"launch_eri_att_{n}" if att else f"launch_eri_{n}"
+    ta = ", true" if att else ""
     kern = "eri_jk_split_kernel" if info["split"] else "eri_jk_kernel"
     skern = "schwarz_split_kernel" if info["split"] else "schwarz_kernel"
     i32 = info.get("f32", info)   # FP32 layout (the class itself unless it has its own)
@@ -721,22 +726,22 @@ def wrapper(info):
          '#include "jk_classes.hpp"',
          "namespace jk {",
          f'#include "cls_{n}.inc"',
-         f"void launch_eri_{n}(const EriLaunch& a, int fp32, hipStream_t s) {{",
+         f"void {fn}(const EriLaunch& a, int fp32, hipStream_t s) {{",
          *([f"  // the bra's exchange rows in LDS, where they fit",
-            f"  if (a.rows && (fp32 ? {rows_call(n, 'float')}",
-            f"                      : {rows_call(n, 'double')})) return;",
+            f"  if (a.rows && (fp32 ? {rows_call(n, 'float', att)}",
+            f"                      : {rows_call(n, 'double', att)})) return;",
             f"  // Boys rows staged in LDS; as many workgroups as fit on the device claim the items",
             f"  constexpr int NT = {info.get('lds_block', 0)};",
             f"  static int per_cu[2] = {{0, 0}};",
             f"  if (!per_cu[fp32]) {{",
             f"    int nb = 0;",
-            f"    if (fp32) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&eri_jk_lds_kernel<Cls_{n}, float, NT>), NT, 0);",
-            f"    else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&eri_jk_lds_kernel<Cls_{n}, double, NT>), NT, 0);",
+            f"    if (fp32) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&eri_jk_lds_kernel<Cls_{n}, float, NT{ta}>), NT, 0);",
+            f"    else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&eri_jk_lds_kernel<Cls_{n}, double, NT{ta}>), NT, 0);",
             f"    per_cu[fp32] = nb > 0 ? nb : 1;",
             f"  }}",
             f"  const dim3 lgrid(std::min((a.nitems + NT / kWave - 1) / (NT / kWave), per_cu[fp32] * a.num_cu));",
-            f"  if (fp32) launch_kernel(&eri_jk_lds_kernel<Cls_{n}, float, NT>, lgrid, dim3(NT), 0, s, a.dry != 0, a);",
-            f"  else launch_kernel(&eri_jk_lds_kernel<Cls_{n}, double, NT>, lgrid, dim3(NT), 0, s, a.dry != 0, a);",
+            f"  if (fp32) launch_kernel(&eri_jk_lds_kernel<Cls_{n}, float, NT{ta}>, lgrid, dim3(NT), 0, s, a.dry != 0, a);",
+            f"  else launch_kernel(&eri_jk_lds_kernel<Cls_{n}, double, NT{ta}>, lgrid, dim3(NT), 0, s, a.dry != 0, a);",
             "}"] if info.get("lds") else []),
          *([] if info.get("lds") else [
          "  const dim3 block(kBlock);",
@@ -746,7 +751,7 @@ def wrapper(info):
          *[ln for g_ in i32["lane_options"] for ln in (
              f"    {'if' if g_ == i32['lane_options'][0] else 'else if'} (a.lanes == {g_} || "
              f"{'true' if g_ == i32['lane_options'][-1] else 'false'})",
-             f"      launch_kernel(&{kern32}<Cls_{n32}, float, {g_}>, grid, block, 0, s, a.dry != 0, a);")],
+             f"      launch_kernel(&{kern32}<Cls_{n32}, float, {g_}{ta}>, grid, block, 0, s, a.dry != 0, a);")],
          "    return;",
          "  }",
          "  const int waves = " + ("a.nwaves" if info["split"] else "a.nitems") + ";",
@@ -754,9 +759,9 @@ def wrapper(info):
          *[ln for g_ in info["lane_options"] for ln in (
              f"  {'if' if g_ == info['lane_options'][0] else 'else if'} (a.lanes == {g_} || "
              f"{'true' if g_ == info['lane_options'][-1] else 'false'})",
-             f"    launch_kernel(&{kern}<Cls_{n}, double, {g_}>, grid, block, 0, s, a.dry != 0, a);")],
+             f"    launch_kernel(&{kern}<Cls_{n}, double, {g_}{ta}>, grid, block, 0, s, a.dry != 0, a);")],
          "}"])]
-    if info["bra_class"] == info["ket_class"]:
+    if info["bra_class"] == info["ket_class"] and not att:   # screening bounds: 1/r12
         w += [f"void launch_schwarz_{n}(const EriLaunch& a, double* Q, hipStream_t s) {{",
               (f"  launch_kernel(&{skern}<Cls_{n}>, dim3((a.nwaves + kWavesPerBlock - 1) / kWavesPerBlock),"
                " dim3(kBlock), 0, s, false, a, Q);") if info["split"] else
@@ -771,12 +776,14 @@ def table(infos):
     t = ["// generated by gen_hgp.py -- do not edit", '#include "jk_classes.hpp"', "namespace jk {"]
     for i in infos:
         t.append(f"void launch_eri_{i['name']}(const EriLaunch&, int, hipStream_t);")
+        t.append(f"void launch_eri_att_{i['name']}(const EriLaunch&, int, hipStream_t);")
         if i["bra_class"] == i["ket_class"]:
             t.append(f"void launch_schwarz_{i['name']}(const EriLaunch&, double*, hipStream_t);")
     t.append("void launch_eri(int cls, int fp32, const EriLaunch& a, hipStream_t s) {")
     t.append("  switch (cls) {")
     for q, i in enumerate(infos):
-        t.append(f"    case {q}: launch_eri_{i['name']}(a, fp32, s); break;")
+        t.append(f"    case {q}: if (a.att) launch_eri_att_{i['name']}(a, fp32, s);"
+                 f" else launch_eri_{i['name']}(a, fp32, s); break;")
     t.append("    default: break;")
     t.append("  }")
     t.append("}")
@@ -872,6 +879,7 @@ def main(outdir):
         write_if_changed(os.path.join(outdir, f"cls_{name}.inc"),
                          "// generated by gen_hgp.py -- do not edit\n" + code)
         write_if_changed(os.path.join(outdir, f"cls_{name}.hip"), wrapper(info))
+        write_if_changed(os.path.join(outdir, f"cls_{name}_att.hip"), wrapper(info, att=True))
     write_if_changed(os.path.join(outdir, "jk_classes_table.hip"), table(infos))
     write_if_changed(os.path.join(outdir, "classes.json"), json.dumps(infos, indent=1))
     return infos

@@ -29,12 +29,13 @@ __global__ void zero_counter_kernel(int* p) {
 // (one device per process).  Several densities (MULTI): one launch per density,
 // each recomputing the integrals, since the LDS holds one density's rows; for
 // classes whose integrals cost less than the per-density scatter they replace.
-template <class C, typename T, int NT, bool MULTI>
+// ATT: the erf(omega r12)/r12 kernel.
+template <class C, typename T, int NT, bool MULTI, bool ATT>
 bool launch_rows(const EriLaunch& a, hipStream_t s) {
   if (a.n_dm > 1 && !MULTI) return false;
   static size_t static_bytes = 0;
   static int max_lds = -1;
-  const void* k = reinterpret_cast<const void*>(&eri_jk_rows_kernel<C, T, NT>);
+  const void* k = reinterpret_cast<const void*>(&eri_jk_rows_kernel<C, T, NT, ATT>);
   if (max_lds < 0) {
     hipFuncAttributes fa{};
     int dev = 0, lds = 0;
@@ -55,7 +56,7 @@ bool launch_rows(const EriLaunch& a, hipStream_t s) {
   (void)hipGetLastError();
   const dim3 grid(static_cast<unsigned>(std::min(a.nitems, nb * a.num_cu)));
   if (a.n_dm == 1) {
-    launch_kernel(&eri_jk_rows_kernel<C, T, NT>, grid, dim3(NT), dyn, s, a.dry != 0, a);
+    launch_kernel(&eri_jk_rows_kernel<C, T, NT, ATT>, grid, dim3(NT), dyn, s, a.dry != 0, a);
     return true;
   }
   EriLaunch b = a;   // density m: D, J, K (and their accumulator copies) at m n^2
@@ -66,7 +67,7 @@ bool launch_rows(const EriLaunch& a, hipStream_t s) {
     b.J = a.J + m * nn;
     b.K = a.K + m * nn;
     if (m > 0 && !a.dry) hipLaunchKernelGGL(zero_counter_kernel<0>, dim3(1), dim3(kWave), 0, s, a.next);
-    launch_kernel(&eri_jk_rows_kernel<C, T, NT>, grid, dim3(NT), dyn, s, a.dry != 0, b);
+    launch_kernel(&eri_jk_rows_kernel<C, T, NT, ATT>, grid, dim3(NT), dyn, s, a.dry != 0, b);
     if (a.dry) break;   // the guard's answer is the same for every density
   }
   return true;

@@ -93,6 +93,8 @@ struct EriLaunch {
   const double* boys64;
   const float* boys32;
   float boys_fp64_T;  // FP32 kernels: F_m in FP64 above this T
+  int att;            // host only: 1 selects the kernels of erf(omega r12)/r12
+  double omega2;      // omega^2 (read by those kernels)
   void* ws;           // multi-pass classes: per-wave workspace (see split_ws_bytes)
   int nwaves;         // multi-pass classes: wavefronts of the launch
   int lanes;          // lanes sharing one shell quartet in this launch (1 or the class maximum)
@@ -325,31 +327,34 @@ __device__ __forceinline__ void boys32_eval(float T, float tcut, const BoysRow32
   }
 }
 
-// Where a kernel reads the Boys rows of its order L from.
-template <typename T>
+// Where a kernel reads the Boys rows of its order L from.  ATT: the kernel
+// computes the integrals of erf(omega r12)/r12 (see prim_geo), om2 = omega^2.
+template <typename T, bool ATT = false>
 struct BoysTab;
-template <>
-struct BoysTab<double> {
+template <bool ATT>
+struct BoysTab<double, ATT> {
   const double* rows;   // order-L FP64 rows
   double tmax;          // tabulated range T < tmax; asymptotic form beyond
+  double om2;
 };
-template <>
-struct BoysTab<float> {
+template <bool ATT>
+struct BoysTab<float, ATT> {
   const float* rows;     // order-L FP32 rows (T <= tcut)
   float tcut;            // FP64 evaluation above
   const double* rows64;  // order-L FP64 rows, for e^{-T} above tcut
+  float om2;
 };
 
 // The tables in global memory.
-template <int L, typename T>
-__device__ __forceinline__ BoysTab<T> global_boys(const EriLaunch& a) {
+template <int L, typename T, bool ATT = false>
+__device__ __forceinline__ BoysTab<T, ATT> global_boys(const EriLaunch& a) {
   static_assert(L <= kBoysMaxL, "Boys table order");
   const double* r64 = a.boys64 + static_cast<size_t>(L) * kBoysRows * kBoysRow;
   if constexpr (sizeof(T) == 8) {
-    return BoysTab<double>{r64, kBoysTmax};
+    return BoysTab<double, ATT>{r64, kBoysTmax, a.omega2};
   } else {
-    return BoysTab<float>{a.boys32 + static_cast<size_t>(L) * kBoys32Rows * kBoys32Row,
-                          a.boys_fp64_T, r64};
+    return BoysTab<float, ATT>{a.boys32 + static_cast<size_t>(L) * kBoys32Rows * kBoys32Row,
+                               a.boys_fp64_T, r64, static_cast<float>(a.omega2)};
   }
 }
 
@@ -358,10 +363,12 @@ struct Boys;
 template <int L>
 struct Boys<L, double> {
   using Row = BoysRow64;
-  __device__ __forceinline__ static Row fetch(double T, const BoysTab<double>& t) {
+  template <bool A>
+  __device__ __forceinline__ static Row fetch(double T, const BoysTab<double, A>& t) {
     return boys64_fetch(T, t.rows, t.tmax);
   }
-  __device__ __forceinline__ static void eval(double T, const Row& r, const BoysTab<double>& t,
+  template <bool A>
+  __device__ __forceinline__ static void eval(double T, const Row& r, const BoysTab<double, A>& t,
                                               double* F) {
     boys64_eval<L>(T, r, t.tmax, F);
   }
@@ -369,10 +376,12 @@ struct Boys<L, double> {
 template <int L>
 struct Boys<L, float> {
   using Row = BoysRow32;
-  __device__ __forceinline__ static Row fetch(float T, const BoysTab<float>& t) {
+  template <bool A>
+  __device__ __forceinline__ static Row fetch(float T, const BoysTab<float, A>& t) {
     return boys32_fetch<L>(T, t.tcut, t.rows);
   }
-  __device__ __forceinline__ static void eval(float T, const Row& r, const BoysTab<float>& t,
+  template <bool A>
+  __device__ __forceinline__ static void eval(float T, const Row& r, const BoysTab<float, A>& t,
                                               float* F) {
     boys32_eval<L>(T, t.tcut, r, t.rows64, F);
   }
@@ -390,15 +399,19 @@ __device__ __forceinline__ T rsqrt_t(T x) {
 //   P - Q = (P - A) - (Q - C) + (A - C)   (keeps FP32 differences small)
 //   W - P = -q/(p+q) (P - Q),  W - Q = p/(p+q) (P - Q),  rho = pq/(p+q)
 //   prefactor = 2 pi^{5/2} K_AB K_CD / (p q sqrt(p+q)) = Kt_AB Kt_CD / sqrt(p+q)
+// The erf(omega r12)/r12 operator (ATT) depends on the geometry through T alone,
+// like 1/r12, with F_m(T) replaced by sqrt(s) s^m F_m(s T), s = omega^2 /
+// (omega^2 + rho): the recurrences are unchanged.  ATT is a compile-time flag, so
+// the 1/r12 kernels carry none of it.
 template <int L, typename T>
 struct PrimGeo {
   T srpq, PQx, PQy, PQz, Tb;
   typename Boys<L, T>::Row row;
 };
 
-template <int L, typename T>
+template <int L, typename T, bool ATT>
 __device__ __forceinline__ void prim_geo(T p, T PAx, T PAy, T PAz, T q, T QCx, T QCy, T QCz,
-                                         T ACx, T ACy, T ACz, const BoysTab<T>& bt,
+                                         T ACx, T ACy, T ACz, const BoysTab<T, ATT>& bt,
                                          PrimGeo<L, T>& g) {
   g.srpq = rsqrt_t<T>(p + q);   // 1/sqrt(p+q)
   const T rpq = g.srpq * g.srpq;
@@ -406,19 +419,31 @@ __device__ __forceinline__ void prim_geo(T p, T PAx, T PAy, T PAz, T q, T QCx, T
   g.PQy = PAy - QCy + ACy;
   g.PQz = PAz - QCz + ACz;
   g.Tb = p * (q * rpq) * (g.PQx * g.PQx + g.PQy * g.PQy + g.PQz * g.PQz);
+  if constexpr (ATT) g.Tb *= bt.om2 / (bt.om2 + p * (q * rpq));
   g.row = Boys<L, T>::fetch(g.Tb, bt);
 }
 
-template <int L, typename T>
+template <int L, typename T, bool ATT>
 __device__ __forceinline__ void prim_finish(const PrimGeo<L, T>& g, T p, T oo2p, T PAx, T PAy,
                                             T PAz, T Kab, T q, T oo2q, T QCx, T QCy, T QCz,
-                                            T Kcd, const BoysTab<T>& bt, T* F, VrrCoef<T>& c) {
+                                            T Kcd, const BoysTab<T, ATT>& bt, T* F,
+                                            VrrCoef<T>& c) {
   const T rpq = g.srpq * g.srpq;
   const T qr = q * rpq, pr = p * rpq;
   Boys<L, T>::eval(g.Tb, g.row, bt, F);
   const T pref = Kab * Kcd * g.srpq;
+  if constexpr (ATT) {
+    const T sa = bt.om2 / (bt.om2 + p * qr);
+    T f = pref * sqrt(sa);
 #pragma unroll
-  for (int m = 0; m <= L; ++m) F[m] *= pref;
+    for (int m = 0; m <= L; ++m) {
+      F[m] *= f;
+      f *= sa;
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m <= L; ++m) F[m] *= pref;
+  }
   c.PAx = PAx; c.PAy = PAy; c.PAz = PAz;
   c.QCx = QCx; c.QCy = QCy; c.QCz = QCz;
   c.WPx = -qr * g.PQx; c.WPy = -qr * g.PQy; c.WPz = -qr * g.PQz;
@@ -432,7 +457,7 @@ template <int L, typename T>
 __device__ __forceinline__ void prim_setup(T p, T oo2p, T PAx, T PAy, T PAz, T Kab, T q, T oo2q,
                                            T QCx, T QCy, T QCz, T Kcd, T ACx, T ACy, T ACz,
                                            const EriLaunch& a, T* F, VrrCoef<T>& c) {
-  const BoysTab<T> bt = global_boys<L, T>(a);
+  const BoysTab<T> bt = global_boys<L, T>(a);   // 1/r12 only
   PrimGeo<L, T> g;
   prim_geo<L, T>(p, PAx, PAy, PAz, q, QCx, QCy, QCz, ACx, ACy, ACz, bt, g);
   prim_finish<L, T>(g, p, oo2p, PAx, PAy, PAz, Kab, q, oo2q, QCx, QCy, QCz, Kcd, bt, F, c);
@@ -467,8 +492,8 @@ __device__ __forceinline__ const T* primT_of(const BinView& v) {
 // G > 1: the G lanes of a group share the quartet; lane `sub` takes the
 // primitive quartets sub, sub+G, ... as (kl, ij) with ij running fastest; the
 // group's accumulators are summed by the caller.
-template <int L, typename T, int G, class V>
-__device__ __forceinline__ void contract(const EriLaunch& a, const BoysTab<T>& bt, int i, int k,
+template <int L, typename T, int G, bool ATT, class V>
+__device__ __forceinline__ void contract(const EriLaunch& a, const BoysTab<T, ATT>& bt, int i, int k,
                                          int sub, T ACx, T ACy, T ACz, V&& vrr) {
   const int nk = a.ket.n;
   const int nppb = a.bra.npp, nppk = a.ket.npp;
@@ -774,8 +799,8 @@ __device__ __forceinline__ void load_block(double* dst, const double* Dm, size_t
 // precision by one wavefront: the bra pair is uniform across the wave (scalar
 // data), each lane (each group of G lanes) takes one ket pair of the current
 // chunk of the item's ket range.
-template <class C, typename T, int G>
-__device__ __forceinline__ void eri_item(const EriLaunch& a, const BoysTab<T>& bt, int item,
+template <class C, typename T, int G, bool ATT>
+__device__ __forceinline__ void eri_item(const EriLaunch& a, const BoysTab<T, ATT>& bt, int item,
                                          double* stage) {
   constexpr int QPW = kWave / G;
   const int lane = threadIdx.x & (kWave - 1);
@@ -935,14 +960,14 @@ __device__ __forceinline__ void eri_item(const EriLaunch& a, const BoysTab<T>& b
   }
 }
 
-template <class C, typename T, int G>
+template <class C, typename T, int G, bool ATT = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(class_waves<C, T>())))
 void eri_jk_kernel(const EriLaunch a) {
   constexpr int ST = stage_doubles<C, kWave / G>();
   __shared__ double stage[kWavesPerBlock * ST];
   const int item = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (item >= a.nitems) return;
-  eri_item<C, T, G>(a, global_boys<C::L, T>(a), item, stage + (threadIdx.x >> 6) * ST);
+  eri_item<C, T, G>(a, global_boys<C::L, T, ATT>(a), item, stage + (threadIdx.x >> 6) * ST);
 }
 
 // Light classes (L <= 3, one lane per quartet): the Boys-table gathers, one
@@ -956,12 +981,12 @@ constexpr int kLdsMaxL = 3;
 constexpr double kLdsTmax = 45.0;
 constexpr int kLdsRows64 = 901;   // T_i = 0.05 i <= 45
 
-template <class C, typename T, int NT>
+template <class C, typename T, int NT, bool ATT = false>
 __global__ __launch_bounds__(NT) void eri_jk_lds_kernel(const EriLaunch a) {
   static_assert(C::L <= kLdsMaxL, "LDS Boys table: orders <= 3");
   constexpr int W = NT / kWave;
-  const BoysTab<T> g = global_boys<C::L, T>(a);
-  BoysTab<T> bt = g;
+  const BoysTab<T, ATT> g = global_boys<C::L, T, ATT>(a);
+  BoysTab<T, ATT> bt = g;
   if constexpr (sizeof(T) == 8) {
     __shared__ double2 rows[kLdsRows64 * kBoysRow / 2];
     const double2* src = reinterpret_cast<const double2*>(g.rows);
@@ -993,8 +1018,8 @@ __global__ __launch_bounds__(NT) void eri_jk_lds_kernel(const EriLaunch a) {
 // J_cd still goes to J per quartet through the staged scatter.
 
 // One 64-ket chunk of a work item, one lane per quartet (one density).
-template <class C, typename T>
-__device__ __forceinline__ void eri_chunk_rows(const EriLaunch& a, const BoysTab<T>& bt, int i,
+template <class C, typename T, bool ATT>
+__device__ __forceinline__ void eri_chunk_rows(const EriLaunch& a, const BoysTab<T, ATT>& bt, int i,
                                                int kc, int kend, double* stage, double* krow,
                                                double* jrow, double* Jm) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -1078,13 +1103,13 @@ __host__ __device__ constexpr size_t rows_lds_doubles(int n) {
   return static_cast<size_t>(C::NA + C::NB) * n + C::NA * C::NB;
 }
 
-template <class C, typename T, int NT>
+template <class C, typename T, int NT, bool ATT = false>
 __global__ __launch_bounds__(NT) void eri_jk_rows_kernel(const EriLaunch a) {
   static_assert(C::L <= kLdsMaxL, "LDS Boys table: orders <= 3");
   constexpr int W = NT / kWave;
   constexpr int NR = C::NA + C::NB;
-  const BoysTab<T> g = global_boys<C::L, T>(a);
-  BoysTab<T> bt = g;
+  const BoysTab<T, ATT> g = global_boys<C::L, T, ATT>(a);
+  BoysTab<T, ATT> bt = g;
   if constexpr (sizeof(T) == 8) {
     __shared__ double2 rows[kLdsRows64 * kBoysRow / 2];
     const double2* src = reinterpret_cast<const double2*>(g.rows);
@@ -1177,7 +1202,7 @@ __global__ __launch_bounds__(kBlock) void schwarz_kernel(const EriLaunch a, doub
 // primitive loop and parks the chunk in the wavefront's workspace; the
 // horizontal recurrences then run as short loops: the ket step for one e at a
 // time into X[e][cd], the bra step plus digestion for one (c, d) at a time.
-template <class C, typename T, int G, int J, class A>
+template <class C, typename T, int G, int J, class A, bool ATT = false>
 __device__ __forceinline__ void split_passes(const EriLaunch& a, int i, int k, int sub, T ACx,
                                              T ACy, T ACz, A cacc, int z) {
   // pass J accumulates the rows e = E0 .. E0+NEJ-1 of the contracted [e0|f0]
@@ -1185,7 +1210,7 @@ __device__ __forceinline__ void split_passes(const EriLaunch& a, int i, int k, i
   T acc[NEJ * C::NF];
 #pragma unroll
   for (int t = 0; t < NEJ * C::NF; ++t) acc[t] = T(0);
-  contract<C::L, T, G>(a, global_boys<C::L, T>(a), i, k, sub, ACx, ACy, ACz,
+  contract<C::L, T, G>(a, global_boys<C::L, T, ATT>(a), i, k, sub, ACx, ACy, ACz,
                                       [&](const T* F, const VrrCoef<T>& c) {
     C::template vrr_pass<J, T>(F, c, acc);
   });
@@ -1194,7 +1219,8 @@ __device__ __forceinline__ void split_passes(const EriLaunch& a, int i, int k, i
 #pragma unroll
     for (int t = 0; t < NEJ * C::NF; ++t) cacc[z + E0 * C::NF + t] = acc[t];
   }
-  if constexpr (J + 1 < C::NPASS) split_passes<C, T, G, J + 1, A>(a, i, k, sub, ACx, ACy, ACz, cacc, z);
+  if constexpr (J + 1 < C::NPASS)
+    split_passes<C, T, G, J + 1, A, ATT>(a, i, k, sub, ACx, ACy, ACz, cacc, z);
 }
 
 template <class C, typename T, class A>
@@ -1213,7 +1239,7 @@ __device__ __forceinline__ void split_ket_hrr(A cacc, A X, int z, T CDx, T CDy, 
   }
 }
 
-template <class C, typename T, int G>
+template <class C, typename T, int G, bool ATT = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(class_waves<C, T>())))
 void eri_jk_split_kernel(const EriLaunch a) {
   constexpr int NCD = C::NC * C::ND;
@@ -1266,7 +1292,7 @@ void eri_jk_split_kernel(const EriLaunch a) {
     const int k = inrange ? kc + ql : kend - 1;
     const T ACx = T(Ax - a.ket.A[k]), ACy = T(Ay - a.ket.A[nk + k]),
             ACz = T(Az - a.ket.A[2 * nk + k]);
-    split_passes<C, T, G, 0, AT>(a, i, k, sub, ACx, ACy, ACz, cacc, z);
+    split_passes<C, T, G, 0, AT, ATT>(a, i, k, sub, ACx, ACy, ACz, cacc, z);
     const T CDx = T(a.ket.AB[k]), CDy = T(a.ket.AB[nk + k]), CDz = T(a.ket.AB[2 * nk + k]);
     // the G lanes of a quartet share the horizontal recurrences and the
     // digestion: lane `sub` takes e = sub, sub+G, ... and (c,d) = sub, sub+G, ...

@@ -1048,6 +1048,8 @@ EriLaunch launch_args(jk_ctx* c, const Plan& P, const Setup& S, int X, int Y, in
   a.boys64 = c->boys64;
   a.boys32 = c->boys32;
   a.boys_fp64_T = static_cast<float>(o.boys_fp64_T);
+  a.att = o.omega > 0.0 ? 1 : 0;
+  a.omega2 = o.omega * o.omega;
   a.num_cu = c->num_cu;
   return a;
 }
@@ -1156,6 +1158,7 @@ int check_opts(const jk_opts* o, jk_opts* out, std::string* msg) {
   if (out->acc_copies < 0 || out->acc_copies > static_cast<int32_t>(kMaxCopies)) { *msg = "opts.acc_copies must be in 0..8"; return JK_EINVAL; }
   if (out->serial != 0 && out->serial != 1) { *msg = "opts.serial must be 0 or 1"; return JK_EINVAL; }
   if (out->reuse_setup != 0 && out->reuse_setup != 1) { *msg = "opts.reuse_setup must be 0 or 1"; return JK_EINVAL; }
+  if (!(out->omega >= 0.0) || !std::isfinite(out->omega)) { *msg = "opts.omega must be finite and >= 0"; return JK_EINVAL; }
   return JK_OK;
 }
 
@@ -1177,6 +1180,7 @@ int jk_opts_default(jk_opts* o) {
   o->reuse_setup = 0;
   o->energy = nullptr;
   o->dEdD = nullptr;
+  o->omega = 0.0;
   return JK_OK;
 }
 
@@ -1396,6 +1400,7 @@ int jk_grad(jk_ctx* c, const jk_basis* basis, const double* D, double* dEdR, dou
   jk_opts o;
   rc = check_opts(opts, &o, &c->err);
   if (rc != JK_OK) return rc;
+  if (o.omega != 0.0) { c->err = "jk_grad: only the 1/r12 operator (opts.omega = 0)"; return JK_EUNSUPPORTED; }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   try {
     HIP_OK(hipSetDevice(c->device));

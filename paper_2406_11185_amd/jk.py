@@ -49,7 +49,7 @@ class jk_opts(ctypes.Structure):
                 ("max_scratch_bytes", ctypes.c_uint64), ("acc_copies", ctypes.c_int32),
                 ("serial", ctypes.c_int32), ("reuse_setup", ctypes.c_int32),
                 ("energy", ctypes.c_void_p),
-                ("dEdD", ctypes.c_void_p)]
+                ("dEdD", ctypes.c_void_p), ("omega", ctypes.c_double)]
 
 
 class jk_stats(ctypes.Structure):
@@ -125,8 +125,9 @@ def jk_opts_default() -> jk_opts:
 
 def make_opts(precision="fp64", fp32_below=1e-4, n_dm=1, timing=False, boys_fp64_T=30.0,
               max_scratch_bytes=0, deterministic=0, acc_copies=0, serial=False, energy=None,
-              dEdD=None, reuse_setup=False) -> jk_opts:
-    """jk_opts from keywords; energy / dEdD are float64 device tensors (or None)."""
+              dEdD=None, reuse_setup=False, omega=0.0) -> jk_opts:
+    """jk_opts from keywords; energy / dEdD are float64 device tensors (or None);
+    omega > 0 selects the erf(omega r12)/r12 integrals."""
     o = jk_opts_default()
     o.precision = {"fp64": JK_FP64, "mixed": JK_MIXED}[precision] if isinstance(precision, str) \
         else int(precision)
@@ -141,6 +142,7 @@ def make_opts(precision="fp64", fp32_below=1e-4, n_dm=1, timing=False, boys_fp64
     o.reuse_setup = 1 if reuse_setup else 0
     o.energy = energy.data_ptr() if energy is not None else None
     o.dEdD = dEdD.data_ptr() if dEdD is not None else None
+    o.omega = float(omega)
     return o
 
 
@@ -249,7 +251,7 @@ def jk(mol, D, tol: float, precision: str = "fp64", fp32_below: float = 1e-4,
 
     energies=True adds E ([n_dm][3]: E_J, E_K, E_J - E_K, from the library's
     finalize step); dEdD=True adds dE/dD = J - K/2 (same shape as J).  Extra
-    keywords go to make_opts (deterministic, acc_copies, serial, ...)."""
+    keywords go to make_opts (deterministic, acc_copies, serial, omega, ...)."""
     import torch
     basis = mol if isinstance(mol, Basis) else Basis(mol)
     squeeze = D.dim() == 2

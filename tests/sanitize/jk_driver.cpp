@@ -10,7 +10,8 @@
 // OUTPUT: for each of the cases below in order, J then K ([n_dm][n][n] doubles).
 // Cases: FP64; mixed; deterministic with reuse_setup (second call, which must
 // reuse the setup); jk_build_noalloc; one accumulator copy with energies and
-// dE/dD (checked against J and K here); timing and jk_get_stats.  Exit status 0
+// dE/dD (checked against J and K here); FP64 at omega = 0.3 (erf(omega r12)/r12);
+// timing and jk_get_stats.  Exit status 0
 // when every call succeeds and every in-driver check holds.
 #include <hip/hip_runtime.h>
 
@@ -129,6 +130,11 @@ int main(int argc, char** argv) {
         std::fabs(he[3 * m + 2] - (he[3 * m] - he[3 * m + 1])) > 1e-12 * std::fmax(1.0, std::fabs(ej)))
       return fail("energies");
   }
+  // erf(omega r12)/r12 at omega = 0.3, and the gradient's refusal of omega > 0
+  jk_opts ow = o;
+  ow.omega = 0.3;
+  if (jk_build(c, &b, D, J, K, tol, &ow, nullptr) != JK_OK || !emit()) return fail("omega", c);
+  if (jk_grad(c, &b, D, G, tol, &ow, nullptr) != JK_EUNSUPPORTED) return fail("grad at omega", c);
   // timing and statistics
   jk_opts ot = o;
   ot.timing = 1;

@@ -34,7 +34,7 @@ def test_opts_default():
     assert o.precision == jkb.JK_FP64 and o.n_dm == 1 and o.fp32_below == 1e-4
     assert o.boys_fp64_T == 30.0 and o.deterministic == 0 and o.max_scratch_bytes == 0
     assert o.acc_copies == 0 and o.serial == 0 and o.reuse_setup == 0
-    assert not o.energy and not o.dEdD
+    assert not o.energy and not o.dEdD and o.omega == 0.0
     assert jkb.load().jk_opts_default(None) == jkb.JK_EINVAL
 
 

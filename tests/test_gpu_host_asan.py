@@ -2,9 +2,9 @@
 real device.  tests/bin/jk_asan_driver (built by tests/sanitize/build_jk_asan.py: the
 host translation unit and the driver instrumented, device code as usual) runs FP64,
 mixed, deterministic with a kept setup, the allocation-free entry, the single-copy
-path with energies and dE/dD (checked in the driver) and timing with statistics, all
-through the C ABI; any memory or undefined-behaviour error aborts it.  Its J and K
-are compared with the oracle."""
+path with energies and dE/dD (checked in the driver), FP64 at omega = 0.3 and timing
+with statistics, all through the C ABI; any memory or undefined-behaviour error aborts
+it.  Its J and K are compared with the oracle."""
 import os
 import subprocess
 
@@ -17,7 +17,7 @@ from paper_2406_11185_amd import molgen
 
 pytestmark = pytest.mark.gpu
 EXE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "bin", "jk_asan_driver")
-CASES = ["fp64", "mixed", "deterministic, kept setup", "allocation-free", "one copy"]
+CASES = ["fp64", "mixed", "deterministic, kept setup", "allocation-free", "one copy", "omega 0.3"]
 
 
 def write_input(path, mol, tol):
@@ -52,8 +52,10 @@ def test_host_code_under_sanitizers_on_device(tmp_path, nh, nH, seed, n_dm, tol)
     shape = (len(CASES), 2) + mol.D.shape
     res = np.fromfile(out, dtype=np.float64).reshape(shape)
     Jo, Ko, _ = oracle.jk(mol, tol)
+    Jw, Kw, _ = oracle.jk(mol, tol, omega=0.3)
     for c, name in enumerate(CASES):
-        dj, dk = np.abs(res[c, 0] - Jo).max(), np.abs(res[c, 1] - Ko).max()
+        jo, ko = (Jw, Kw) if name == "omega 0.3" else (Jo, Ko)
+        dj, dk = np.abs(res[c, 0] - jo).max(), np.abs(res[c, 1] - ko).max()
         say(f"  {name}: max|dJ|={dj:.2e} max|dK|={dk:.2e}")
         if name == "mixed":
             assert dj <= 1e-6 * np.abs(Jo).max() and dk <= 1e-6 * np.abs(Ko).max()

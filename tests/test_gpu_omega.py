@@ -1,0 +1,158 @@
+"""GPU parity of the erf(omega r12)/r12 (long-range, range-separated) J/K build
+against the CPU oracle: FP64 elementwise, the mixed dispatch, the omega limits,
+and the options that share the attenuated kernels (kept setup, no-alloc entry)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import blocks_of, sample_pairs, say
+from paper_2406_11185_amd import molgen
+
+pytestmark = pytest.mark.gpu
+TOL_ABS = 1e-10   # plain FP64 path against the FP64 oracle
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    from paper_2406_11185_amd import jk as jkb
+    jkb.load()
+
+
+def _gpu(mol, tol, omega, **kw):
+    import torch
+    from paper_2406_11185_amd import jk as jkb
+    D = torch.as_tensor(np.ascontiguousarray(mol.D), device="cuda")
+    J, K = jkb.jk(mol, D, tol, omega=omega, **kw)
+    torch.cuda.synchronize()
+    return J.cpu().numpy(), K.cpu().numpy()
+
+
+CASES = [
+    ("m3_3_21", lambda: molgen.make_molecule(3, 3, 21), 0.0, 0.3),
+    ("w4", lambda: molgen.workload("w4"), 0.0, 1.0),
+    ("ragged", lambda: molgen.ragged_molecule(2, 3, 5), 0.0, 0.11),
+    ("m4_5_5 n_dm=3", lambda: molgen.make_molecule(4, 5, 5, n_dm=3), 1e-8, 0.4),
+    ("one atom", lambda: molgen.make_molecule(1, 0, 13), 0.0, 0.25),
+]
+
+
+@pytest.mark.parametrize("name,make,tol,omega", CASES, ids=[c[0] for c in CASES])
+def test_omega_fp64_against_oracle(name, make, tol, omega):
+    mol = make()
+    say(f"case {name} ({mol.n_bf} functions, n_dm {mol.D.shape[0]}, tol {tol}, omega {omega})")
+    J, K = _gpu(mol, tol, omega)
+    Jo, Ko, _ = oracle.jk(mol, tol, omega=omega)
+    say("  max|dJ| =", np.abs(J - Jo).max(), " max|dK| =", np.abs(K - Ko).max())
+    assert np.abs(J - Jo).max() <= TOL_ABS
+    assert np.abs(K - Ko).max() <= TOL_ABS
+
+
+def test_omega_w30_sampled_blocks():
+    mol = molgen.workload("w30")
+    say("case w30 (270 functions, tol 1e-10, omega 0.3), sampled blocks")
+    J, K = _gpu(mol, 1e-10, 0.3)
+    pairs = sample_pairs(mol, 9, seed=31)
+    ref = oracle.jk_blocks(mol, 1e-10, pairs, omega=0.3)
+    for (m, n), gj, gk, (oj, ok) in zip(pairs, blocks_of(mol, J, pairs), blocks_of(mol, K, pairs), ref):
+        say(f"  block ({m},{n}) dJ={np.abs(gj - oj).max():.2e} dK={np.abs(gk - ok).max():.2e}")
+        assert np.abs(gj - oj).max() <= TOL_ABS
+        assert np.abs(gk - ok).max() <= TOL_ABS
+
+
+@pytest.mark.parametrize("n_dm", [1, 3])
+def test_omega_all_fp32_against_oracle(n_dm):
+    """Every quartet in FP32 (threshold above every bound), the per-density launches
+    of the light classes included at n_dm = 3: relative bound as for 1/r12."""
+    from paper_2406_11185_amd import jk as jkb
+    mol = molgen.make_molecule(3, 3, 21, n_dm=n_dm)
+    say(f"case all-FP32 m3_3_21 ({mol.n_bf} functions, n_dm {n_dm}, omega 0.3)")
+    J, K = _gpu(mol, 0.0, 0.3, precision="mixed", fp32_below=1e9)
+    st = jkb.default_context(0).stats()
+    assert sum(st.quartets_fp64) == 0
+    Jo, Ko, _ = oracle.jk(mol, 0.0, omega=0.3)
+    say(f"  max|dJ|={np.abs(J - Jo).max():.2e} max|dK|={np.abs(K - Ko).max():.2e}")
+    assert np.abs(J - Jo).max() <= 1e-6 * np.abs(Jo).max()
+    assert np.abs(K - Ko).max() <= 1e-6 * np.abs(Ko).max()
+
+
+def test_omega_mixed_against_fp64_w30():
+    from paper_2406_11185_amd import jk as jkb
+    mol = molgen.workload("w30")
+    say("case mixed vs fp64 w30 (tol 1e-10, FP32 below 1e-4, omega 0.3)")
+    J64, K64 = _gpu(mol, 1e-10, 0.3)
+    Jm, Km = _gpu(mol, 1e-10, 0.3, precision="mixed")
+    st = jkb.default_context(0).stats()
+    assert sum(st.quartets_fp32) > sum(st.quartets_fp64)
+    D = mol.D[0]
+    dEJ = 0.5 * float(np.sum(D * (Jm[0] - J64[0])))
+    dEK = 0.25 * float(np.sum(D * (Km[0] - K64[0])))
+    say(f"  dEJ={dEJ:.2e} dEK={dEK:.2e} max|dK|={np.abs(Km - K64).max():.2e}")
+    assert abs(dEJ) <= 1e-6 and abs(dEK) <= 1e-6
+
+
+def test_omega_limits_on_gpu():
+    """omega = 1e8 reproduces the 1/r12 build; the long-range part is smaller than
+    the full 1/r12 interaction for a positive semidefinite density."""
+    mol = molgen.make_molecule(2, 2, 11)
+    say(f"case omega limits ({mol.n_bf} functions)")
+    J0, K0 = _gpu(mol, 0.0, 0.0)
+    J8, K8 = _gpu(mol, 0.0, 1e8)
+    say(f"  omega 1e8: max|dJ|={np.abs(J8 - J0).max():.2e} max|dK|={np.abs(K8 - K0).max():.2e}")
+    assert np.abs(J8 - J0).max() <= 1e-12 * np.abs(J0).max()
+    assert np.abs(K8 - K0).max() <= 1e-12 * np.abs(K0).max()
+    rng = np.random.default_rng(5)
+    C = rng.normal(size=(mol.n_bf, 4))
+    P = C @ C.T
+    Jl, Kl = _gpu(mol.with_D(P[None]), 0.0, 0.5)
+    Jf, Kf = _gpu(mol.with_D(P[None]), 0.0, 0.0)
+    assert 0.0 < float(np.sum(P * Jl[0])) < float(np.sum(P * Jf[0]))
+    assert 0.0 < float(np.sum(P * Kl[0])) < float(np.sum(P * Kf[0]))
+
+
+def test_omega_kept_setup_and_noalloc_are_bitwise():
+    """The setup does not depend on omega: a build at omega that reuses the setup
+    of a 1/r12 build, and the no-alloc entry at omega, equal a fresh build bitwise
+    (deterministic sums)."""
+    import torch
+    from paper_2406_11185_amd import jk as jkb
+    mol = molgen.make_molecule(4, 5, 5, n_dm=2)
+    say(f"case omega with kept setup / no-alloc ({mol.n_bf} functions, n_dm 2)")
+    b = jkb.Basis(mol)
+    D = torch.as_tensor(np.ascontiguousarray(mol.D), device="cuda")
+    ctx = jkb.Context(0)
+    out = []
+    for reuse, omega, entry in [(0, 0.35, jkb.jk_build), (1, 0.0, jkb.jk_build),
+                                (1, 0.35, jkb.jk_build), (0, 0.35, jkb.jk_build_noalloc)]:
+        J, K = torch.full_like(D, 7.0), torch.full_like(D, 7.0)
+        entry(ctx, b, D, J, K, 1e-8, jkb.make_opts(n_dm=2, deterministic=1, omega=omega,
+                                                   reuse_setup=reuse))
+        torch.cuda.synchronize()
+        out.append((J.cpu().numpy(), K.cpu().numpy(), ctx.stats().setup_reused))
+    assert out[2][2] == 1
+    for J, K, _ in (out[2], out[3]):
+        assert np.array_equal(J, out[0][0]) and np.array_equal(K, out[0][1])
+    assert not np.array_equal(out[1][0], out[0][0])
+
+
+def test_omega_argument_checks():
+    """A negative or non-finite omega is rejected, and jk_grad refuses omega > 0;
+    both before any device work, so the outputs keep their contents."""
+    import torch
+    from paper_2406_11185_amd import jk as jkb
+    mol = molgen.make_molecule(1, 1, 7)
+    b = jkb.Basis(mol)
+    D = torch.as_tensor(np.ascontiguousarray(mol.D), device="cuda")
+    ctx = jkb.Context(0)
+    J, K = torch.full_like(D, 7.0), torch.full_like(D, 7.0)
+    for bad in (-0.1, float("inf"), float("nan")):
+        with pytest.raises(jkb.JkError) as e:
+            jkb.jk_build(ctx, b, D, J, K, 0.0, jkb.make_opts(omega=bad))
+        assert e.value.code == jkb.JK_EINVAL and "omega" in str(e.value)
+    G = torch.full((1, mol.n_atoms, 3), 7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(jkb.JkError) as e:
+        jkb.jk_grad(ctx, b, D, G, 0.0, jkb.make_opts(omega=0.3))
+    assert e.value.code == jkb.JK_EUNSUPPORTED
+    torch.cuda.synchronize()
+    assert bool((J == 7.0).all()) and bool((K == 7.0).all()) and bool((G == 7.0).all())
