@@ -8,7 +8,8 @@ function, plain digestion); this module only marshals numpy arrays.
 Parity status of each entry point (what pins it is listed in the tests):
   boys, prim_eri, shell_quartet, schwarz, jk, jk_blocks, jk_bra_sample, grad,
   screen_counts  -- pinned (the erf(omega r12)/r12 form of prim_eri, shell_quartet,
-  jk and jk_blocks as well)
+  jk and jk_blocks as well, and their pure-d form: pure_d, shell_quartet, jk,
+  jk_blocks)
 """
 from __future__ import annotations
 
@@ -42,6 +43,9 @@ def _load():
     lib.orc_prim_eri_omega.restype = ctypes.c_double
     lib.orc_prim_eri_omega.argtypes = [_ip, ctypes.c_double, _dp] * 4 + [ctypes.c_double]
     lib.orc_basis_set_omega.argtypes = [ctypes.c_void_p, ctypes.c_double]
+    lib.orc_basis_set_pure.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.orc_n_bf.argtypes = [ctypes.c_void_p]
+    lib.orc_pure_d.argtypes = [_dp]
     lib.orc_shell_quartet.argtypes = [ctypes.c_void_p] + [ctypes.c_int] * 4 + [_dp]
     lib.orc_schwarz.argtypes = [ctypes.c_void_p, _dp]
     lib.orc_jk.restype = ctypes.c_longlong
@@ -83,9 +87,10 @@ def ncart(l):
 
 class Basis:
     """Oracle-side copy of a basis (any object with the molgen.Molecule fields).
-    omega > 0: its integrals are those of erf(omega r12)/r12."""
+    omega > 0: its integrals are those of erf(omega r12)/r12.  pure: d shells carry
+    the five pure functions of pure_d() (basis functions renumbered)."""
 
-    def __init__(self, mol, omega: float = 0.0):
+    def __init__(self, mol, omega: float = 0.0, pure: bool = False):
         lib = _load()
         self._keep = [_d(mol.xyz), _i(mol.shell_atom), _i(mol.shell_l), _i(mol.shell_nprim),
                       _i(mol.shell_prim0), _d(mol.exps), _d(mol.coefs)]
@@ -97,6 +102,14 @@ class Basis:
                                    _pi(sp), _pd(e), _pd(c))
         if omega and lib.orc_basis_set_omega(self.h, float(omega)) != 0:
             raise ValueError("omega must be finite and >= 0")
+        self.pure = bool(pure)
+        if self.pure:
+            lib.orc_basis_set_pure(self.h, 1)
+            self.n_bf = int(lib.orc_n_bf(self.h))
+
+    def nfun(self, s: int) -> int:
+        l = int(self.shell_l[s])
+        return 5 if self.pure and l == 2 else ncart(l)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -125,9 +138,17 @@ def prim_eri(pa, a, A, pb, b, B, pc, c, C, pd, d, D, omega: float = 0.0) -> floa
     return float(_load().orc_prim_eri(*args))
 
 
+def pure_d() -> np.ndarray:
+    """C[c][m]: coefficient of Cartesian component c (xx, xy, xz, yy, yz, zz) in the
+    pure d function m (m = -2..2)."""
+    C = np.zeros((6, 5))
+    _load().orc_pure_d(_pd(C))
+    return C
+
+
 def shell_quartet(basis: Basis, A: int, B: int, C: int, D: int) -> np.ndarray:
-    l = basis.shell_l
-    shape = (ncart(int(l[A])), ncart(int(l[B])), ncart(int(l[C])), ncart(int(l[D])))
+    """Contracted block over the shells' functions (pure d where the basis has them)."""
+    shape = (basis.nfun(A), basis.nfun(B), basis.nfun(C), basis.nfun(D))
     out = np.zeros(shape)
     _load().orc_shell_quartet(basis.h, A, B, C, D, _pd(out))
     return out
@@ -147,32 +168,40 @@ def _dm(D):
     return np.ascontiguousarray(D)
 
 
-def jk(mol, tol: float, D=None, nthreads: int = 0, omega: float = 0.0):
-    """Full J, K ([n_dm][n][n]) and the number of quartets kept by screening
-    (omega > 0: of erf(omega r12)/r12, screened with the 1/r12 bounds)."""
-    b = Basis(mol, omega)
+def _dm_for(b: Basis, mol, D):
     D = _dm(mol.D if D is None else D)
+    if D.shape[1:] != (b.n_bf, b.n_bf):
+        raise ValueError(f"D must be [n_dm][{b.n_bf}][{b.n_bf}] for this basis")
+    return D
+
+
+def jk(mol, tol: float, D=None, nthreads: int = 0, omega: float = 0.0, pure: bool = False):
+    """Full J, K ([n_dm][n][n]) and the number of quartets kept by screening
+    (omega > 0: of erf(omega r12)/r12, screened with the 1/r12 bounds; pure: over
+    the pure-d basis, D given in it)."""
+    b = Basis(mol, omega, pure)
+    D = _dm_for(b, mol, D)
     J = np.zeros_like(D)
     K = np.zeros_like(D)
     kept = _load().orc_jk(b.h, D.shape[0], _pd(D), float(tol), _pd(J), _pd(K), nthreads)
     return J, K, int(kept)
 
 
-def jk_blocks(mol, tol: float, pairs, D=None, nthreads: int = 0, omega: float = 0.0):
+def jk_blocks(mol, tol: float, pairs, D=None, nthreads: int = 0, omega: float = 0.0,
+              pure: bool = False):
     """J and K blocks of the shell pairs (M, N) by the plain definitions."""
-    b = Basis(mol, omega)
-    D = _dm(mol.D if D is None else D)
+    b = Basis(mol, omega, pure)
+    D = _dm_for(b, mol, D)
     sM = _i([p[0] for p in pairs])
     sN = _i([p[1] for p in pairs])
-    l = b.shell_l
-    sizes = [D.shape[0] * ncart(int(l[m])) * ncart(int(l[n])) for m, n in pairs]
+    sizes = [D.shape[0] * b.nfun(m) * b.nfun(n) for m, n in pairs]
     Jo = np.zeros(sum(sizes))
     Ko = np.zeros(sum(sizes))
     _load().orc_jk_blocks(b.h, D.shape[0], _pd(D), float(tol), len(pairs), _pi(sM), _pi(sN),
                           _pd(Jo), _pd(Ko), nthreads)
     out, o = [], 0
     for (m, n), s in zip(pairs, sizes):
-        shp = (D.shape[0], ncart(int(l[m])), ncart(int(l[n])))
+        shp = (D.shape[0], b.nfun(m), b.nfun(n))
         out.append((Jo[o:o + s].reshape(shp), Ko[o:o + s].reshape(shp)))
         o += s
     return out

@@ -22,6 +22,8 @@
 // Basis convention: a shell is a contraction of unnormalised primitives
 // x^lx y^ly z^lz exp(-a r^2) centred on its atom; Cartesian components are
 // ordered with descending powers of x then y (xx, xy, xz, yy, yz, zz).
+// Optionally (orc_basis_set_pure) a d shell carries the five pure functions of
+// pure_d below instead, and D, J, K are over those functions.
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -189,14 +191,78 @@ struct PrimQuartet {
   }
 };
 
+// The five pure d functions, real solid harmonics of degree 2 times the shell's
+// radial part, written over the Cartesian components (xx, xy, xz, yy, yz, zz), in
+// the order m = -2, -1, 0, 1, 2:
+//   S(2,-2) = sqrt(3) xy            S(2,-1) = sqrt(3) yz
+//   S(2, 0) = zz - (xx + yy)/2      S(2, 1) = sqrt(3) xz
+//   S(2, 2) = sqrt(3)/2 (xx - yy)
+// Each has the norm of the xx component and they are mutually orthogonal and
+// free of the s-type combination xx + yy + zz.  C[c][m] = coefficient of
+// Cartesian component c in function m.
+void pure_d(double C[6][5]) {
+  const double r3 = std::sqrt(3.0);
+  for (int c = 0; c < 6; ++c)
+    for (int m = 0; m < 5; ++m) C[c][m] = 0.0;
+  C[1][0] = r3;                           // xy
+  C[4][1] = r3;                           // yz
+  C[5][2] = 1.0; C[0][2] = -0.5; C[3][2] = -0.5;
+  C[2][3] = r3;                           // xz
+  C[0][4] = 0.5 * r3; C[3][4] = -0.5 * r3;
+}
+
 struct Basis {
   int n_atoms = 0, n_shells = 0, n_bf = 0;
   double omega = 0.0;   // > 0: integrals of erf(omega r12)/r12 (screening stays Coulomb)
+  int pure = 0;         // 1: d shells carry the five pure functions of pure_d
   std::vector<double> xyz;
   std::vector<int> atom, l, nprim, prim0, bf0;
   std::vector<double> exps, coefs;
   const double* center(int s) const { return &xyz[3 * atom[s]]; }
 };
+
+int nfun(const Basis& bs, int s) { return bs.pure && bs.l[s] == 2 ? 5 : ncart(bs.l[s]); }
+
+// Coefficient of Cartesian component c in function f of shell s.
+double fun_coef(const Basis& bs, int s, int c, int f) {
+  if (!(bs.pure && bs.l[s] == 2)) return c == f ? 1.0 : 0.0;
+  double C[6][5];
+  pure_d(C);
+  return C[c][f];
+}
+
+// The Cartesian block of shells sh[0..3] over their functions:
+//   out[al be ga de] = sum_{abcd} C_A[a][al] C_B[b][be] C_C[c][ga] C_D[d][de] cart[abcd]
+// (a copy when no shell has pure functions).
+void to_functions(const Basis& bs, const int sh[4], const double* cart, double* out) {
+  int nc[4], nf[4];
+  for (int k = 0; k < 4; ++k) { nc[k] = ncart(bs.l[sh[k]]); nf[k] = nfun(bs, sh[k]); }
+  int o = 0;
+  for (int al = 0; al < nf[0]; ++al)
+    for (int be = 0; be < nf[1]; ++be)
+      for (int ga = 0; ga < nf[2]; ++ga)
+        for (int de = 0; de < nf[3]; ++de) {
+          double v = 0.0;
+          for (int a = 0; a < nc[0]; ++a) {
+            const double ca = fun_coef(bs, sh[0], a, al);
+            if (ca == 0.0) continue;
+            for (int b = 0; b < nc[1]; ++b) {
+              const double cb = fun_coef(bs, sh[1], b, be);
+              if (cb == 0.0) continue;
+              for (int c = 0; c < nc[2]; ++c) {
+                const double cc = fun_coef(bs, sh[2], c, ga);
+                if (cc == 0.0) continue;
+                for (int d = 0; d < nc[3]; ++d) {
+                  const double cd = fun_coef(bs, sh[3], d, de);
+                  if (cd == 0.0) continue;
+                  v += ca * cb * cc * cd * cart[((a * nc[1] + b) * nc[2] + c) * nc[3] + d];
+                }
+              }
+            }
+          }
+          out[o++] = v;
+        }
+}
 
 // Contracted Cartesian block (AB|CD), out[((a*nb+b)*nc+c)*nd+d].
 void shell_quartet(const Basis& bs, int sA, int sB, int sC, int sD, double* out,
@@ -324,6 +390,29 @@ double orc_prim_eri_omega(const int* pa, double a, const double* A, const int* p
 
 // Integrals of this basis handle use erf(omega r12)/r12 from here on (omega > 0), or
 // 1/r12 (omega = 0); the Schwarz bounds stay those of 1/r12, which bound both.
+// d shells with the five pure functions (pure = 1) or the six Cartesian ones
+// (pure = 0); renumbers the basis functions.  The gradient and the timing leg
+// take Cartesian bases only.
+int orc_basis_set_pure(void* h, int pure) {
+  if (pure != 0 && pure != 1) return -1;
+  Basis& b = *static_cast<Basis*>(h);
+  b.pure = pure;
+  int nbf = 0;
+  for (int s = 0; s < b.n_shells; ++s) { b.bf0[s] = nbf; nbf += nfun(b, s); }
+  b.n_bf = nbf;
+  return 0;
+}
+
+int orc_n_bf(void* h) { return static_cast<Basis*>(h)->n_bf; }
+
+// The pure-d coefficient table, C[c][m] row-major [6][5].
+void orc_pure_d(double* out) {
+  double C[6][5];
+  pure_d(C);
+  for (int c = 0; c < 6; ++c)
+    for (int m = 0; m < 5; ++m) out[c * 5 + m] = C[c][m];
+}
+
 int orc_basis_set_omega(void* h, double omega) {
   if (!(omega >= 0.0) || !std::isfinite(omega)) return -1;
   static_cast<Basis*>(h)->omega = omega;
@@ -333,7 +422,10 @@ int orc_basis_set_omega(void* h, double omega) {
 int orc_shell_quartet(void* h, int A, int B, int C, int D, double* out) {
   const Basis& bs = *static_cast<Basis*>(h);
   PrimQuartet pq;
-  shell_quartet(bs, A, B, C, D, out, pq, bs.omega);
+  std::vector<double> cart(6 * 6 * 6 * 6);
+  shell_quartet(bs, A, B, C, D, cart.data(), pq, bs.omega);
+  const int sh[4] = {A, B, C, D};
+  to_functions(bs, sh, cart.data(), out);   // over the shells' functions
   return 0;
 }
 
@@ -362,7 +454,7 @@ long long orc_jk(void* h, int n_dm, const double* D, double tol, double* J, doub
 #pragma omp parallel reduction(+ : kept)
   {
     std::vector<double> aj((size_t)n_dm * nn, 0.0), ak((size_t)n_dm * nn, 0.0);
-    std::vector<double> blk(6 * 6 * 6 * 6);
+    std::vector<double> cart(6 * 6 * 6 * 6), blk(6 * 6 * 6 * 6);
     PrimQuartet pq;
 #pragma omp for schedule(dynamic, 1)
     for (long long pi = 0; pi < npair; ++pi) {
@@ -371,13 +463,14 @@ long long orc_jk(void* h, int n_dm, const double* D, double tol, double* J, doub
         const int C = pairs[qi].A, Dd = pairs[qi].B;
         if (Q[(size_t)A * ns + B] * Q[(size_t)C * ns + Dd] < tol) continue;
         ++kept;
-        shell_quartet(bs, A, B, C, Dd, blk.data(), pq, bs.omega);
+        shell_quartet(bs, A, B, C, Dd, cart.data(), pq, bs.omega);
+        const int sh[4] = {A, B, C, Dd};
+        to_functions(bs, sh, cart.data(), blk.data());
         double f = 1.0;
         if (A == B) f *= 0.5;
         if (C == Dd) f *= 0.5;
         if (pi == qi) f *= 0.5;
-        const int na = ncart(bs.l[A]), nb = ncart(bs.l[B]), nc = ncart(bs.l[C]),
-                  nd = ncart(bs.l[Dd]);
+        const int na = nfun(bs, A), nb = nfun(bs, B), nc = nfun(bs, C), nd = nfun(bs, Dd);
         const int a0 = bs.bf0[A], b0 = bs.bf0[B], c0 = bs.bf0[C], d0 = bs.bf0[Dd];
         for (int m = 0; m < n_dm; ++m) {
           const double* Dm = D + (size_t)m * nn;
@@ -427,24 +520,26 @@ int orc_jk_blocks(void* h, int n_dm, const double* D, double tol, int nblk, cons
   const std::vector<double> Q = schwarz(bs);
   std::vector<size_t> off(nblk + 1, 0);
   for (int i = 0; i < nblk; ++i)
-    off[i + 1] = off[i] + (size_t)n_dm * ncart(bs.l[sM[i]]) * ncart(bs.l[sN[i]]);
+    off[i + 1] = off[i] + (size_t)n_dm * nfun(bs, sM[i]) * nfun(bs, sN[i]);
   if (nthreads > 0) omp_set_num_threads(nthreads);
   for (int ib = 0; ib < nblk; ++ib) {
     const int M = sM[ib], N = sN[ib];
-    const int nm = ncart(bs.l[M]), nnb = ncart(bs.l[N]);
+    const int nm = nfun(bs, M), nnb = nfun(bs, N);
     std::vector<double> jb((size_t)n_dm * nm * nnb, 0.0), kb((size_t)n_dm * nm * nnb, 0.0);
 #pragma omp parallel
     {
       std::vector<double> jl(jb.size(), 0.0), kl(kb.size(), 0.0);
-      std::vector<double> blk(6 * 6 * 6 * 6);
+      std::vector<double> cart(6 * 6 * 6 * 6), blk(6 * 6 * 6 * 6);
       PrimQuartet pq;
 #pragma omp for schedule(dynamic, 1)
       for (int L = 0; L < ns; ++L)
         for (int S = 0; S < ns; ++S) {
-          const int nl = ncart(bs.l[L]), nsg = ncart(bs.l[S]);
+          const int nl = nfun(bs, L), nsg = nfun(bs, S);
           const int l0 = bs.bf0[L], s0 = bs.bf0[S];
           if (Q[(size_t)M * ns + N] * Q[(size_t)L * ns + S] >= tol) {
-            shell_quartet(bs, M, N, L, S, blk.data(), pq, bs.omega);
+            shell_quartet(bs, M, N, L, S, cart.data(), pq, bs.omega);
+            const int sh[4] = {M, N, L, S};
+            to_functions(bs, sh, cart.data(), blk.data());
             for (int m = 0; m < n_dm; ++m)
               for (int a = 0; a < nm; ++a)
                 for (int b = 0; b < nnb; ++b) {
@@ -457,7 +552,9 @@ int orc_jk_blocks(void* h, int n_dm, const double* D, double tol, int nblk, cons
                 }
           }
           if (Q[(size_t)M * ns + L] * Q[(size_t)N * ns + S] >= tol) {
-            shell_quartet(bs, M, L, N, S, blk.data(), pq, bs.omega);
+            shell_quartet(bs, M, L, N, S, cart.data(), pq, bs.omega);
+            const int sh[4] = {M, L, N, S};
+            to_functions(bs, sh, cart.data(), blk.data());
             for (int m = 0; m < n_dm; ++m)
               for (int a = 0; a < nm; ++a)
                 for (int b = 0; b < nnb; ++b) {
@@ -494,7 +591,7 @@ int orc_jk_blocks(void* h, int n_dm, const double* D, double tol, int nblk, cons
 int orc_grad(void* h, int n_dm, const double* D, double tol, double* dEdR, int nthreads,
              long long bra_pairs, const int* atom_sel) {
   const Basis& bs = *static_cast<Basis*>(h);
-  if (n_dm < 1 || n_dm > 16 || bs.omega != 0.0) return -1;
+  if (n_dm < 1 || n_dm > 16 || bs.omega != 0.0 || bs.pure) return -1;
   const int n = bs.n_bf, ns = bs.n_shells, na_ = bs.n_atoms;
   const size_t nn = (size_t)n * n;
   const std::vector<double> Q = schwarz(bs);
@@ -588,6 +685,7 @@ int orc_grad(void* h, int n_dm, const double* D, double tol, double* dEdR, int n
 long long orc_jk_bra_sample(void* h, int n_dm, const double* D, double tol, int nbra,
                             const int* bra_idx, double* J, double* K, int nthreads) {
   const Basis& bs = *static_cast<Basis*>(h);
+  if (bs.pure) return -1;
   const int n = bs.n_bf, ns = bs.n_shells;
   const std::vector<double> Q = schwarz(bs);
   const std::vector<PairIdx> pairs = unique_pairs(ns);

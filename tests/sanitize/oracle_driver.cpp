@@ -27,6 +27,9 @@ double orc_prim_eri_omega(const int*, double, const double*, const int*, double,
                           const int*, double, const double*, const int*, double, const double*,
                           double);
 int orc_basis_set_omega(void*, double);
+int orc_basis_set_pure(void*, int);
+int orc_n_bf(void*);
+void orc_pure_d(double*);
 }
 
 static int fail(const char* what) {
@@ -123,6 +126,18 @@ int main() {
   if (orc_grad(b, n_dm, D.data(), 1e-10, g.data(), 2, -1, nullptr) == 0)
     return fail("grad must refuse omega > 0");
   if (orc_basis_set_omega(b, 0.0) != 0) return fail("basis_set_omega");
+  // pure d functions: renumbered basis, J/K over it, a quartet block, the table
+  if (orc_basis_set_pure(b, 2) == 0 || orc_basis_set_pure(b, 1) != 0) return fail("basis_set_pure");
+  const int np_ = orc_n_bf(b);
+  if (np_ != n - 2) return fail("pure basis size");
+  std::vector<double> Dp(static_cast<size_t>(np_) * np_, 0.1), Jp(Dp.size()), Kp(Dp.size());
+  if (orc_jk(b, 1, Dp.data(), 1e-10, Jp.data(), Kp.data(), 2) <= 0) return fail("pure jk");
+  std::vector<double> pblk(5 * 5 * 5 * 5), tab(30);
+  if (orc_shell_quartet(b, 2, 5, 2, 5, pblk.data()) != 0) return fail("pure shell_quartet");
+  orc_pure_d(tab.data());
+  if (orc_grad(b, 1, Dp.data(), 1e-10, g.data(), 1, -1, nullptr) == 0)
+    return fail("grad must refuse a pure basis");
+  if (orc_basis_set_pure(b, 0) != 0 || orc_n_bf(b) != n) return fail("back to Cartesian");
   long long counts[63], near[21];
   if (orc_screen_counts(b, 1e-10, 1e-4, counts, near) != 0) return fail("screen_counts");
   long long tot = 0;

@@ -538,3 +538,97 @@ def test_omega_rejected_by_gradient():
     mol = molgen.make_molecule(1, 1, seed=7)
     with pytest.raises(ValueError, match="omega"):
         oracle.grad(mol, 0.0, omega=0.3)
+
+
+# --- pure (spherical) d functions --------------------------------------------------
+
+def _cart_overlap_same_centre(l, a):
+    """S[c][c'] of x^p y^q z^r exp(-a r^2) components on one centre: products of 1-D
+    moments int x^k exp(-2 a x^2) dx by Gauss-Hermite quadrature (exact)."""
+    x, w = np.polynomial.hermite.hermgauss(8)
+    t = x / math.sqrt(2 * a)
+    mom = lambda k: float(w @ t ** k) / math.sqrt(2 * a)   # noqa: E731
+    comps = CART[l]
+    S = np.zeros((len(comps), len(comps)))
+    for i, p in enumerate(comps):
+        for j, q in enumerate(comps):
+            S[i, j] = np.prod([mom(p[k] + q[k]) for k in range(3)])
+    return S
+
+
+def test_pure_d_functions_orthonormal_and_free_of_s():
+    """The five pure d functions have the norm of the xx component, are mutually
+    orthogonal and have no overlap with the s-type combination xx + yy + zz."""
+    C = oracle.pure_d()
+    for a in (0.3, 1.7):
+        S = _cart_overlap_same_centre(2, a)
+        np.testing.assert_allclose(C.T @ S @ C, S[0, 0] * np.eye(5), rtol=1e-13, atol=1e-14 * S[0, 0])
+        r2 = np.array([1.0, 0, 0, 1.0, 0, 1.0])
+        np.testing.assert_allclose(r2 @ S @ C, 0.0, atol=1e-14 * S[0, 0])
+
+
+def test_pure_d_trace_is_rotation_invariant():
+    """sum_m (d_m d_m|s s') is unchanged when the molecule is rotated (the five
+    functions span a rotation-invariant space with equal norms); the Cartesian sum
+    over the six components is not."""
+    mol = molgen.make_molecule(2, 2, seed=17)
+    rng = np.random.default_rng(4)
+    Rm, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    rot = mol.with_xyz(mol.xyz @ Rm.T)
+    ls = np.asarray(mol.shell_l)
+    d_sh = int(np.where(ls == 2)[0][0])
+    s_sh = [int(x) for x in np.where(ls == 0)[0] if mol.shell_atom[x] != mol.shell_atom[d_sh]][:2]
+    vals = []
+    for pure in (True, False):
+        pair = []
+        for m in (mol, rot):
+            blk = oracle.shell_quartet(oracle.Basis(m, pure=pure), d_sh, d_sh, s_sh[0], s_sh[1])
+            pair.append(sum(blk[i, i, 0, 0] for i in range(blk.shape[0])))
+        vals.append(pair)
+    assert vals[0][1] == pytest.approx(vals[0][0], rel=1e-12)
+    assert abs(vals[1][1] - vals[1][0]) > 1e-6 * abs(vals[1][0])
+
+
+def _pure_transform(mol):
+    """Block-diagonal T ([n_cart][n_pure]) with the oracle's pure-d table in the d blocks."""
+    C = oracle.pure_d()
+    ls = [int(l) for l in mol.shell_l]
+    nc = [ncart for ncart in (molgen.ncart(l) for l in ls)]
+    npu = [5 if l == 2 else molgen.ncart(l) for l in ls]
+    T = np.zeros((sum(nc), sum(npu)))
+    r = c = 0
+    for l, a, b in zip(ls, nc, npu):
+        T[r:r + a, c:c + b] = C if l == 2 else np.eye(a)
+        r, c = r + a, c + b
+    return T
+
+
+@pytest.mark.parametrize("tol", [0.0, 1e-6])
+def test_pure_jk_equals_the_cartesian_build_transformed(tol):
+    """J, K over pure functions (each quartet block transformed, then digested) equal
+    T^T J_cart[T D T^T] T, K likewise, for the same screening decisions."""
+    mol = molgen.make_molecule(2, 3, seed=19, n_dm=2)
+    T = _pure_transform(mol)
+    rng = np.random.default_rng(8)
+    X = rng.normal(size=(2, T.shape[1], T.shape[1]))
+    Dp = X + X.transpose(0, 2, 1)
+    Jp, Kp, kept_p = oracle.jk(mol, tol, D=Dp, pure=True)
+    Dc = np.einsum("ia,mab,jb->mij", T, Dp, T)
+    Jc, Kc, kept_c = oracle.jk(mol, tol, D=Dc)
+    assert kept_p == kept_c
+    np.testing.assert_allclose(Jp, np.einsum("ia,mij,jb->mab", T, Jc, T), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(Kp, np.einsum("ia,mij,jb->mab", T, Kc, T), rtol=1e-12, atol=1e-12)
+    pairs = [(0, 2), (3, 3), (5, 1), (2, 7)]
+    bf0 = np.concatenate([[0], np.cumsum([5 if l == 2 else molgen.ncart(int(l)) for l in mol.shell_l])])
+    for (m, n), (jb, kb) in zip(pairs, oracle.jk_blocks(mol, tol, pairs, D=Dp, pure=True)):
+        np.testing.assert_allclose(jb, Jp[:, bf0[m]:bf0[m + 1], bf0[n]:bf0[n + 1]], rtol=1e-12,
+                                   atol=1e-12)
+        np.testing.assert_allclose(kb, Kp[:, bf0[m]:bf0[m + 1], bf0[n]:bf0[n + 1]], rtol=1e-12,
+                                   atol=1e-12)
+
+
+def test_pure_basis_rejected_by_gradient():
+    mol = molgen.make_molecule(1, 1, seed=7)
+    b = oracle.Basis(mol, pure=True)
+    assert oracle._load().orc_grad(b.h, 1, oracle._pd(np.zeros((1, b.n_bf, b.n_bf))), 0.0,
+                                   oracle._pd(np.zeros((1, b.n_atoms, 3))), 1, -1, None) == -1
