@@ -192,6 +192,33 @@ int jk_build_noalloc(jk_ctx* ctx, const jk_basis* basis, const double* D, double
 int jk_grad(jk_ctx* ctx, const jk_basis* basis, const double* D, double* dEdR, double tol,
             const jk_opts* opts, void* hip_stream);
 
+/* Pure (spherical) d functions.  The paper's workloads use bases of pure
+ * functions ("Benchmarks"); the builds above work on Cartesian shells, and these
+ * calls carry matrices between the two bases so that a pure-basis caller can use
+ * them: a d shell's five pure functions are the real solid harmonics of degree 2
+ * over its Cartesian components (xx, xy, xz, yy, yz, zz), in the order
+ *   m = -2: sqrt(3) xy,  m = -1: sqrt(3) yz,  m = 0: zz - (xx + yy)/2,
+ *   m = 1: sqrt(3) xz,   m = 2: sqrt(3)/2 (xx - yy),
+ * each with the norm of the xx component; s and p shells are the same in both
+ * bases.  Pure functions are numbered shell by shell like the Cartesian ones.
+ * With T the block-diagonal [n_cart][n_pure] matrix of these coefficients:
+ *   jk_pure_to_cart: X_cart = T X_pure T^T  (a pure density -> the D of jk_build)
+ *   jk_cart_to_pure: X_pure = T^T X_cart T  (J, K, dE/dD of jk_build -> pure)
+ * for each of n_dm (1..JK_MAX_NDM) matrices; energies need no change
+ * (tr(P T^T J T) = tr(T P T^T J)).  Input and output are DEVICE pointers
+ * ([n_dm][n_pure][n_pure] and [n_dm][n_cart][n_cart], row-major FP64) on the
+ * current HIP device and must not overlap; the work is enqueued on hip_stream
+ * (NULL = legacy default stream), which the call synchronises once (after a
+ * small table is copied to the device).  No method arithmetic beyond this
+ * change of basis.  JK_EINVAL for a bad basis, NULL pointers or n_dm out of
+ * range; JK_EUNSUPPORTED above 65535 output functions; JK_ENOMEM / JK_EHIP if
+ * the table cannot be allocated or a HIP call fails. */
+int jk_pure_count(const jk_basis* basis, int32_t* n_pure_out);
+int jk_pure_to_cart(const jk_basis* basis, int32_t n_dm, const double* X_pure, double* X_cart,
+                    void* hip_stream);
+int jk_cart_to_pure(const jk_basis* basis, int32_t n_dm, const double* X_cart, double* X_pure,
+                    void* hip_stream);
+
 /* Counters of the last successful jk_build / jk_grad.  With opts.timing = 1
  * this waits for the recorded events. */
 int jk_get_stats(jk_ctx* ctx, jk_stats* out);

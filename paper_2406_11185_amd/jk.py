@@ -23,7 +23,8 @@ JK_MAX_NDM = 16
 ERR_NAMES = {1: "JK_EINVAL", 2: "JK_EUNSUPPORTED", 3: "JK_ENOMEM", 4: "JK_EHIP"}
 
 EXPORTS = ["jk_opts_default", "jk_ctx_create", "jk_ctx_destroy", "jk_validate_basis", "jk_build",
-           "jk_build_noalloc", "jk_grad", "jk_get_stats", "jk_last_error"]
+           "jk_build_noalloc", "jk_grad", "jk_get_stats", "jk_last_error", "jk_pure_count",
+           "jk_pure_to_cart", "jk_cart_to_pure"]
 
 
 class JkError(RuntimeError):
@@ -89,6 +90,9 @@ def load():
     lib.jk_get_stats.argtypes = [vp, ctypes.POINTER(jk_stats)]
     lib.jk_last_error.argtypes = [vp]
     lib.jk_last_error.restype = ctypes.c_char_p
+    lib.jk_pure_count.argtypes = [ctypes.POINTER(jk_basis), ctypes.POINTER(ctypes.c_int32)]
+    lib.jk_pure_to_cart.argtypes = [ctypes.POINTER(jk_basis), ctypes.c_int32, vp, vp, vp]
+    lib.jk_cart_to_pure.argtypes = lib.jk_pure_to_cart.argtypes
     _lib = lib
     return lib
 
@@ -234,6 +238,39 @@ def jk_build_noalloc(ctx: Context, basis: Basis, D, J, K, tol: float,
     ctx._check(rc)
 
 
+def jk_pure_count(basis: Basis) -> int:
+    n = ctypes.c_int32(0)
+    rc = load().jk_pure_count(ctypes.byref(basis.c), ctypes.byref(n))
+    if rc != JK_OK:
+        raise JkError(rc, "invalid basis")
+    return int(n.value)
+
+
+def _change_basis(fn, basis: Basis, X, Y, stream):
+    import torch
+    s = stream if stream is not None else _stream_ptr(torch, X.device)
+    rc = fn(ctypes.byref(basis.c), int(X.shape[0]), ctypes.c_void_p(X.data_ptr()),
+            ctypes.c_void_p(Y.data_ptr()), s)
+    if rc != JK_OK:
+        raise JkError(rc, "change of basis between pure and Cartesian functions")
+
+
+def jk_pure_to_cart(basis: Basis, X_pure, X_cart, stream=None) -> None:
+    """X_cart = T X_pure T^T (device tensors [n_dm][n_pure][n_pure] -> [n_dm][n][n])."""
+    n, npu = jk_validate_basis(basis), jk_pure_count(basis)
+    _check_dev(X_pure, (X_pure.shape[0], npu, npu), "X_pure")
+    _check_dev(X_cart, (X_pure.shape[0], n, n), "X_cart")
+    _change_basis(load().jk_pure_to_cart, basis, X_pure, X_cart, stream)
+
+
+def jk_cart_to_pure(basis: Basis, X_cart, X_pure, stream=None) -> None:
+    """X_pure = T^T X_cart T (device tensors [n_dm][n][n] -> [n_dm][n_pure][n_pure])."""
+    n, npu = jk_validate_basis(basis), jk_pure_count(basis)
+    _check_dev(X_cart, (X_cart.shape[0], n, n), "X_cart")
+    _check_dev(X_pure, (X_cart.shape[0], npu, npu), "X_pure")
+    _change_basis(load().jk_cart_to_pure, basis, X_cart, X_pure, stream)
+
+
 def jk_grad(ctx: Context, basis: Basis, D, dEdR, tol: float, opts: jk_opts | None = None,
             stream=None) -> None:
     import torch
@@ -246,17 +283,24 @@ def jk_grad(ctx: Context, basis: Basis, D, dEdR, tol: float, opts: jk_opts | Non
 
 def jk(mol, D, tol: float, precision: str = "fp64", fp32_below: float = 1e-4,
        timing: bool = False, ctx: Context | None = None, energies: bool = False,
-       dEdD: bool = False, **opt):
+       dEdD: bool = False, pure: bool = False, **opt):
     """J, K for the densities D ([n][n] or [n_dm][n][n] float64 CUDA tensor).
 
     energies=True adds E ([n_dm][3]: E_J, E_K, E_J - E_K, from the library's
-    finalize step); dEdD=True adds dE/dD = J - K/2 (same shape as J).  Extra
-    keywords go to make_opts (deterministic, acc_copies, serial, omega, ...)."""
+    finalize step); dEdD=True adds dE/dD = J - K/2 (same shape as J).  pure=True:
+    D, J, K and dE/dD are over pure d functions (jk_pure_to_cart, jk_build,
+    jk_cart_to_pure in turn).  Extra keywords go to make_opts (deterministic,
+    acc_copies, serial, omega, ...)."""
     import torch
     basis = mol if isinstance(mol, Basis) else Basis(mol)
     squeeze = D.dim() == 2
     Dd = D.unsqueeze(0) if squeeze else D
     Dd = Dd.contiguous()
+    if pure:
+        Dp = Dd
+        n = jk_validate_basis(basis)
+        Dd = torch.empty((Dp.shape[0], n, n), dtype=torch.float64, device=Dp.device)
+        jk_pure_to_cart(basis, Dp, Dd)
     n_dm, n = Dd.shape[0], Dd.shape[1]
     _check_dev(Dd, (n_dm, n, n), "D")
     ctx = ctx or default_context(Dd.device.index or 0)
@@ -266,6 +310,15 @@ def jk(mol, D, tol: float, precision: str = "fp64", fp32_below: float = 1e-4,
     G = torch.empty_like(Dd) if dEdD else None
     opts = make_opts(precision, fp32_below, n_dm, timing, energy=E, dEdD=G, **opt)
     jk_build(ctx, basis, Dd, J, K, tol, opts)
+    if pure:
+        mats = [J, K] + ([G] if dEdD else [])
+        for i, X in enumerate(mats):
+            Y = torch.empty_like(Dp)
+            jk_cart_to_pure(basis, X, Y)
+            mats[i] = Y
+        J, K = mats[0], mats[1]
+        if dEdD:
+            G = mats[2]
     out = [J[0], K[0]] if squeeze else [J, K]
     if energies:
         out.append(E[0] if squeeze else E)

@@ -1,4 +1,5 @@
-"""Build tests/bin/jk_asan_driver: the library's host translation unit and the driver
+"""Build tests/bin/jk_asan_driver: the library's host translation units (jk_host.hip,
+jk_pure.hip) and the driver
 (tests/sanitize/jk_driver.cpp) with host-side AddressSanitizer and
 UndefinedBehaviorSanitizer, linked with the per-class objects of the regular build
 (_build/obj, so run `python -m paper_2406_11185_amd.build` first).  Device code is
@@ -28,12 +29,13 @@ def build() -> str:
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", *HOST_SAN, *inc]
     objs = []
     for src, extra in ((os.path.join(ROOT, "paper_2406_11185_amd", "csrc", "jk_host.hip"), []),
+                       (os.path.join(ROOT, "paper_2406_11185_amd", "csrc", "jk_pure.hip"), []),
                        (os.path.join(HERE, "jk_driver.cpp"), ["-x", "hip"])):
         obj = os.path.join(os.path.dirname(OUT), os.path.basename(src) + ".asan.o")
         subprocess.run([HIPCC, *common, *extra, "-c", src, "-o", obj], check=True)
         objs.append(obj)
     others = sorted(os.path.join(OBJ, f) for f in os.listdir(OBJ)
-                    if f.endswith(".o") and f != "jk_host.o")
+                    if f.endswith(".o") and f not in ("jk_host.o", "jk_pure.o"))
     link = [HIPCC, "--offload-arch=gfx950", "-fno-gpu-sanitize", "-fsanitize=address,undefined"]
     subprocess.run([*link, *objs, *others, "-o", OUT], check=True)
     for o in objs:

@@ -11,7 +11,8 @@
 // Cases: FP64; mixed; deterministic with reuse_setup (second call, which must
 // reuse the setup); jk_build_noalloc; one accumulator copy with energies and
 // dE/dD (checked against J and K here); FP64 at omega = 0.3 (erf(omega r12)/r12);
-// timing and jk_get_stats.  Exit status 0
+// FP64 again; timing and jk_get_stats.  Between the last two, the pure-function
+// transforms are checked in the driver by a trace identity.  Exit status 0
 // when every call succeeds and every in-driver check holds.
 #include <hip/hip_runtime.h>
 
@@ -135,6 +136,41 @@ int main(int argc, char** argv) {
   ow.omega = 0.3;
   if (jk_build(c, &b, D, J, K, tol, &ow, nullptr) != JK_OK || !emit()) return fail("omega", c);
   if (jk_grad(c, &b, D, G, tol, &ow, nullptr) != JK_EUNSUPPORTED) return fail("grad at omega", c);
+  // pure d functions: with P the leading pure-sized block of D (symmetric),
+  // tr(P T^T J T) = tr(T P T^T J) for the FP64 J of the last build
+  int32_t npu = 0;
+  if (jk_pure_count(&b, &npu) != JK_OK || npu > n) return fail("jk_pure_count");
+  if (jk_build(c, &b, D, J, K, tol, &o, nullptr) != JK_OK || !emit()) return fail("fp64 again", c);
+  {
+    const size_t pm = static_cast<size_t>(n_dm) * npu * npu;
+    std::vector<double> Ph(pm), Jp(pm), Xc(mat);
+    for (int m = 0; m < n_dm; ++m)
+      for (int i = 0; i < npu; ++i)
+        for (int j = 0; j < npu; ++j)
+          Ph[(static_cast<size_t>(m) * npu + i) * npu + j] = Dh[(static_cast<size_t>(m) * n + i) * n + j];
+    double *P = nullptr, *Pj = nullptr;
+    if (hipMalloc(&P, pm * 8) != hipSuccess || hipMalloc(&Pj, pm * 8) != hipSuccess) return fail("hipMalloc");
+    if (hipMemcpy(P, Ph.data(), pm * 8, hipMemcpyHostToDevice) != hipSuccess) return fail("copy P");
+    if (jk_pure_to_cart(&b, n_dm, P, G, nullptr) != JK_OK ||
+        jk_cart_to_pure(&b, n_dm, J, Pj, nullptr) != JK_OK || hipDeviceSynchronize() != hipSuccess)
+      return fail("pure transforms");
+    if (hipMemcpy(Xc.data(), G, mat * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(Jp.data(), Pj, pm * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail("copy pure results");
+    for (int m = 0; m < n_dm; ++m) {
+      double a = 0.0, bsum = 0.0, scale = 0.0;
+      for (size_t t = 0; t < static_cast<size_t>(npu) * npu; ++t) {
+        a += Ph[m * static_cast<size_t>(npu) * npu + t] * Jp[m * static_cast<size_t>(npu) * npu + t];
+        scale += std::fabs(Ph[m * static_cast<size_t>(npu) * npu + t] * Jp[m * static_cast<size_t>(npu) * npu + t]);
+      }
+      for (size_t t = 0; t < static_cast<size_t>(n) * n; ++t)
+        bsum += Xc[m * static_cast<size_t>(n) * n + t] * hj[m * static_cast<size_t>(n) * n + t];
+      if (std::fabs(a - bsum) > 1e-12 * std::fmax(1.0, scale)) return fail("pure trace identity");
+    }
+    if (jk_pure_to_cart(&b, 0, P, G, nullptr) != JK_EINVAL) return fail("pure n_dm check");
+    (void)hipFree(P);
+    (void)hipFree(Pj);
+  }
   // timing and statistics
   jk_opts ot = o;
   ot.timing = 1;

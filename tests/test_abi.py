@@ -109,3 +109,12 @@ def test_null_arguments():
     b = jkb.Basis(molgen.workload("w4"))
     b.c.n_shells = 0
     assert lib.jk_validate_basis(ctypes.byref(b.c), None) == jkb.JK_EINVAL
+
+
+def test_pure_count_on_the_host():
+    """jk_pure_count: 2l + 1 functions per shell, a bad basis rejected (no GPU)."""
+    for w in ("w4", "w30"):
+        mol = molgen.workload(w)
+        want = int(sum(2 * int(l) + 1 for l in mol.shell_l))
+        assert jkb.jk_pure_count(jkb.Basis(mol)) == want
+    assert jkb.load().jk_pure_count(None, None) == jkb.JK_EINVAL

@@ -2,9 +2,10 @@
 real device.  tests/bin/jk_asan_driver (built by tests/sanitize/build_jk_asan.py: the
 host translation unit and the driver instrumented, device code as usual) runs FP64,
 mixed, deterministic with a kept setup, the allocation-free entry, the single-copy
-path with energies and dE/dD (checked in the driver), FP64 at omega = 0.3 and timing
-with statistics, all through the C ABI; any memory or undefined-behaviour error aborts
-it.  Its J and K are compared with the oracle."""
+path with energies and dE/dD (checked in the driver), FP64 at omega = 0.3, the
+pure-function transforms (a trace identity checked in the driver) and timing with
+statistics, all through the C ABI; any memory or undefined-behaviour error aborts it.
+Its J and K are compared with the oracle."""
 import os
 import subprocess
 
@@ -17,7 +18,8 @@ from paper_2406_11185_amd import molgen
 
 pytestmark = pytest.mark.gpu
 EXE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "bin", "jk_asan_driver")
-CASES = ["fp64", "mixed", "deterministic, kept setup", "allocation-free", "one copy", "omega 0.3"]
+CASES = ["fp64", "mixed", "deterministic, kept setup", "allocation-free", "one copy", "omega 0.3",
+         "fp64 again"]
 
 
 def write_input(path, mol, tol):
