@@ -233,7 +233,8 @@ def extra_measurements(args, jkb, molgen, ctx, mol, basis, D, J, K, E_head, tol,
                        ms_per_step, torch):
     """The same build in the other precision (time, speedup, energy differences),
     the paper's own FP32 threshold (tolerance x 1e5), the long-range build of a
-    range-separated hybrid (omega = 0.3), and the nuclear gradient:
+    range-separated hybrid (omega = 0.3), the SCF steps beside the build
+    (diagonalisation, DIIS), and the nuclear gradient:
     of the 30-atom molecule, or of the workload itself (autograd through
     JKEnergy) when it carries several densities."""
     import numpy as np
@@ -283,6 +284,36 @@ def extra_measurements(args, jkb, molgen, ctx, mol, basis, D, J, K, E_head, tol,
             "precision": precision, "ms": 1e3 * t4, "time_over_1_r12_build": 1e3 * t4 / ms_per_step,
             "E_J": float(E4[0, 0]), "E_K": float(E4[0, 1])}
         progress("long-range (omega 0.3) build done")
+    if n_dm == 1:
+        # the SCF steps beside the build at the workload's size: Roothaan
+        # diagonalisation with the density (n_occ = n/4) and one DIIS step over a
+        # full history of 8 pairs; F = J - K/2 of the last build above, S a seeded
+        # overlap-like positive-definite matrix
+        import math
+        n = int(D.shape[1])
+        rng = np.random.default_rng(7)
+        X = rng.normal(size=(n, n)) * 0.3 / math.sqrt(n)
+        S = torch.as_tensor(1.3 * np.eye(n) + 0.5 * (X + X.T), device=dev)
+        F = (J[0] - 0.5 * K[0]).contiguous()
+        h = jkb.ScfSteps(n, depth=8)
+        h.diag(F, S, n // 4)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            _, _, Dn = h.diag(F, S, n // 4)
+        torch.cuda.synchronize()
+        diag_ms = 1e3 * (time.perf_counter() - t) / 3
+        for _ in range(8):
+            h.diis(F, Dn, S)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            h.diis(F, Dn, S)
+        torch.cuda.synchronize()
+        ex["scf_steps"] = {"n": n, "diag_with_density_ms": diag_ms,
+                           "diis_depth8_ms": 1e3 * (time.perf_counter() - t) / 3}
+        h.close()
+        progress("SCF steps (diagonalisation, DIIS) done")
     if n_dm == 1 and args.with_grad:
         # nuclear gradient of the 30-atom molecule, FP64 and mixed
         mg = molgen.workload("w30grad")

@@ -219,6 +219,35 @@ int jk_pure_to_cart(const jk_basis* basis, int32_t n_dm, const double* X_pure, d
 int jk_cart_to_pure(const jk_basis* basis, int32_t n_dm, const double* X_cart, double* X_pure,
                     void* hip_stream);
 
+/* The SCF steps beside the build, on the GPU (paper, "Key Components Redesign and
+ * Implementation", SCF-iteration paragraph; "DFT Calculation Flow"): the
+ * Roothaan diagonalisation with the closed-shell density, and Pulay's DIIS
+ * extrapolation.  A jk_scf handle (one device, one size n, a DIIS history of
+ * `depth` pairs) owns a rocBLAS handle and workspace for ~(2 depth + 3) n^2
+ * doubles.  All matrices are DEVICE pointers, [n][n] row-major FP64, symmetric
+ * where stated; calls on one handle must not overlap; the work is enqueued on
+ * hip_stream (NULL = legacy default), and each call synchronises that stream
+ * once (to read the solver's status).
+ *
+ * jk_scf_create: JK_EINVAL unless 1 <= n <= 46340 and 1 <= depth <= 32.
+ * jk_scf_diag: solves F C = S C diag(eps) for symmetric F and symmetric
+ *   positive-definite S.  eps [n] ascending (required); C [n][n] (optional):
+ *   row j = orbital j, S-orthonormal (C S C^T = I); D [n][n] (optional) =
+ *   2 sum_{j < n_occ} c_j c_j^T.  JK_EINVAL if S is not positive definite.
+ * jk_scf_diis: stores (F, D) with its error e = F D S - S D F (replacing the
+ *   oldest pair once depth are stored) and writes F_out = sum_i c_i F_i over the
+ *   stored pairs, c minimising |sum_i c_i e_i| with sum_i c_i = 1; if that
+ *   system is singular, F_out = F.  err_out (optional, DEVICE, 1 double) =
+ *   max |e| of the new pair.  jk_scf_diis_reset empties the history. */
+typedef struct jk_scf jk_scf;
+int jk_scf_create(jk_scf** out, int device, int32_t n, int32_t depth);
+int jk_scf_destroy(jk_scf* scf);
+int jk_scf_diag(jk_scf* scf, const double* F, const double* S, int32_t n_occ, double* C,
+                double* eps, double* D, void* hip_stream);
+int jk_scf_diis(jk_scf* scf, const double* F, const double* D, const double* S, double* F_out,
+                double* err_out, void* hip_stream);
+int jk_scf_diis_reset(jk_scf* scf);
+
 /* Counters of the last successful jk_build / jk_grad.  With opts.timing = 1
  * this waits for the recorded events. */
 int jk_get_stats(jk_ctx* ctx, jk_stats* out);

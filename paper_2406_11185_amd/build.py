@@ -96,6 +96,7 @@ def _build_locked(jobs: int, verbose: bool, incremental: bool) -> str:
     shutil.copyfile(os.path.join(GEN, "classes.json"), os.path.join(PKG, "classes.json"))
     shutil.copyfile(os.path.join(GEN, "grad_classes.json"), os.path.join(PKG, "grad_classes.json"))
     sources = [os.path.join(CSRC, "jk_host.hip"), os.path.join(CSRC, "jk_pure.hip"),
+               os.path.join(CSRC, "jk_scf.hip"),
                os.path.join(GEN, "jk_classes_table.hip"),
                os.path.join(GEN, "jk_grad_table.hip")]
     sources += sorted(os.path.join(GEN, f) for f in os.listdir(GEN)
@@ -111,7 +112,8 @@ def _build_locked(jobs: int, verbose: bool, incremental: bool) -> str:
             if verbose:
                 print(f"  {os.path.basename(src)}: {dt:.1f}s", flush=True)
     tmp = f"{LIB}.{os.getpid()}.tmp"
-    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs,
+           "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

@@ -24,7 +24,8 @@ ERR_NAMES = {1: "JK_EINVAL", 2: "JK_EUNSUPPORTED", 3: "JK_ENOMEM", 4: "JK_EHIP"}
 
 EXPORTS = ["jk_opts_default", "jk_ctx_create", "jk_ctx_destroy", "jk_validate_basis", "jk_build",
            "jk_build_noalloc", "jk_grad", "jk_get_stats", "jk_last_error", "jk_pure_count",
-           "jk_pure_to_cart", "jk_cart_to_pure"]
+           "jk_pure_to_cart", "jk_cart_to_pure", "jk_scf_create", "jk_scf_destroy", "jk_scf_diag",
+           "jk_scf_diis", "jk_scf_diis_reset"]
 
 
 class JkError(RuntimeError):
@@ -93,6 +94,11 @@ def load():
     lib.jk_pure_count.argtypes = [ctypes.POINTER(jk_basis), ctypes.POINTER(ctypes.c_int32)]
     lib.jk_pure_to_cart.argtypes = [ctypes.POINTER(jk_basis), ctypes.c_int32, vp, vp, vp]
     lib.jk_cart_to_pure.argtypes = lib.jk_pure_to_cart.argtypes
+    lib.jk_scf_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int32, ctypes.c_int32]
+    lib.jk_scf_destroy.argtypes = [vp]
+    lib.jk_scf_diag.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp, vp]
+    lib.jk_scf_diis.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.jk_scf_diis_reset.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -269,6 +275,63 @@ def jk_cart_to_pure(basis: Basis, X_cart, X_pure, stream=None) -> None:
     _check_dev(X_cart, (X_cart.shape[0], n, n), "X_cart")
     _check_dev(X_pure, (X_cart.shape[0], npu, npu), "X_pure")
     _change_basis(load().jk_cart_to_pure, basis, X_cart, X_pure, stream)
+
+
+class ScfSteps:
+    """A jk_scf handle: Roothaan diagonalisation and DIIS on the GPU for [n][n]
+    float64 CUDA tensors (jk_scf_diag, jk_scf_diis)."""
+
+    def __init__(self, n: int, depth: int = 8, device: int = 0):
+        h = ctypes.c_void_p()
+        rc = load().jk_scf_create(ctypes.byref(h), int(device), int(n), int(depth))
+        if rc != JK_OK:
+            raise JkError(rc, "jk_scf_create")
+        self.h, self.n, self.device = h, int(n), int(device)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().jk_scf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def diag(self, F, S, n_occ: int, vectors: bool = True, density: bool = True):
+        """(eps [n], C [n][n] with row j = orbital j or None, D or None)."""
+        import torch
+        n = self.n
+        _check_dev(F, (n, n), "F")
+        _check_dev(S, (n, n), "S")
+        eps = torch.empty(n, dtype=torch.float64, device=F.device)
+        C = torch.empty_like(F) if vectors else None
+        D = torch.empty_like(F) if density else None
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
+        rc = load().jk_scf_diag(self.h, ptr(F), ptr(S), int(n_occ), ptr(C), ptr(eps), ptr(D),
+                                _stream_ptr(torch, F.device))
+        if rc != JK_OK:
+            raise JkError(rc, "jk_scf_diag")
+        return eps, C, D
+
+    def diis(self, F, D, S):
+        """(extrapolated F, max |F D S - S D F| as a 1-element device tensor)."""
+        import torch
+        n = self.n
+        for t, name in ((F, "F"), (D, "D"), (S, "S")):
+            _check_dev(t, (n, n), name)
+        Fo = torch.empty_like(F)
+        err = torch.empty(1, dtype=torch.float64, device=F.device)
+        rc = load().jk_scf_diis(self.h, ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(D.data_ptr()),
+                                ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(Fo.data_ptr()),
+                                ctypes.c_void_p(err.data_ptr()), _stream_ptr(torch, F.device))
+        if rc != JK_OK:
+            raise JkError(rc, "jk_scf_diis")
+        return Fo, err
+
+    def reset(self):
+        load().jk_scf_diis_reset(self.h)
 
 
 def jk_grad(ctx: Context, basis: Basis, D, dEdR, tol: float, opts: jk_opts | None = None,

@@ -36,7 +36,8 @@ def build() -> str:
         objs.append(obj)
     others = sorted(os.path.join(OBJ, f) for f in os.listdir(OBJ)
                     if f.endswith(".o") and f not in ("jk_host.o", "jk_pure.o"))
-    link = [HIPCC, "--offload-arch=gfx950", "-fno-gpu-sanitize", "-fsanitize=address,undefined"]
+    link = [HIPCC, "--offload-arch=gfx950", "-fno-gpu-sanitize", "-fsanitize=address,undefined",
+            "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     subprocess.run([*link, *objs, *others, "-o", OUT], check=True)
     for o in objs:
         os.remove(o)
