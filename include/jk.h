@@ -248,6 +248,27 @@ int jk_scf_diis(jk_scf* scf, const double* F, const double* D, const double* S, 
                 double* err_out, void* hip_stream);
 int jk_scf_diis_reset(jk_scf* scf);
 
+/* Grid part of the exchange-correlation integration (paper, "Key Components
+ * Redesign and Implementation", EXC paragraph): basis-function values on the grid
+ * points with distance-based sparsity (a shell is skipped beyond the radius where
+ * r^l sum_k |c_k| exp(-a_k r^2) falls below eps), stored in 32 x 32 blocks of
+ * functions x points, a block left out when all its values are below eps, and
+ * block-sparse matrix products:
+ *   jk_xc_rho:  rho[m][g] = sum_{mu,nu} phi_mu(g) D[m][mu][nu] phi_nu(g)
+ *   jk_xc_vmat: V[mu][nu] = sum_g wv[g] phi_mu(g) phi_nu(g)   (symmetric)
+ * with wv = grid weight times the functional's potential (the functional is the
+ * caller's).  grid: DEVICE [n_grid][3] points (bohr); D: DEVICE [n_dm][n_bf][n_bf]
+ * (symmetric), rho: DEVICE [n_dm][n_grid]; wv: DEVICE [n_grid]; V: DEVICE
+ * [n_bf][n_bf]; Cartesian functions as in jk_build.  eps in (0, 1) (the paper's
+ * default 1e-12).  Points are processed in batches of 32768; the call allocates its
+ * workspace (about n_bf x 32768 doubles) stream-ordered on the current device, and
+ * synchronises hip_stream once (after copying the shell table).  JK_EINVAL for a bad
+ * basis, pointer, count or eps; JK_ENOMEM / JK_EHIP on allocation or HIP failure. */
+int jk_xc_rho(const jk_basis* basis, const double* grid, int32_t n_grid, const double* D,
+              int32_t n_dm, double eps, double* rho, void* hip_stream);
+int jk_xc_vmat(const jk_basis* basis, const double* grid, int32_t n_grid, const double* wv,
+               double eps, double* V, void* hip_stream);
+
 /* Counters of the last successful jk_build / jk_grad.  With opts.timing = 1
  * this waits for the recorded events. */
 int jk_get_stats(jk_ctx* ctx, jk_stats* out);

@@ -96,7 +96,7 @@ def _build_locked(jobs: int, verbose: bool, incremental: bool) -> str:
     shutil.copyfile(os.path.join(GEN, "classes.json"), os.path.join(PKG, "classes.json"))
     shutil.copyfile(os.path.join(GEN, "grad_classes.json"), os.path.join(PKG, "grad_classes.json"))
     sources = [os.path.join(CSRC, "jk_host.hip"), os.path.join(CSRC, "jk_pure.hip"),
-               os.path.join(CSRC, "jk_scf.hip"),
+               os.path.join(CSRC, "jk_scf.hip"), os.path.join(CSRC, "jk_xc.hip"),
                os.path.join(GEN, "jk_classes_table.hip"),
                os.path.join(GEN, "jk_grad_table.hip")]
     sources += sorted(os.path.join(GEN, f) for f in os.listdir(GEN)

@@ -1,0 +1,378 @@
+// Grid part of the exchange-correlation integration (paper, "Key Components
+// Redesign and Implementation", EXC paragraph): the AO matrix on the grid with
+// distance-based sparsity, then the density on the grid and the XC matrix as
+// block-sparse matrix products over 32 x 32 blocks.  The functional itself (the
+// potential at each point) is the caller's.
+//
+//   phi[mu][g]  basis function mu at grid point g.  A shell is skipped at points
+//               farther from its atom than its cut-off radius, beyond which the
+//               bound r^l sum_k |c_k| exp(-a_k r^2) of every component is below eps.
+//   blocks      phi is stored dense in 32 x 32 blocks (32 functions x 32 points);
+//               a block is zero when all its values are below eps and is then
+//               left out of every product.
+//   rho_g     = sum_{mu,nu} phi_mu(g) D_mu,nu phi_nu(g): per grid block G and
+//               each nonzero AO block I of G, X_IG = sum_J D_IJ phi_JG over the
+//               nonzero J of G, then the column sums of phi_IG * X_IG, reduced over
+//               I in a fixed order.
+//   V_mu,nu   = sum_g wv_g phi_mu(g) phi_nu(g): per block pair I >= J, the sum over
+//               the grid blocks where both are nonzero of phi_IG diag(wv_G) phi_JG^T;
+//               the upper triangle by symmetry.
+//
+// Layout in HBM per batch of grid points: phi [NA][GB] row-major (NA = n_ao
+// rounded up to 32, GB = points of the batch rounded up to 32), the block mask
+// [NA/32][GB/32] and per grid block the list of its nonzero AO blocks.  The tile
+// products run on the vector FP64 units (the FP64 matrix rate of this chip is the
+// same as the vector rate), one wavefront per 32 x 32 output tile, each lane
+// holding 4 x 4 outputs, operands staged in LDS.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "jk.h"
+
+namespace {
+
+constexpr int kB = 32;            // block edge (functions and points)
+constexpr int kBatch = 32768;     // grid points per batch
+constexpr int kWaveT = 64;
+
+struct XcShell {
+  double x, y, z;      // centre
+  double rcut2;        // squared cut-off radius
+  int l, nprim, bf0, prim0;
+};
+
+// Values of shell s at point g of the batch, into phi rows bf0.. (zero beyond the
+// cut-off radius or past the batch's end).
+__global__ void ao_kernel(const XcShell* __restrict__ sh, const double* __restrict__ exps,
+                          const double* __restrict__ coefs, const double* __restrict__ grid,
+                          int g0, int ng, int GB, double* __restrict__ phi) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (g >= GB) return;
+  const XcShell S = sh[s];
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  if (g < ng) {
+    const double dx = grid[3 * static_cast<size_t>(g0 + g)] - S.x;
+    const double dy = grid[3 * static_cast<size_t>(g0 + g) + 1] - S.y;
+    const double dz = grid[3 * static_cast<size_t>(g0 + g) + 2] - S.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 <= S.rcut2) {
+      double rad = 0.0;
+      for (int k = 0; k < S.nprim; ++k) rad += coefs[S.prim0 + k] * exp(-exps[S.prim0 + k] * r2);
+      if (S.l == 0) {
+        v[0] = rad;
+      } else if (S.l == 1) {
+        v[0] = dx * rad; v[1] = dy * rad; v[2] = dz * rad;
+      } else {   // xx, xy, xz, yy, yz, zz
+        v[0] = dx * dx * rad; v[1] = dx * dy * rad; v[2] = dx * dz * rad;
+        v[3] = dy * dy * rad; v[4] = dy * dz * rad; v[5] = dz * dz * rad;
+      }
+    }
+  }
+  const int nc = (S.l + 1) * (S.l + 2) / 2;
+  for (int c = 0; c < nc; ++c) phi[static_cast<size_t>(S.bf0 + c) * GB + g] = v[c];
+}
+
+__global__ void fill_kernel(double* p, size_t count, double v) {
+  const size_t k = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k < count) p[k] = v;
+}
+
+// Block mask: one wavefront per block (I = blockIdx.y, G = blockIdx.x).
+__global__ __launch_bounds__(kWaveT) void mask_kernel(const double* __restrict__ phi, int GB,
+                                                      double eps, unsigned char* __restrict__ mask) {
+  const int G = blockIdx.x, I = blockIdx.y, t = threadIdx.x;
+  double m = 0.0;
+  for (int e = t; e < kB * kB; e += kWaveT) {
+    const int i = e / kB, g = e % kB;
+    m = fmax(m, fabs(phi[static_cast<size_t>(I * kB + i) * GB + G * kB + g]));
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if (t == 0) mask[static_cast<size_t>(I) * gridDim.x + G] = m >= eps ? 1 : 0;
+}
+
+// Nonzero AO blocks of each grid block, in increasing order.
+__global__ void list_kernel(const unsigned char* __restrict__ mask, int nIb, int nGb,
+                            int* __restrict__ list, int* __restrict__ count) {
+  const int G = blockIdx.x * blockDim.x + threadIdx.x;
+  if (G >= nGb) return;
+  int c = 0;
+  for (int I = 0; I < nIb; ++I)
+    if (mask[static_cast<size_t>(I) * nGb + G]) list[static_cast<size_t>(G) * nIb + c++] = I;
+  count[G] = c;
+}
+
+// One 32 x 32 tile product per wavefront: lane t holds rows 4 (t / 8) .. +3 and
+// columns 4 (t % 8) .. +3 of the output; a[k][i] (k-major) and b[k][j] in LDS.
+__device__ __forceinline__ void tile_fma(const double (*a)[kB], const double (*b)[kB], int t,
+                                         double acc[4][4]) {
+  const int r0 = 4 * (t >> 3), c0 = 4 * (t & 7);
+#pragma unroll 8
+  for (int k = 0; k < kB; ++k) {
+    const double2 a01 = *reinterpret_cast<const double2*>(&a[k][r0]);
+    const double2 a23 = *reinterpret_cast<const double2*>(&a[k][r0 + 2]);
+    const double2 b01 = *reinterpret_cast<const double2*>(&b[k][c0]);
+    const double2 b23 = *reinterpret_cast<const double2*>(&b[k][c0 + 2]);
+    const double av[4] = {a01.x, a01.y, a23.x, a23.y}, bv[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
+  }
+}
+
+// rho partials: workgroup (G = blockIdx.x, k = blockIdx.y) takes AO block I =
+// list[G][k]; X_IG = sum over J in list[G] of D_IJ phi_JG; partial[G][k][g] =
+// sum_i phi_IG[i][g] X_IG[i][g].
+__global__ __launch_bounds__(kWaveT) void rho_kernel(const double* __restrict__ phi, int GB,
+                                                     const double* __restrict__ D, int n,
+                                                     const int* __restrict__ list,
+                                                     const int* __restrict__ count, int nIb,
+                                                     double* __restrict__ partial) {
+  const int G = blockIdx.x, k = blockIdx.y, t = threadIdx.x;
+  const int cnt = count[G];
+  if (k >= cnt) return;
+  const int I = list[static_cast<size_t>(G) * nIb + k];
+  __shared__ __attribute__((aligned(16))) double a[kB][kB];   // a[jj][i] = D[I*32+i][J*32+jj]
+  __shared__ __attribute__((aligned(16))) double b[kB][kB];   // b[jj][g] = phi[J*32+jj][G*32+g]
+  double acc[4][4] = {};
+  for (int q = 0; q < cnt; ++q) {
+    const int J = list[static_cast<size_t>(G) * nIb + q];
+    for (int e = t; e < kB * kB; e += kWaveT) {
+      const int r = e / kB, c = e % kB;
+      // a[r][c] = D[I*32+c][J*32+r], read as D[J*32+r][I*32+c] (D symmetric) so
+      // that consecutive lanes read consecutive columns
+      const int row = J * kB + r, col = I * kB + c;
+      a[r][c] = row < n && col < n ? D[static_cast<size_t>(row) * n + col] : 0.0;
+      b[r][c] = phi[static_cast<size_t>(J * kB + r) * GB + G * kB + c];
+    }
+    __syncthreads();
+    tile_fma(a, b, t, acc);
+    __syncthreads();
+  }
+  // column sums of phi_IG * X_IG
+  const int r0 = 4 * (t >> 3), c0 = 4 * (t & 7);
+  double part[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      part[c] += phi[static_cast<size_t>(I * kB + r0 + r) * GB + G * kB + c0 + c] * acc[r][c];
+  __shared__ double red[8][kB];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) red[t >> 3][c0 + c] = part[c];
+  __syncthreads();
+  if (t < kB) {
+    double s = 0.0;
+    for (int q = 0; q < 8; ++q) s += red[q][t];
+    partial[(static_cast<size_t>(G) * nIb + k) * kB + t] = s;
+  }
+}
+
+// rho of the batch's points: fixed-order sum of the partials of its grid block.
+__global__ void rho_reduce_kernel(const double* __restrict__ partial, const int* __restrict__ count,
+                                  int nIb, int ng, double* __restrict__ rho) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  const int G = g / kB;
+  double s = 0.0;
+  for (int k = 0; k < count[G]; ++k) s += partial[(static_cast<size_t>(G) * nIb + k) * kB + g % kB];
+  rho[g] = s;
+}
+
+// V_acc[I][J] (I >= J) += sum over grid blocks G with both blocks nonzero of
+// phi_IG diag(wv_G) phi_JG^T; workgroup (I = blockIdx.y, J = blockIdx.x).
+__global__ __launch_bounds__(kWaveT) void vmat_kernel(const double* __restrict__ phi, int GB,
+                                                      const unsigned char* __restrict__ mask,
+                                                      int nGb, const double* __restrict__ wv,
+                                                      int g0, int ng, int NA,
+                                                      double* __restrict__ vacc) {
+  const int J = blockIdx.x, I = blockIdx.y, t = threadIdx.x;
+  if (I < J) return;
+  __shared__ __attribute__((aligned(16))) double a[kB][kB];   // a[g][i] = phi[I*32+i][G*32+g]
+  __shared__ __attribute__((aligned(16))) double b[kB][kB];   // b[g][j] = wv[g] phi[J*32+j][G*32+g]
+  double acc[4][4] = {};
+  bool any = false;
+  for (int G = 0; G < nGb; ++G) {
+    if (!(mask[static_cast<size_t>(I) * nGb + G] && mask[static_cast<size_t>(J) * nGb + G])) continue;
+    any = true;
+    for (int e = t; e < kB * kB; e += kWaveT) {
+      const int i = e / kB, g = e % kB;
+      const int gg = G * kB + g;
+      const double w = gg < ng ? wv[g0 + gg] : 0.0;
+      a[g][i] = phi[static_cast<size_t>(I * kB + i) * GB + gg];
+      b[g][i] = w * phi[static_cast<size_t>(J * kB + i) * GB + gg];
+    }
+    __syncthreads();
+    tile_fma(a, b, t, acc);
+    __syncthreads();
+  }
+  if (!any) return;
+  const int r0 = 4 * (t >> 3), c0 = 4 * (t & 7);
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      vacc[static_cast<size_t>(I * kB + r0 + r) * NA + J * kB + c0 + c] += acc[r][c];
+}
+
+// V from the lower triangle of V_acc (mu >= nu lies in a block pair I >= J), so
+// that V is exactly symmetric.
+__global__ void vmat_finish_kernel(const double* __restrict__ vacc, int NA, int n,
+                                   double* __restrict__ V) {
+  const size_t e = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= static_cast<size_t>(n) * n) return;
+  const int mu = static_cast<int>(e / n), nu = static_cast<int>(e % n);
+  V[e] = mu >= nu ? vacc[static_cast<size_t>(mu) * NA + nu] : vacc[static_cast<size_t>(nu) * NA + mu];
+}
+
+// Cut-off radius of a shell: the largest r with r^l sum_k |c_k| exp(-a_k r^2) >= eps
+// (past the last maximum of every term, the bound only decreases).
+double cutoff_radius(int l, const double* a, const double* c, int np, double eps) {
+  auto f = [&](double r) {
+    double s = 0.0;
+    for (int k = 0; k < np; ++k) s += std::fabs(c[k]) * std::exp(-a[k] * r * r);
+    return std::pow(r, l) * s;
+  };
+  double lo = 0.0;
+  for (int k = 0; k < np; ++k) lo = std::max(lo, std::sqrt(0.5 * l / a[k]));
+  double hi = std::max(2.0 * lo, 1.0);
+  while (f(hi) >= eps && hi < 1e4) hi *= 2.0;
+  if (f(lo) < eps) return lo;
+  for (int it = 0; it < 100; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    (f(mid) >= eps ? lo : hi) = mid;
+  }
+  return hi;
+}
+
+// Everything a call needs on the device, freed on the stream at the end.
+struct XcCall {
+  hipStream_t s = nullptr;
+  std::vector<void*> bufs;
+  int n = 0, NA = 0, nIb = 0, ns = 0;
+  XcShell* shells = nullptr;
+  double *exps = nullptr, *coefs = nullptr, *phi = nullptr;
+  unsigned char* mask = nullptr;
+  int *list = nullptr, *count = nullptr;
+
+  template <typename T>
+  bool alloc(T** p, size_t bytes) {
+    void* q = nullptr;
+    if (hipMallocAsync(&q, std::max<size_t>(bytes, 8), s) != hipSuccess) return false;
+    bufs.push_back(q);
+    *p = static_cast<T*>(q);
+    return true;
+  }
+  ~XcCall() {
+    for (void* p : bufs) (void)hipFreeAsync(p, s);
+  }
+};
+
+int xc_setup(XcCall& x, const jk_basis* b, double eps) {
+  int32_t n = 0;
+  const int rc = jk_validate_basis(b, &n);
+  if (rc != JK_OK) return rc;
+  x.n = n;
+  x.NA = (n + kB - 1) / kB * kB;
+  x.nIb = x.NA / kB;
+  x.ns = b->n_shells;
+  if (x.ns > 65535) return JK_EUNSUPPORTED;
+  std::vector<XcShell> hs(x.ns);
+  int np = 0, bf = 0;
+  for (int s = 0; s < x.ns; ++s) np = std::max(np, b->shell_prim0[s] + b->shell_nprim[s]);
+  for (int s = 0; s < x.ns; ++s) {
+    const int l = b->shell_l[s], a = b->shell_atom[s];
+    const double r = cutoff_radius(l, b->exps + b->shell_prim0[s], b->coefs + b->shell_prim0[s],
+                                   b->shell_nprim[s], eps);
+    hs[s] = XcShell{b->xyz[3 * a], b->xyz[3 * a + 1], b->xyz[3 * a + 2], r * r, l,
+                    b->shell_nprim[s], bf, b->shell_prim0[s]};
+    bf += (l + 1) * (l + 2) / 2;
+  }
+  const int nGb = kBatch / kB;
+  if (!x.alloc(&x.shells, hs.size() * sizeof(XcShell)) || !x.alloc(&x.exps, np * 8) ||
+      !x.alloc(&x.coefs, np * 8) || !x.alloc(&x.phi, static_cast<size_t>(x.NA) * kBatch * 8) ||
+      !x.alloc(&x.mask, static_cast<size_t>(x.nIb) * nGb) ||
+      !x.alloc(&x.list, static_cast<size_t>(nGb) * x.nIb * 4) || !x.alloc(&x.count, nGb * 4))
+    return JK_ENOMEM;
+  if (hipMemcpyAsync(x.shells, hs.data(), hs.size() * sizeof(XcShell), hipMemcpyHostToDevice, x.s) != hipSuccess ||
+      hipMemcpyAsync(x.exps, b->exps, np * 8, hipMemcpyHostToDevice, x.s) != hipSuccess ||
+      hipMemcpyAsync(x.coefs, b->coefs, np * 8, hipMemcpyHostToDevice, x.s) != hipSuccess ||
+      hipStreamSynchronize(x.s) != hipSuccess)   // the host tables go out of scope
+    return JK_EHIP;
+  return JK_OK;
+}
+
+// AO values, mask and lists of one batch (points g0 .. g0+ng-1).
+void xc_batch(XcCall& x, const double* grid, int g0, int ng, int GB, double eps) {
+  const int nGb = GB / kB;
+  // padding rows (functions n .. NA-1) are zero at this batch's row stride
+  const size_t pad = static_cast<size_t>(x.NA - x.n) * GB;
+  if (pad) hipLaunchKernelGGL(fill_kernel, dim3((pad + 255) / 256), dim3(256), 0, x.s,
+                              x.phi + static_cast<size_t>(x.n) * GB, pad, 0.0);
+  hipLaunchKernelGGL(ao_kernel, dim3((GB + 255) / 256, x.ns), dim3(256), 0, x.s, x.shells, x.exps,
+                     x.coefs, grid, g0, ng, GB, x.phi);
+  hipLaunchKernelGGL(mask_kernel, dim3(nGb, x.nIb), dim3(kWaveT), 0, x.s, x.phi, GB, eps, x.mask);
+  hipLaunchKernelGGL(list_kernel, dim3((nGb + 63) / 64), dim3(64), 0, x.s, x.mask, x.nIb, nGb,
+                     x.list, x.count);
+}
+
+bool check_eps(double eps) { return eps > 0.0 && eps < 1.0 && std::isfinite(eps); }
+
+}  // namespace
+
+extern "C" {
+
+int jk_xc_rho(const jk_basis* basis, const double* grid, int32_t n_grid, const double* D,
+              int32_t n_dm, double eps, double* rho, void* hip_stream) {
+  if (!grid || !D || !rho || n_grid < 1 || n_dm < 1 || n_dm > JK_MAX_NDM || !check_eps(eps))
+    return JK_EINVAL;
+  XcCall x;
+  x.s = static_cast<hipStream_t>(hip_stream);
+  int rc = xc_setup(x, basis, eps);
+  if (rc != JK_OK) return rc;
+  double* partial = nullptr;
+  if (!x.alloc(&partial, static_cast<size_t>(kBatch / kB) * x.nIb * kB * 8)) return JK_ENOMEM;
+  for (int g0 = 0; g0 < n_grid; g0 += kBatch) {
+    const int ng = std::min(kBatch, n_grid - g0);
+    const int GB = (ng + kB - 1) / kB * kB, nGb = GB / kB;
+    xc_batch(x, grid, g0, ng, GB, eps);
+    for (int m = 0; m < n_dm; ++m) {
+      const double* Dm = D + static_cast<size_t>(m) * x.n * x.n;
+      hipLaunchKernelGGL(rho_kernel, dim3(nGb, x.nIb), dim3(kWaveT), 0, x.s, x.phi, GB, Dm, x.n,
+                         x.list, x.count, x.nIb, partial);
+      hipLaunchKernelGGL(rho_reduce_kernel, dim3((ng + 255) / 256), dim3(256), 0, x.s, partial,
+                         x.count, x.nIb, ng, rho + static_cast<size_t>(m) * n_grid + g0);
+    }
+  }
+  return hipGetLastError() == hipSuccess ? JK_OK : JK_EHIP;
+}
+
+int jk_xc_vmat(const jk_basis* basis, const double* grid, int32_t n_grid, const double* wv,
+               double eps, double* V, void* hip_stream) {
+  if (!grid || !wv || !V || n_grid < 1 || !check_eps(eps)) return JK_EINVAL;
+  XcCall x;
+  x.s = static_cast<hipStream_t>(hip_stream);
+  int rc = xc_setup(x, basis, eps);
+  if (rc != JK_OK) return rc;
+  double* vacc = nullptr;
+  const size_t na2 = static_cast<size_t>(x.NA) * x.NA;
+  if (!x.alloc(&vacc, na2 * 8)) return JK_ENOMEM;
+  hipLaunchKernelGGL(fill_kernel, dim3((na2 + 255) / 256), dim3(256), 0, x.s, vacc, na2, 0.0);
+  for (int g0 = 0; g0 < n_grid; g0 += kBatch) {
+    const int ng = std::min(kBatch, n_grid - g0);
+    const int GB = (ng + kB - 1) / kB * kB, nGb = GB / kB;
+    xc_batch(x, grid, g0, ng, GB, eps);
+    hipLaunchKernelGGL(vmat_kernel, dim3(x.nIb, x.nIb), dim3(kWaveT), 0, x.s, x.phi, GB, x.mask,
+                       nGb, wv, g0, ng, x.NA, vacc);
+  }
+  const size_t nn = static_cast<size_t>(x.n) * x.n;
+  hipLaunchKernelGGL(vmat_finish_kernel, dim3((nn + 255) / 256), dim3(256), 0, x.s, vacc, x.NA,
+                     x.n, V);
+  return hipGetLastError() == hipSuccess ? JK_OK : JK_EHIP;
+}
+
+}  // extern "C"

@@ -25,7 +25,7 @@ ERR_NAMES = {1: "JK_EINVAL", 2: "JK_EUNSUPPORTED", 3: "JK_ENOMEM", 4: "JK_EHIP"}
 EXPORTS = ["jk_opts_default", "jk_ctx_create", "jk_ctx_destroy", "jk_validate_basis", "jk_build",
            "jk_build_noalloc", "jk_grad", "jk_get_stats", "jk_last_error", "jk_pure_count",
            "jk_pure_to_cart", "jk_cart_to_pure", "jk_scf_create", "jk_scf_destroy", "jk_scf_diag",
-           "jk_scf_diis", "jk_scf_diis_reset"]
+           "jk_scf_diis", "jk_scf_diis_reset", "jk_xc_rho", "jk_xc_vmat"]
 
 
 class JkError(RuntimeError):
@@ -99,6 +99,10 @@ def load():
     lib.jk_scf_diag.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp, vp]
     lib.jk_scf_diis.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.jk_scf_diis_reset.argtypes = [vp]
+    lib.jk_xc_rho.argtypes = [ctypes.POINTER(jk_basis), vp, ctypes.c_int32, vp, ctypes.c_int32,
+                              ctypes.c_double, vp, vp]
+    lib.jk_xc_vmat.argtypes = [ctypes.POINTER(jk_basis), vp, ctypes.c_int32, vp, ctypes.c_double,
+                               vp, vp]
     _lib = lib
     return lib
 
@@ -332,6 +336,41 @@ class ScfSteps:
 
     def reset(self):
         load().jk_scf_diis_reset(self.h)
+
+
+def xc_rho(mol, grid, D, eps: float = 1e-12):
+    """Density on the grid points (jk_xc_rho): grid [n_grid][3], D [n][n] or
+    [n_dm][n][n] float64 CUDA tensors; returns [n_grid] or [n_dm][n_grid]."""
+    import torch
+    basis = mol if isinstance(mol, Basis) else Basis(mol)
+    n = jk_validate_basis(basis)
+    squeeze = D.dim() == 2
+    Dd = (D.unsqueeze(0) if squeeze else D).contiguous()
+    _check_dev(grid, (grid.shape[0], 3), "grid")
+    _check_dev(Dd, (Dd.shape[0], n, n), "D")
+    rho = torch.empty((Dd.shape[0], grid.shape[0]), dtype=torch.float64, device=grid.device)
+    rc = load().jk_xc_rho(ctypes.byref(basis.c), ctypes.c_void_p(grid.data_ptr()),
+                          int(grid.shape[0]), ctypes.c_void_p(Dd.data_ptr()), int(Dd.shape[0]),
+                          float(eps), ctypes.c_void_p(rho.data_ptr()), _stream_ptr(torch, grid.device))
+    if rc != JK_OK:
+        raise JkError(rc, "jk_xc_rho")
+    return rho[0] if squeeze else rho
+
+
+def xc_vmat(mol, grid, wv, eps: float = 1e-12):
+    """V[mu][nu] = sum_g wv[g] phi_mu(g) phi_nu(g) (jk_xc_vmat); float64 CUDA tensors."""
+    import torch
+    basis = mol if isinstance(mol, Basis) else Basis(mol)
+    n = jk_validate_basis(basis)
+    _check_dev(grid, (grid.shape[0], 3), "grid")
+    _check_dev(wv, (grid.shape[0],), "wv")
+    V = torch.empty((n, n), dtype=torch.float64, device=grid.device)
+    rc = load().jk_xc_vmat(ctypes.byref(basis.c), ctypes.c_void_p(grid.data_ptr()),
+                           int(grid.shape[0]), ctypes.c_void_p(wv.data_ptr()), float(eps),
+                           ctypes.c_void_p(V.data_ptr()), _stream_ptr(torch, grid.device))
+    if rc != JK_OK:
+        raise JkError(rc, "jk_xc_vmat")
+    return V
 
 
 def jk_grad(ctx: Context, basis: Basis, D, dEdR, tol: float, opts: jk_opts | None = None,

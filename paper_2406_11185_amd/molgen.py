@@ -233,3 +233,24 @@ def single_bin_molecule(n_h: int, seed: int) -> Molecule:
                    shell_prim0=base.shell_prim0[keep].astype(np.int32),
                    exps=base.exps, coefs=base.coefs, name=f"s{n_h}_{seed}")
     return mol.with_D(density(nbf, max(1, nbf // 2), rng))
+
+
+def atom_grid(mol: Molecule, n_rad: int = 40, n_ang: int = 110, r_scale: float = 1.0):
+    """Synthetic integration grid: around each atom, n_rad radial shells at
+    r = r_scale x / (1 - x), x = (i + 1/2) / n_rad, times n_ang directions spread
+    over the sphere (golden-angle spiral); weight = the shell's volume element
+    times 4 pi / n_ang.  Returns (points [n][3], weights [n]).  Input data only:
+    no partition of the molecular volume between atoms."""
+    x = (np.arange(n_rad) + 0.5) / n_rad
+    r = r_scale * x / (1.0 - x)
+    dr = r_scale / (1.0 - x) ** 2 / n_rad
+    k = np.arange(n_ang) + 0.5
+    cos_t = 1.0 - 2.0 * k / n_ang
+    sin_t = np.sqrt(1.0 - cos_t ** 2)
+    phi = np.pi * (1.0 + 5 ** 0.5) * k
+    dirs = np.stack([sin_t * np.cos(phi), sin_t * np.sin(phi), cos_t], axis=1)
+    shell_pts = (r[:, None, None] * dirs[None, :, :]).reshape(-1, 3)
+    shell_w = np.repeat(4.0 * np.pi * r ** 2 * dr / n_ang, n_ang)
+    pts = np.concatenate([shell_pts + a for a in np.asarray(mol.xyz)])
+    w = np.tile(shell_w, len(mol.xyz))
+    return np.ascontiguousarray(pts), np.ascontiguousarray(w)
