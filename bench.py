@@ -234,7 +234,8 @@ def extra_measurements(args, jkb, molgen, ctx, mol, basis, D, J, K, E_head, tol,
     """The same build in the other precision (time, speedup, energy differences),
     the paper's own FP32 threshold (tolerance x 1e5), the long-range build of a
     range-separated hybrid (omega = 0.3), the SCF steps beside the build
-    (diagonalisation, DIIS), and the nuclear gradient:
+    (diagonalisation, DIIS), the XC integration's grid part, and the nuclear
+    gradient:
     of the 30-atom molecule, or of the workload itself (autograd through
     JKEnergy) when it carries several densities."""
     import numpy as np
@@ -314,6 +315,33 @@ def extra_measurements(args, jkb, molgen, ctx, mol, basis, D, J, K, E_head, tol,
                            "diis_depth8_ms": 1e3 * (time.perf_counter() - t) / 3}
         h.close()
         progress("SCF steps (diagonalisation, DIIS) done")
+    if n_dm == 1:
+        # the XC integration's grid part at the workload's size: a synthetic grid of
+        # 50 radial x 110 angular points per atom, rho of the workload's density and
+        # V for the grid weight times a smooth synthetic potential; algorithmic work
+        # = the 32 x 32 x 32 block products the calls ran (2 * 32^3 flops each)
+        pts, wgt = molgen.atom_grid(mol, 50, 110)
+        Gd = torch.as_tensor(pts, device=dev)
+        wvd = torch.as_tensor(wgt * np.exp(-0.02 * np.sum(pts ** 2, axis=1)), device=dev)
+        D0 = D[0].contiguous()
+        jkb.xc_rho(mol, Gd, D0)
+        jkb.xc_vmat(mol, Gd, wvd)
+        xc = {"points": int(len(pts))}
+        for name, call in (("rho", lambda t: jkb.xc_rho(mol, Gd, D0, tiles=t)),
+                           ("vmat", lambda t: jkb.xc_vmat(mol, Gd, wvd, tiles=t))):
+            tiles = torch.zeros(1, dtype=torch.int64, device=dev)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(2):
+                call(tiles)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 2
+            tf = int(tiles.cpu()[0]) / 2 * 2 * 32 ** 3 / (ms / 1e3) / 1e12
+            xc[name] = {"ms": ms, "block_products": int(tiles.cpu()[0]) // 2,
+                        "tflops_algorithmic": tf, "frac_of_fp64_vector_peak": tf / 78.6}
+        ex["xc_grid"] = xc
+        progress("XC grid part (rho, V) done")
     if n_dm == 1 and args.with_grad:
         # nuclear gradient of the 30-atom molecule, FP64 and mixed
         mg = molgen.workload("w30grad")

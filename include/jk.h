@@ -260,14 +260,17 @@ int jk_scf_diis_reset(jk_scf* scf);
  * caller's).  grid: DEVICE [n_grid][3] points (bohr); D: DEVICE [n_dm][n_bf][n_bf]
  * (symmetric), rho: DEVICE [n_dm][n_grid]; wv: DEVICE [n_grid]; V: DEVICE
  * [n_bf][n_bf]; Cartesian functions as in jk_build.  eps in (0, 1) (the paper's
- * default 1e-12).  Points are processed in batches of 32768; the call allocates its
- * workspace (about n_bf x 32768 doubles) stream-ordered on the current device, and
+ * default 1e-12).  tiles (optional, DEVICE int64, NULL = not written): the number
+ * of 32 x 32 x 32 block products the call ran is ADDED to *tiles (2 * 32^3 flops
+ * each; zero it first).  Points are processed in batches of 32768; the call allocates its
+ * workspace (about n_bf x 32768 doubles, and 8 n_bf^2 more for jk_xc_vmat)
+ * stream-ordered on the current device, and
  * synchronises hip_stream once (after copying the shell table).  JK_EINVAL for a bad
  * basis, pointer, count or eps; JK_ENOMEM / JK_EHIP on allocation or HIP failure. */
 int jk_xc_rho(const jk_basis* basis, const double* grid, int32_t n_grid, const double* D,
-              int32_t n_dm, double eps, double* rho, void* hip_stream);
+              int32_t n_dm, double eps, double* rho, int64_t* tiles, void* hip_stream);
 int jk_xc_vmat(const jk_basis* basis, const double* grid, int32_t n_grid, const double* wv,
-               double eps, double* V, void* hip_stream);
+               double eps, double* V, int64_t* tiles, void* hip_stream);
 
 /* Counters of the last successful jk_build / jk_grad.  With opts.timing = 1
  * this waits for the recorded events. */

@@ -8,10 +8,12 @@
 //     divide-and-conquer solver) and the closed-shell density D = 2 C_occ C_occ^T
 //     (one rocBLAS GEMM).
 //   jk_scf_diis: Pulay's extrapolation over a ring of the last `depth` (F, D)
-//     pairs: error e = F D S - S D F (two GEMMs and a transposed difference), the
-//     Gram matrix B = E^T E of the stored errors (one GEMM with K = n^2), the
-//     bordered system [B -1; -1^T 0] [c; l] = [0; -1] (rocSOLVER, on the device),
-//     F_out = sum c_i F_i (one GEMV over the stored Fock matrices).
+//     pairs: error e = F D S - S D F (two GEMMs and a transposed difference); the
+//     Gram matrix B_ij = <e_i, e_j> of the stored errors is kept on the device and
+//     only the new error's row is formed per call (m dot products of length n^2 in
+//     one pass over the stored errors, block partial sums reduced in a fixed
+//     order); the bordered system [B -1; -1^T 0] [c; l] = [0; -1] (rocSOLVER, on
+//     the device); F_out = sum c_i F_i (one GEMV over the stored Fock matrices).
 //
 // The matrices are symmetric, so their row-major storage equals the
 // column-major storage the libraries assume.  Eigenvectors come back as the
@@ -35,7 +37,8 @@ struct jk_scf {
   double* E = nullptr;      // n: off-diagonal work of the eigensolver; DIIS: F D S (n^2)
   double* Fh = nullptr;     // depth n^2: stored Fock matrices
   double* Eh = nullptr;     // depth n^2: stored errors
-  double* G = nullptr;      // (depth+1)^2: bordered Gram matrix
+  double* G = nullptr;      // (depth+1)^2 bordered system, then depth^2 Gram matrix,
+                            // then kDotBlocks x depth dot-product partials
   double* rhs = nullptr;    // depth+1: right-hand side, then [c; l]
   int* info = nullptr;      // 1
   int* ipiv = nullptr;      // depth+1
@@ -46,15 +49,55 @@ namespace {
 
 bool blas_ok(rocblas_status s) { return s == rocblas_status_success; }
 
-// Bordered DIIS system from the m x m Gram matrix (column-major, leading m).
-__global__ void diis_border_kernel(const double* __restrict__ gram, int m, double* __restrict__ G,
-                                   double* __restrict__ rhs) {
+constexpr int kDotBlocks = 512;
+constexpr int kDotThreads = 256;
+
+// Partial dot products of the new error e with the m stored errors: block b
+// sums its grid-stride share of the n^2 elements, part[b][j].
+__global__ __launch_bounds__(kDotThreads) void diis_dots_kernel(const double* __restrict__ e,
+                                                                const double* __restrict__ Eh,
+                                                                size_t nn, int m,
+                                                                double* __restrict__ part) {
+  __shared__ double red[kDotThreads];
+  for (int j = 0; j < m; ++j) {
+    const double* ej = Eh + static_cast<size_t>(j) * nn;
+    double s = 0.0;
+    for (size_t k = static_cast<size_t>(blockIdx.x) * kDotThreads + threadIdx.x; k < nn;
+         k += static_cast<size_t>(kDotBlocks) * kDotThreads)
+      s += e[k] * ej[k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kDotThreads / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[static_cast<size_t>(blockIdx.x) * m + j] = red[0];
+    __syncthreads();
+  }
+}
+
+// Row and column `slot` of the Gram matrix (leading dimension depth) from the
+// partials, summed over blocks in a fixed order.
+__global__ void diis_gram_kernel(const double* __restrict__ part, int m, int slot, int depth,
+                                 double* __restrict__ gram) {
+  const int j = threadIdx.x;
+  if (j >= m) return;
+  double s = 0.0;
+  for (int b = 0; b < kDotBlocks; ++b) s += part[static_cast<size_t>(b) * m + j];
+  gram[static_cast<size_t>(slot) * depth + j] = s;
+  gram[static_cast<size_t>(j) * depth + slot] = s;
+}
+
+// Bordered DIIS system from the leading m x m of the Gram matrix (leading
+// dimension depth).
+__global__ void diis_border_kernel(const double* __restrict__ gram, int m, int depth,
+                                   double* __restrict__ G, double* __restrict__ rhs) {
   const int t = threadIdx.x;
   const int M = m + 1;
   for (int k = t; k < M * M; k += blockDim.x) {
     const int i = k % M, j = k / M;   // column-major (i row, j column)
     double v;
-    if (i < m && j < m) v = gram[j * m + i];
+    if (i < m && j < m) v = gram[static_cast<size_t>(j) * depth + i];
     else if (i == m && j == m) v = 0.0;
     else v = -1.0;
     G[k] = v;
@@ -114,7 +157,8 @@ int jk_scf_create(jk_scf** out, int device, int32_t n, int32_t depth) {
                   hipMalloc(&h->E, nn * 8) == hipSuccess &&
                   hipMalloc(&h->Fh, depth * nn * 8) == hipSuccess &&
                   hipMalloc(&h->Eh, depth * nn * 8) == hipSuccess &&
-                  hipMalloc(&h->G, static_cast<size_t>(depth + 1) * (depth + 1) * 8 + depth * depth * 8) == hipSuccess &&
+                  hipMalloc(&h->G, (static_cast<size_t>(depth + 1) * (depth + 1) + depth * depth +
+                                    static_cast<size_t>(kDotBlocks) * depth) * 8) == hipSuccess &&
                   hipMalloc(&h->rhs, static_cast<size_t>(depth + 1) * 8) == hipSuccess &&
                   hipMalloc(&h->info, sizeof(int)) == hipSuccess &&
                   hipMalloc(&h->ipiv, static_cast<size_t>(depth + 1) * sizeof(int)) == hipSuccess;
@@ -192,13 +236,15 @@ int jk_scf_diis(jk_scf* h, const double* F, const double* D, const double* S, do
     return JK_EHIP;
   if (hipMemcpyAsync(Fs, F, nn * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) return JK_EHIP;
   if (err_out) hipLaunchKernelGGL(max_abs_kernel, dim3(1), dim3(kMaxThreads), 0, s, Es, nn, err_out);
-  // Gram matrix of the stored errors (slots 0..m-1 are the live ones)
+  // the new error's row of the Gram matrix (slots 0..m-1 are the live ones)
   double* gram = h->G + static_cast<size_t>(h->depth + 1) * (h->depth + 1);
+  double* part = gram + static_cast<size_t>(h->depth) * h->depth;
   const int ldk = static_cast<int>(nn);
-  if (!blas_ok(rocblas_dgemm(h->blas, rocblas_operation_transpose, rocblas_operation_none, m, m,
-                             ldk, &one, h->Eh, ldk, h->Eh, ldk, &zero, gram, m)))
-    return JK_EHIP;
-  hipLaunchKernelGGL(diis_border_kernel, dim3(1), dim3(256), 0, s, gram, m, h->G, h->rhs);
+  hipLaunchKernelGGL(diis_dots_kernel, dim3(kDotBlocks), dim3(kDotThreads), 0, s, Es, h->Eh, nn,
+                     m, part);
+  hipLaunchKernelGGL(diis_gram_kernel, dim3(1), dim3(64), 0, s, part, m, slot, h->depth, gram);
+  hipLaunchKernelGGL(diis_border_kernel, dim3(1), dim3(256), 0, s, gram, m, h->depth, h->G,
+                     h->rhs);
   if (!blas_ok(rocsolver_dgesv(h->blas, m + 1, 1, h->G, m + 1, h->ipiv, h->rhs, m + 1, h->info)))
     return JK_EHIP;
   int info = 0;

@@ -37,6 +37,7 @@ namespace {
 constexpr int kB = 32;            // block edge (functions and points)
 constexpr int kBatch = 32768;     // grid points per batch
 constexpr int kWaveT = 64;
+constexpr int kVChunks = 8;       // V: grid blocks of a batch split over this many workgroups
 
 struct XcShell {
   double x, y, z;      // centre
@@ -183,8 +184,9 @@ __global__ void rho_reduce_kernel(const double* __restrict__ partial, const int*
   rho[g] = s;
 }
 
-// V_acc[I][J] (I >= J) += sum over grid blocks G with both blocks nonzero of
-// phi_IG diag(wv_G) phi_JG^T; workgroup (I = blockIdx.y, J = blockIdx.x).
+// V_acc[z][I][J] (I >= J) += sum over the grid blocks G of chunk z with both
+// blocks nonzero of phi_IG diag(wv_G) phi_JG^T; workgroup (J = blockIdx.x,
+// I = blockIdx.y, z = blockIdx.z); the chunks are summed in order at the end.
 __global__ __launch_bounds__(kWaveT) void vmat_kernel(const double* __restrict__ phi, int GB,
                                                       const unsigned char* __restrict__ mask,
                                                       int nGb, const double* __restrict__ wv,
@@ -192,11 +194,14 @@ __global__ __launch_bounds__(kWaveT) void vmat_kernel(const double* __restrict__
                                                       double* __restrict__ vacc) {
   const int J = blockIdx.x, I = blockIdx.y, t = threadIdx.x;
   if (I < J) return;
+  const int per = (nGb + kVChunks - 1) / kVChunks;
+  const int Gb = blockIdx.z * per, Ge = min(nGb, Gb + per);
+  vacc += static_cast<size_t>(blockIdx.z) * NA * NA;
   __shared__ __attribute__((aligned(16))) double a[kB][kB];   // a[g][i] = phi[I*32+i][G*32+g]
   __shared__ __attribute__((aligned(16))) double b[kB][kB];   // b[g][j] = wv[g] phi[J*32+j][G*32+g]
   double acc[4][4] = {};
   bool any = false;
-  for (int G = 0; G < nGb; ++G) {
+  for (int G = Gb; G < Ge; ++G) {
     if (!(mask[static_cast<size_t>(I) * nGb + G] && mask[static_cast<size_t>(J) * nGb + G])) continue;
     any = true;
     for (int e = t; e < kB * kB; e += kWaveT) {
@@ -219,14 +224,17 @@ __global__ __launch_bounds__(kWaveT) void vmat_kernel(const double* __restrict__
       vacc[static_cast<size_t>(I * kB + r0 + r) * NA + J * kB + c0 + c] += acc[r][c];
 }
 
-// V from the lower triangle of V_acc (mu >= nu lies in a block pair I >= J), so
-// that V is exactly symmetric.
+// V from the lower triangle of the chunk sums of V_acc (mu >= nu lies in a block
+// pair I >= J), summed over chunks in order, so that V is exactly symmetric.
 __global__ void vmat_finish_kernel(const double* __restrict__ vacc, int NA, int n,
                                    double* __restrict__ V) {
   const size_t e = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= static_cast<size_t>(n) * n) return;
   const int mu = static_cast<int>(e / n), nu = static_cast<int>(e % n);
-  V[e] = mu >= nu ? vacc[static_cast<size_t>(mu) * NA + nu] : vacc[static_cast<size_t>(nu) * NA + mu];
+  const size_t o = mu >= nu ? static_cast<size_t>(mu) * NA + nu : static_cast<size_t>(nu) * NA + mu;
+  double s = 0.0;
+  for (int z = 0; z < kVChunks; ++z) s += vacc[static_cast<size_t>(z) * NA * NA + o];
+  V[e] = s;
 }
 
 // Cut-off radius of a shell: the largest r with r^l sum_k |c_k| exp(-a_k r^2) >= eps
@@ -322,12 +330,22 @@ void xc_batch(XcCall& x, const double* grid, int g0, int ng, int GB, double eps)
 
 bool check_eps(double eps) { return eps > 0.0 && eps < 1.0 && std::isfinite(eps); }
 
+// Tile products of a batch into *tiles: sum over grid blocks of c^2 (rho, per
+// density) or c (c + 1) / 2 (V, block pairs I >= J), c = nonzero AO blocks.
+__global__ void tiles_kernel(const int* __restrict__ count, int nGb, int pairs, int mult,
+                             unsigned long long* tiles) {
+  const int G = blockIdx.x * blockDim.x + threadIdx.x;
+  if (G >= nGb) return;
+  const unsigned long long c = static_cast<unsigned long long>(count[G]);
+  atomicAdd(tiles, (pairs ? c * (c + 1) / 2 : c * c) * static_cast<unsigned long long>(mult));
+}
+
 }  // namespace
 
 extern "C" {
 
 int jk_xc_rho(const jk_basis* basis, const double* grid, int32_t n_grid, const double* D,
-              int32_t n_dm, double eps, double* rho, void* hip_stream) {
+              int32_t n_dm, double eps, double* rho, int64_t* tiles, void* hip_stream) {
   if (!grid || !D || !rho || n_grid < 1 || n_dm < 1 || n_dm > JK_MAX_NDM || !check_eps(eps))
     return JK_EINVAL;
   XcCall x;
@@ -340,6 +358,9 @@ int jk_xc_rho(const jk_basis* basis, const double* grid, int32_t n_grid, const d
     const int ng = std::min(kBatch, n_grid - g0);
     const int GB = (ng + kB - 1) / kB * kB, nGb = GB / kB;
     xc_batch(x, grid, g0, ng, GB, eps);
+    if (tiles)
+      hipLaunchKernelGGL(tiles_kernel, dim3((nGb + 255) / 256), dim3(256), 0, x.s, x.count, nGb, 0,
+                         n_dm, reinterpret_cast<unsigned long long*>(tiles));
     for (int m = 0; m < n_dm; ++m) {
       const double* Dm = D + static_cast<size_t>(m) * x.n * x.n;
       hipLaunchKernelGGL(rho_kernel, dim3(nGb, x.nIb), dim3(kWaveT), 0, x.s, x.phi, GB, Dm, x.n,
@@ -352,21 +373,24 @@ int jk_xc_rho(const jk_basis* basis, const double* grid, int32_t n_grid, const d
 }
 
 int jk_xc_vmat(const jk_basis* basis, const double* grid, int32_t n_grid, const double* wv,
-               double eps, double* V, void* hip_stream) {
+               double eps, double* V, int64_t* tiles, void* hip_stream) {
   if (!grid || !wv || !V || n_grid < 1 || !check_eps(eps)) return JK_EINVAL;
   XcCall x;
   x.s = static_cast<hipStream_t>(hip_stream);
   int rc = xc_setup(x, basis, eps);
   if (rc != JK_OK) return rc;
   double* vacc = nullptr;
-  const size_t na2 = static_cast<size_t>(x.NA) * x.NA;
+  const size_t na2 = static_cast<size_t>(x.NA) * x.NA * kVChunks;
   if (!x.alloc(&vacc, na2 * 8)) return JK_ENOMEM;
   hipLaunchKernelGGL(fill_kernel, dim3((na2 + 255) / 256), dim3(256), 0, x.s, vacc, na2, 0.0);
   for (int g0 = 0; g0 < n_grid; g0 += kBatch) {
     const int ng = std::min(kBatch, n_grid - g0);
     const int GB = (ng + kB - 1) / kB * kB, nGb = GB / kB;
     xc_batch(x, grid, g0, ng, GB, eps);
-    hipLaunchKernelGGL(vmat_kernel, dim3(x.nIb, x.nIb), dim3(kWaveT), 0, x.s, x.phi, GB, x.mask,
+    if (tiles)
+      hipLaunchKernelGGL(tiles_kernel, dim3((nGb + 255) / 256), dim3(256), 0, x.s, x.count, nGb, 1,
+                         1, reinterpret_cast<unsigned long long*>(tiles));
+    hipLaunchKernelGGL(vmat_kernel, dim3(x.nIb, x.nIb, kVChunks), dim3(kWaveT), 0, x.s, x.phi, GB, x.mask,
                        nGb, wv, g0, ng, x.NA, vacc);
   }
   const size_t nn = static_cast<size_t>(x.n) * x.n;

@@ -100,9 +100,9 @@ def load():
     lib.jk_scf_diis.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.jk_scf_diis_reset.argtypes = [vp]
     lib.jk_xc_rho.argtypes = [ctypes.POINTER(jk_basis), vp, ctypes.c_int32, vp, ctypes.c_int32,
-                              ctypes.c_double, vp, vp]
+                              ctypes.c_double, vp, vp, vp]
     lib.jk_xc_vmat.argtypes = [ctypes.POINTER(jk_basis), vp, ctypes.c_int32, vp, ctypes.c_double,
-                               vp, vp]
+                               vp, vp, vp]
     _lib = lib
     return lib
 
@@ -338,9 +338,11 @@ class ScfSteps:
         load().jk_scf_diis_reset(self.h)
 
 
-def xc_rho(mol, grid, D, eps: float = 1e-12):
+def xc_rho(mol, grid, D, eps: float = 1e-12, tiles=None):
     """Density on the grid points (jk_xc_rho): grid [n_grid][3], D [n][n] or
-    [n_dm][n][n] float64 CUDA tensors; returns [n_grid] or [n_dm][n_grid]."""
+    [n_dm][n][n] float64 CUDA tensors; returns [n_grid] or [n_dm][n_grid].
+    tiles: optional int64 CUDA tensor of one element, incremented by the block
+    products run."""
     import torch
     basis = mol if isinstance(mol, Basis) else Basis(mol)
     n = jk_validate_basis(basis)
@@ -351,13 +353,15 @@ def xc_rho(mol, grid, D, eps: float = 1e-12):
     rho = torch.empty((Dd.shape[0], grid.shape[0]), dtype=torch.float64, device=grid.device)
     rc = load().jk_xc_rho(ctypes.byref(basis.c), ctypes.c_void_p(grid.data_ptr()),
                           int(grid.shape[0]), ctypes.c_void_p(Dd.data_ptr()), int(Dd.shape[0]),
-                          float(eps), ctypes.c_void_p(rho.data_ptr()), _stream_ptr(torch, grid.device))
+                          float(eps), ctypes.c_void_p(rho.data_ptr()),
+                          ctypes.c_void_p(tiles.data_ptr()) if tiles is not None else None,
+                          _stream_ptr(torch, grid.device))
     if rc != JK_OK:
         raise JkError(rc, "jk_xc_rho")
     return rho[0] if squeeze else rho
 
 
-def xc_vmat(mol, grid, wv, eps: float = 1e-12):
+def xc_vmat(mol, grid, wv, eps: float = 1e-12, tiles=None):
     """V[mu][nu] = sum_g wv[g] phi_mu(g) phi_nu(g) (jk_xc_vmat); float64 CUDA tensors."""
     import torch
     basis = mol if isinstance(mol, Basis) else Basis(mol)
@@ -367,7 +371,9 @@ def xc_vmat(mol, grid, wv, eps: float = 1e-12):
     V = torch.empty((n, n), dtype=torch.float64, device=grid.device)
     rc = load().jk_xc_vmat(ctypes.byref(basis.c), ctypes.c_void_p(grid.data_ptr()),
                            int(grid.shape[0]), ctypes.c_void_p(wv.data_ptr()), float(eps),
-                           ctypes.c_void_p(V.data_ptr()), _stream_ptr(torch, grid.device))
+                           ctypes.c_void_p(V.data_ptr()),
+                           ctypes.c_void_p(tiles.data_ptr()) if tiles is not None else None,
+                           _stream_ptr(torch, grid.device))
     if rc != JK_OK:
         raise JkError(rc, "jk_xc_vmat")
     return V

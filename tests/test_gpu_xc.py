@@ -65,8 +65,15 @@ def test_xc_full_size_sampled_points_and_trace_identity():
     say(f"case XC w120 ({mol.n_bf} functions, {len(pts)} points, eps 1e-12)")
     G = torch.as_tensor(pts, device="cuda")
     D = torch.as_tensor(mol.D, device="cuda")
-    rho = jkb.xc_rho(mol, G, D).cpu().numpy()
-    V = jkb.xc_vmat(mol, G, torch.as_tensor(wv, device="cuda")).cpu().numpy()
+    t_rho = torch.zeros(1, dtype=torch.int64, device="cuda")
+    t_v = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rho = jkb.xc_rho(mol, G, D, tiles=t_rho).cpu().numpy()
+    V = jkb.xc_vmat(mol, G, torch.as_tensor(wv, device="cuda"), tiles=t_v).cpu().numpy()
+    nr, nv = int(t_rho.cpu()[0]), int(t_v.cpu()[0])
+    nIb, nGb = (mol.n_bf + 31) // 32, sum((min(32768, len(pts) - g0) + 31) // 32
+                                        for g0 in range(0, len(pts), 32768))
+    say(f"  tile products: rho {nr}, V {nv} (dense: {nIb * nIb * nGb}, {nIb * (nIb + 1) // 2 * nGb})")
+    assert 0 < nr < nIb * nIb * nGb and 0 < nv < nIb * (nIb + 1) // 2 * nGb
     idx = np.random.default_rng(3).choice(len(pts), 3000, replace=False)
     ro = xc_oracle.rho(mol, pts[idx], mol.D)
     say(f"  sampled max|drho|={np.abs(rho[0, idx] - ro).max():.2e} (max {np.abs(ro).max():.2e})")
@@ -88,9 +95,9 @@ def test_xc_argument_checks():
     lib = jkb.load()
     p = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
     s = None
-    assert lib.jk_xc_rho(ctypes.byref(b.c), p(G), 10, p(D), 1, 0.0, p(rho), s) == jkb.JK_EINVAL
-    assert lib.jk_xc_rho(ctypes.byref(b.c), p(G), 0, p(D), 1, 1e-12, p(rho), s) == jkb.JK_EINVAL
-    assert lib.jk_xc_rho(None, p(G), 10, p(D), 1, 1e-12, p(rho), s) == jkb.JK_EINVAL
-    assert lib.jk_xc_vmat(ctypes.byref(b.c), p(G), 10, None, 1e-12, p(D), s) == jkb.JK_EINVAL
+    assert lib.jk_xc_rho(ctypes.byref(b.c), p(G), 10, p(D), 1, 0.0, p(rho), None, s) == jkb.JK_EINVAL
+    assert lib.jk_xc_rho(ctypes.byref(b.c), p(G), 0, p(D), 1, 1e-12, p(rho), None, s) == jkb.JK_EINVAL
+    assert lib.jk_xc_rho(None, p(G), 10, p(D), 1, 1e-12, p(rho), None, s) == jkb.JK_EINVAL
+    assert lib.jk_xc_vmat(ctypes.byref(b.c), p(G), 10, None, 1e-12, p(D), None, s) == jkb.JK_EINVAL
     torch.cuda.synchronize()
     assert bool((rho == 7.0).all())
