@@ -53,34 +53,51 @@ constexpr int kDotBlocks = 512;
 constexpr int kDotThreads = 256;
 
 // Partial dot products of the new error e with the m stored errors: block b
-// sums its grid-stride share of the n^2 elements, part[b][j].
+// sums its grid-stride share of the n^2 elements, part[b][j]; pmax[b] = the
+// largest |e| of that share.
 __global__ __launch_bounds__(kDotThreads) void diis_dots_kernel(const double* __restrict__ e,
                                                                 const double* __restrict__ Eh,
                                                                 size_t nn, int m,
-                                                                double* __restrict__ part) {
-  __shared__ double red[kDotThreads];
+                                                                double* __restrict__ part,
+                                                                double* __restrict__ pmax) {
+  __shared__ double red[kDotThreads], rmax[kDotThreads];
   for (int j = 0; j < m; ++j) {
     const double* ej = Eh + static_cast<size_t>(j) * nn;
-    double s = 0.0;
+    double s = 0.0, mx = 0.0;
     for (size_t k = static_cast<size_t>(blockIdx.x) * kDotThreads + threadIdx.x; k < nn;
-         k += static_cast<size_t>(kDotBlocks) * kDotThreads)
+         k += static_cast<size_t>(kDotBlocks) * kDotThreads) {
       s += e[k] * ej[k];
+      if (j == 0) mx = fmax(mx, fabs(e[k]));
+    }
     red[threadIdx.x] = s;
+    rmax[threadIdx.x] = mx;
     __syncthreads();
     for (int w = kDotThreads / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      if (threadIdx.x < w) {
+        red[threadIdx.x] += red[threadIdx.x + w];
+        rmax[threadIdx.x] = fmax(rmax[threadIdx.x], rmax[threadIdx.x + w]);
+      }
       __syncthreads();
     }
-    if (threadIdx.x == 0) part[static_cast<size_t>(blockIdx.x) * m + j] = red[0];
+    if (threadIdx.x == 0) {
+      part[static_cast<size_t>(blockIdx.x) * m + j] = red[0];
+      if (j == 0) pmax[blockIdx.x] = rmax[0];
+    }
     __syncthreads();
   }
 }
 
 // Row and column `slot` of the Gram matrix (leading dimension depth) from the
-// partials, summed over blocks in a fixed order.
-__global__ void diis_gram_kernel(const double* __restrict__ part, int m, int slot, int depth,
-                                 double* __restrict__ gram) {
+// partials, summed over blocks in a fixed order; *err_out = max |e| if wanted.
+__global__ void diis_gram_kernel(const double* __restrict__ part, const double* __restrict__ pmax,
+                                 int m, int slot, int depth, double* __restrict__ gram,
+                                 double* err_out) {
   const int j = threadIdx.x;
+  if (j == 0 && err_out) {
+    double mx = 0.0;
+    for (int b = 0; b < kDotBlocks; ++b) mx = fmax(mx, pmax[b]);
+    *err_out = mx;
+  }
   if (j >= m) return;
   double s = 0.0;
   for (int b = 0; b < kDotBlocks; ++b) s += part[static_cast<size_t>(b) * m + j];
@@ -108,22 +125,6 @@ __global__ void diis_border_kernel(const double* __restrict__ gram, int m, int d
 __global__ void fill_zero_kernel(double* p, size_t count) {
   const size_t k = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k < count) p[k] = 0.0;
-}
-
-// max |e| over n^2 elements into *out (one workgroup).
-constexpr int kMaxThreads = 1024;
-__global__ __launch_bounds__(kMaxThreads) void max_abs_kernel(const double* __restrict__ e,
-                                                              size_t count, double* out) {
-  __shared__ double part[kMaxThreads];
-  double v = 0.0;
-  for (size_t k = threadIdx.x; k < count; k += kMaxThreads) v = fmax(v, fabs(e[k]));
-  part[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = kMaxThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + w]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = part[0];
 }
 
 void release(jk_scf* h) {
@@ -158,7 +159,7 @@ int jk_scf_create(jk_scf** out, int device, int32_t n, int32_t depth) {
                   hipMalloc(&h->Fh, depth * nn * 8) == hipSuccess &&
                   hipMalloc(&h->Eh, depth * nn * 8) == hipSuccess &&
                   hipMalloc(&h->G, (static_cast<size_t>(depth + 1) * (depth + 1) + depth * depth +
-                                    static_cast<size_t>(kDotBlocks) * depth) * 8) == hipSuccess &&
+                                    static_cast<size_t>(kDotBlocks) * (depth + 1)) * 8) == hipSuccess &&
                   hipMalloc(&h->rhs, static_cast<size_t>(depth + 1) * 8) == hipSuccess &&
                   hipMalloc(&h->info, sizeof(int)) == hipSuccess &&
                   hipMalloc(&h->ipiv, static_cast<size_t>(depth + 1) * sizeof(int)) == hipSuccess;
@@ -235,14 +236,15 @@ int jk_scf_diis(jk_scf* h, const double* F, const double* D, const double* S, do
                              &one, h->E, n, &mone, h->E, n, Es, n)))
     return JK_EHIP;
   if (hipMemcpyAsync(Fs, F, nn * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) return JK_EHIP;
-  if (err_out) hipLaunchKernelGGL(max_abs_kernel, dim3(1), dim3(kMaxThreads), 0, s, Es, nn, err_out);
   // the new error's row of the Gram matrix (slots 0..m-1 are the live ones)
   double* gram = h->G + static_cast<size_t>(h->depth + 1) * (h->depth + 1);
   double* part = gram + static_cast<size_t>(h->depth) * h->depth;
+  double* pmax = part + static_cast<size_t>(kDotBlocks) * h->depth;
   const int ldk = static_cast<int>(nn);
   hipLaunchKernelGGL(diis_dots_kernel, dim3(kDotBlocks), dim3(kDotThreads), 0, s, Es, h->Eh, nn,
-                     m, part);
-  hipLaunchKernelGGL(diis_gram_kernel, dim3(1), dim3(64), 0, s, part, m, slot, h->depth, gram);
+                     m, part, pmax);
+  hipLaunchKernelGGL(diis_gram_kernel, dim3(1), dim3(64), 0, s, part, pmax, m, slot, h->depth, gram,
+                     err_out);
   hipLaunchKernelGGL(diis_border_kernel, dim3(1), dim3(256), 0, s, gram, m, h->depth, h->G,
                      h->rhs);
   if (!blas_ok(rocsolver_dgesv(h->blas, m + 1, 1, h->G, m + 1, h->ipiv, h->rhs, m + 1, h->info)))
