@@ -21,9 +21,10 @@
 // Layout in HBM per batch of grid points: phi [NA][GB] row-major (NA = n_ao
 // rounded up to 32, GB = points of the batch rounded up to 32), the block mask
 // [NA/32][GB/32] and per grid block the list of its nonzero AO blocks.  The tile
-// products run on the vector FP64 units (the FP64 matrix rate of this chip is the
-// same as the vector rate), one wavefront per 32 x 32 output tile, each lane
-// holding 4 x 4 outputs, operands staged in LDS.
+// products run on the FP64 matrix cores (their rate on this chip equals the
+// vector FP64 rate, but a matrix instruction reads a quarter of the operands
+// from LDS per flop that 4 x 4 register tiles would), one wavefront per 32 x 32
+// output tile, operands staged in LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -106,22 +107,24 @@ __global__ void list_kernel(const unsigned char* __restrict__ mask, int nIb, int
   count[G] = c;
 }
 
-// One 32 x 32 tile product per wavefront: lane t holds rows 4 (t / 8) .. +3 and
-// columns 4 (t % 8) .. +3 of the output; a[k][i] (k-major) and b[k][j] in LDS.
-__device__ __forceinline__ void tile_fma(const double (*a)[kB], const double (*b)[kB], int t,
-                                         double acc[4][4]) {
-  const int r0 = 4 * (t >> 3), c0 = 4 * (t & 7);
-#pragma unroll 8
-  for (int k = 0; k < kB; ++k) {
-    const double2 a01 = *reinterpret_cast<const double2*>(&a[k][r0]);
-    const double2 a23 = *reinterpret_cast<const double2*>(&a[k][r0 + 2]);
-    const double2 b01 = *reinterpret_cast<const double2*>(&b[k][c0]);
-    const double2 b23 = *reinterpret_cast<const double2*>(&b[k][c0 + 2]);
-    const double av[4] = {a01.x, a01.y, a23.x, a23.y}, bv[4] = {b01.x, b01.y, b23.x, b23.y};
+// One 32 x 32 x 32 tile product per wavefront on the FP64 matrix cores: four
+// 16 x 16 output sub-tiles, eight steps of k = 4 each.  a[k][i] (k-major) and
+// b[k][j] in LDS; for one step lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16], and holds D[l / 16 + 4 r][l % 16], r = 0..3, of each
+// sub-tile (layout checked on the device): acc[si][sj][r] is output row
+// 16 si + l / 16 + 4 r, column 16 sj + l % 16.
+typedef double dx4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void tile_mfma(const double (*a)[kB], const double (*b)[kB], int lane,
+                                          dx4 acc[2][2]) {
+  const int l16 = lane & 15, kq = lane >> 4;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
+  for (int k0 = 0; k0 < kB; k0 += 4) {
+    const double a0 = a[k0 + kq][l16], a1 = a[k0 + kq][16 + l16];
+    const double b0 = b[k0 + kq][l16], b1 = b[k0 + kq][16 + l16];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
   }
 }
 
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(kWaveT) void rho_kernel(const double* __restrict__ 
   const int I = list[static_cast<size_t>(G) * nIb + k];
   __shared__ __attribute__((aligned(16))) double a[kB][kB];   // a[jj][i] = D[I*32+i][J*32+jj]
   __shared__ __attribute__((aligned(16))) double b[kB][kB];   // b[jj][g] = phi[J*32+jj][G*32+g]
-  double acc[4][4] = {};
+  dx4 acc[2][2] = {};
   for (int q = 0; q < cnt; ++q) {
     const int J = list[static_cast<size_t>(G) * nIb + q];
     for (int e = t; e < kB * kB; e += kWaveT) {
@@ -151,25 +154,29 @@ __global__ __launch_bounds__(kWaveT) void rho_kernel(const double* __restrict__ 
       b[r][c] = phi[static_cast<size_t>(J * kB + r) * GB + G * kB + c];
     }
     __syncthreads();
-    tile_fma(a, b, t, acc);
+    tile_mfma(a, b, t, acc);
     __syncthreads();
   }
-  // column sums of phi_IG * X_IG
-  const int r0 = 4 * (t >> 3), c0 = 4 * (t & 7);
-  double part[4] = {0, 0, 0, 0};
+  // column sums of phi_IG * X_IG: each lane sums its 8 rows of its two columns,
+  // then the four lane groups that share a column are added
+  const int l16 = t & 15, kq = t >> 4;
+  double part[2];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int sj = 0; sj < 2; ++sj) {
+    double v = 0.0;
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      part[c] += phi[static_cast<size_t>(I * kB + r0 + r) * GB + G * kB + c0 + c] * acc[r][c];
-  __shared__ double red[8][kB];
+    for (int si = 0; si < 2; ++si)
 #pragma unroll
-  for (int c = 0; c < 4; ++c) red[t >> 3][c0 + c] = part[c];
-  __syncthreads();
-  if (t < kB) {
-    double s = 0.0;
-    for (int q = 0; q < 8; ++q) s += red[q][t];
-    partial[(static_cast<size_t>(G) * nIb + k) * kB + t] = s;
+      for (int r = 0; r < 4; ++r)
+        v += phi[static_cast<size_t>(I * kB + 16 * si + kq + 4 * r) * GB + G * kB + 16 * sj + l16] *
+             acc[si][sj][r];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    part[sj] = v;
+  }
+  if (kq == 0) {
+    partial[(static_cast<size_t>(G) * nIb + k) * kB + l16] = part[0];
+    partial[(static_cast<size_t>(G) * nIb + k) * kB + 16 + l16] = part[1];
   }
 }
 
@@ -199,7 +206,7 @@ __global__ __launch_bounds__(kWaveT) void vmat_kernel(const double* __restrict__
   vacc += static_cast<size_t>(blockIdx.z) * NA * NA;
   __shared__ __attribute__((aligned(16))) double a[kB][kB];   // a[g][i] = phi[I*32+i][G*32+g]
   __shared__ __attribute__((aligned(16))) double b[kB][kB];   // b[g][j] = wv[g] phi[J*32+j][G*32+g]
-  double acc[4][4] = {};
+  dx4 acc[2][2] = {};
   bool any = false;
   for (int G = Gb; G < Ge; ++G) {
     if (!(mask[static_cast<size_t>(I) * nGb + G] && mask[static_cast<size_t>(J) * nGb + G])) continue;
@@ -212,16 +219,19 @@ __global__ __launch_bounds__(kWaveT) void vmat_kernel(const double* __restrict__
       b[g][i] = w * phi[static_cast<size_t>(J * kB + i) * GB + gg];
     }
     __syncthreads();
-    tile_fma(a, b, t, acc);
+    tile_mfma(a, b, t, acc);
     __syncthreads();
   }
   if (!any) return;
-  const int r0 = 4 * (t >> 3), c0 = 4 * (t & 7);
+  const int l16 = t & 15, kq = t >> 4;
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int si = 0; si < 2; ++si)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      vacc[static_cast<size_t>(I * kB + r0 + r) * NA + J * kB + c0 + c] += acc[r][c];
+    for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        vacc[static_cast<size_t>(I * kB + 16 * si + kq + 4 * r) * NA + J * kB + 16 * sj + l16] +=
+            acc[si][sj][r];
 }
 
 // V from the lower triangle of the chunk sums of V_acc (mu >= nu lies in a block
