@@ -156,3 +156,19 @@ def test_omega_argument_checks():
     assert e.value.code == jkb.JK_EUNSUPPORTED
     torch.cuda.synchronize()
     assert bool((J == 7.0).all()) and bool((K == 7.0).all()) and bool((G == 7.0).all())
+
+
+@pytest.mark.parametrize("precision,bound", [("fp64", TOL_ABS), ("mixed", 1e-7)])
+def test_omega_w120_sampled_blocks(precision, bound):
+    """The benchmark's long-range leg (1080 functions, tol 1e-10, omega 0.3):
+    sampled blocks against the oracle, FP64 at the FP64 bound, mixed within 1e-7
+    (FP32 only for quartets whose bound is below 1e-4)."""
+    mol = molgen.workload("w120")
+    say(f"case w120 (1080 functions, tol 1e-10, omega 0.3, {precision}), sampled blocks")
+    J, K = _gpu(mol, 1e-10, 0.3, precision=precision)
+    pairs = sample_pairs(mol, 4, seed=121)
+    ref = oracle.jk_blocks(mol, 1e-10, pairs, omega=0.3)
+    for (m, n), gj, gk, (oj, ok) in zip(pairs, blocks_of(mol, J, pairs), blocks_of(mol, K, pairs), ref):
+        say(f"  block ({m},{n}) dJ={np.abs(gj - oj).max():.2e} dK={np.abs(gk - ok).max():.2e}")
+        assert np.abs(gj - oj).max() <= bound
+        assert np.abs(gk - ok).max() <= bound
