@@ -113,8 +113,12 @@ __global__ void list_kernel(const unsigned char* __restrict__ mask, int nIb, int
 // B[l / 16][l % 16], and holds D[l / 16 + 4 r][l % 16], r = 0..3, of each
 // sub-tile (layout checked on the device): acc[si][sj][r] is output row
 // 16 si + l / 16 + 4 r, column 16 sj + l % 16.
+// The LDS rows are padded to kLd doubles: with 64-bit elements every access then
+// takes the minimum of two bank passes (an unpadded 32-double row puts the four
+// k rows of one step, and the 32 rows of a transposing store, on the same banks).
 typedef double dx4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void tile_mfma(const double (*a)[kB], const double (*b)[kB], int lane,
+constexpr int kLd = kB + 1;
+__device__ __forceinline__ void tile_mfma(const double (*a)[kLd], const double (*b)[kLd], int lane,
                                           dx4 acc[2][2]) {
   const int l16 = lane & 15, kq = lane >> 4;
 #pragma unroll
@@ -140,20 +144,34 @@ __global__ __launch_bounds__(kWaveT) void rho_kernel(const double* __restrict__ 
   const int cnt = count[G];
   if (k >= cnt) return;
   const int I = list[static_cast<size_t>(G) * nIb + k];
-  __shared__ __attribute__((aligned(16))) double a[kB][kB];   // a[jj][i] = D[I*32+i][J*32+jj]
-  __shared__ __attribute__((aligned(16))) double b[kB][kB];   // b[jj][g] = phi[J*32+jj][G*32+g]
+  __shared__ double a[kB][kLd];   // a[jj][i] = D[I*32+i][J*32+jj]
+  __shared__ double b[kB][kLd];   // b[jj][g] = phi[J*32+jj][G*32+g]
   dx4 acc[2][2] = {};
-  for (int q = 0; q < cnt; ++q) {
-    const int J = list[static_cast<size_t>(G) * nIb + q];
-    for (int e = t; e < kB * kB; e += kWaveT) {
-      const int r = e / kB, c = e % kB;
+  // the next J's operands are loaded into registers while the current tile
+  // product runs; element u of lane t is e = t + 64 u: row e / 32, column e % 32
+  constexpr int PER = kB * kB / kWaveT;
+  double ra[PER], rb[PER];
+  auto fetch = [&](int J) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + kWaveT * u, r = e / kB, c = e % kB;
       // a[r][c] = D[I*32+c][J*32+r], read as D[J*32+r][I*32+c] (D symmetric) so
       // that consecutive lanes read consecutive columns
       const int row = J * kB + r, col = I * kB + c;
-      a[r][c] = row < n && col < n ? D[static_cast<size_t>(row) * n + col] : 0.0;
-      b[r][c] = phi[static_cast<size_t>(J * kB + r) * GB + G * kB + c];
+      ra[u] = row < n && col < n ? D[static_cast<size_t>(row) * n + col] : 0.0;
+      rb[u] = phi[static_cast<size_t>(J * kB + r) * GB + G * kB + c];
+    }
+  };
+  fetch(list[static_cast<size_t>(G) * nIb]);
+  for (int q = 0; q < cnt; ++q) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + kWaveT * u;
+      a[e / kB][e % kB] = ra[u];
+      b[e / kB][e % kB] = rb[u];
     }
     __syncthreads();
+    if (q + 1 < cnt) fetch(list[static_cast<size_t>(G) * nIb + q + 1]);
     tile_mfma(a, b, t, acc);
     __syncthreads();
   }
@@ -204,25 +222,44 @@ __global__ __launch_bounds__(kWaveT) void vmat_kernel(const double* __restrict__
   const int per = (nGb + kVChunks - 1) / kVChunks;
   const int Gb = blockIdx.z * per, Ge = min(nGb, Gb + per);
   vacc += static_cast<size_t>(blockIdx.z) * NA * NA;
-  __shared__ __attribute__((aligned(16))) double a[kB][kB];   // a[g][i] = phi[I*32+i][G*32+g]
-  __shared__ __attribute__((aligned(16))) double b[kB][kB];   // b[g][j] = wv[g] phi[J*32+j][G*32+g]
+  __shared__ double a[kB][kLd];   // a[g][i] = phi[I*32+i][G*32+g]
+  __shared__ double b[kB][kLd];   // b[g][j] = wv[g] phi[J*32+j][G*32+g]
   dx4 acc[2][2] = {};
-  bool any = false;
-  for (int G = Gb; G < Ge; ++G) {
-    if (!(mask[static_cast<size_t>(I) * nGb + G] && mask[static_cast<size_t>(J) * nGb + G])) continue;
-    any = true;
-    for (int e = t; e < kB * kB; e += kWaveT) {
-      const int i = e / kB, g = e % kB;
+  // grid blocks where both AO blocks are nonzero, in order; the next one's
+  // operands are loaded into registers while the current tile product runs
+  auto next_g = [&](int G) {
+    while (G < Ge && !(mask[static_cast<size_t>(I) * nGb + G] && mask[static_cast<size_t>(J) * nGb + G]))
+      ++G;
+    return G;
+  };
+  constexpr int PER = kB * kB / kWaveT;
+  double ra[PER], rb[PER];
+  auto fetch = [&](int G) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + kWaveT * u, i = e / kB, g = e % kB;
       const int gg = G * kB + g;
       const double w = gg < ng ? wv[g0 + gg] : 0.0;
-      a[g][i] = phi[static_cast<size_t>(I * kB + i) * GB + gg];
-      b[g][i] = w * phi[static_cast<size_t>(J * kB + i) * GB + gg];
+      ra[u] = phi[static_cast<size_t>(I * kB + i) * GB + gg];
+      rb[u] = w * phi[static_cast<size_t>(J * kB + i) * GB + gg];
+    }
+  };
+  int G = next_g(Gb);
+  if (G >= Ge) return;
+  fetch(G);
+  while (G < Ge) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + kWaveT * u;
+      a[e % kB][e / kB] = ra[u];   // a[g][i]
+      b[e % kB][e / kB] = rb[u];   // b[g][j]
     }
     __syncthreads();
+    G = next_g(G + 1);
+    if (G < Ge) fetch(G);
     tile_mfma(a, b, t, acc);
     __syncthreads();
   }
-  if (!any) return;
   const int l16 = t & 15, kq = t >> 4;
 #pragma unroll
   for (int si = 0; si < 2; ++si)
