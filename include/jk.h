@@ -262,8 +262,8 @@ int jk_scf_diis_reset(jk_scf* scf);
  * [n_bf][n_bf]; Cartesian functions as in jk_build.  eps in (0, 1) (the paper's
  * default 1e-12).  tiles (optional, DEVICE int64, NULL = not written): the number
  * of 32 x 32 x 32 block products the call ran is ADDED to *tiles (2 * 32^3 flops
- * each; zero it first).  Points are processed in batches of 32768; the call allocates its
- * workspace (about n_bf x 32768 doubles, and 8 n_bf^2 more for jk_xc_vmat)
+ * each; zero it first).  Points are processed in batches of 16384; the call allocates its
+ * workspace (about n_bf x 16384 doubles, and 8 n_bf^2 more for jk_xc_vmat)
  * stream-ordered on the current device, and
  * synchronises hip_stream once (after copying the shell table).  JK_EINVAL for a bad
  * basis, pointer, count or eps; JK_ENOMEM / JK_EHIP on allocation or HIP failure. */

@@ -36,7 +36,7 @@
 namespace {
 
 constexpr int kB = 32;            // block edge (functions and points)
-constexpr int kBatch = 32768;     // grid points per batch
+constexpr int kBatch = 16384;     // grid points per batch
 constexpr int kWaveT = 64;
 constexpr int kVChunks = 8;       // V: grid blocks of a batch split over this many workgroups
 
@@ -225,12 +225,26 @@ __global__ __launch_bounds__(kWaveT) void vmat_kernel(const double* __restrict__
   __shared__ double a[kB][kLd];   // a[g][i] = phi[I*32+i][G*32+g]
   __shared__ double b[kB][kLd];   // b[g][j] = wv[g] phi[J*32+j][G*32+g]
   dx4 acc[2][2] = {};
-  // grid blocks where both AO blocks are nonzero, in order; the next one's
-  // operands are loaded into registers while the current tile product runs
-  auto next_g = [&](int G) {
-    while (G < Ge && !(mask[static_cast<size_t>(I) * nGb + G] && mask[static_cast<size_t>(J) * nGb + G]))
-      ++G;
-    return G;
+  // grid blocks of this chunk where both AO blocks are nonzero, as two 64-bit
+  // wavefront ballots (a chunk holds at most 128 grid blocks), taken in order;
+  // the next one's operands are loaded into registers while the current tile
+  // product runs
+  static_assert(kBatch / kB / kVChunks <= 2 * kWaveT, "grid blocks per chunk");
+  unsigned long long bits[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int Gh = Gb + kWaveT * h + t;
+    bits[h] = __ballot(Gh < Ge && mask[static_cast<size_t>(I) * nGb + Gh] &&
+                       mask[static_cast<size_t>(J) * nGb + Gh]);
+  }
+  auto next_g = [&](int) {
+    for (int h = 0; h < 2; ++h)
+      if (bits[h]) {
+        const int q = __ffsll(static_cast<long long>(bits[h])) - 1;
+        bits[h] &= bits[h] - 1;
+        return Gb + kWaveT * h + q;
+      }
+    return Ge;
   };
   constexpr int PER = kB * kB / kWaveT;
   double ra[PER], rb[PER];
@@ -244,7 +258,7 @@ __global__ __launch_bounds__(kWaveT) void vmat_kernel(const double* __restrict__
       rb[u] = w * phi[static_cast<size_t>(J * kB + i) * GB + gg];
     }
   };
-  int G = next_g(Gb);
+  int G = next_g(0);
   if (G >= Ge) return;
   fetch(G);
   while (G < Ge) {
@@ -255,7 +269,7 @@ __global__ __launch_bounds__(kWaveT) void vmat_kernel(const double* __restrict__
       b[e % kB][e / kB] = rb[u];   // b[g][j]
     }
     __syncthreads();
-    G = next_g(G + 1);
+    G = next_g(0);
     if (G < Ge) fetch(G);
     tile_mfma(a, b, t, acc);
     __syncthreads();

@@ -1,6 +1,6 @@
 """GPU parity of the XC integration's grid part (jk_xc_rho, jk_xc_vmat) against
 the dense oracle definitions (oracle/xc_oracle.py): elementwise on small and
-270-function molecules (two batches of points), sampled points of the
+270-function molecules (three batches of points), sampled points of the
 1080-function molecule on its full grid, and the identity tr(D V) = sum_g wv_g
 rho_g at full size."""
 import numpy as np
@@ -30,7 +30,7 @@ def _wv(pts, w, seed):
 
 CASES = [("w4", lambda: molgen.workload("w4"), (30, 50), 1e-14, 1e-11),
          ("ragged", lambda: molgen.ragged_molecule(2, 3, 5), (24, 38), 1e-13, 1e-10),
-         ("w30, two batches", lambda: molgen.workload("w30"), (30, 37), 1e-12, 1e-9)]
+         ("w30, three batches", lambda: molgen.workload("w30"), (30, 37), 1e-12, 1e-9)]
 
 
 @pytest.mark.parametrize("name,make,grid,eps,rel", CASES, ids=[c[0] for c in CASES])
@@ -70,8 +70,8 @@ def test_xc_full_size_sampled_points_and_trace_identity():
     rho = jkb.xc_rho(mol, G, D, tiles=t_rho).cpu().numpy()
     V = jkb.xc_vmat(mol, G, torch.as_tensor(wv, device="cuda"), tiles=t_v).cpu().numpy()
     nr, nv = int(t_rho.cpu()[0]), int(t_v.cpu()[0])
-    nIb, nGb = (mol.n_bf + 31) // 32, sum((min(32768, len(pts) - g0) + 31) // 32
-                                        for g0 in range(0, len(pts), 32768))
+    nIb, nGb = (mol.n_bf + 31) // 32, sum((min(16384, len(pts) - g0) + 31) // 32
+                                        for g0 in range(0, len(pts), 16384))
     say(f"  tile products: rho {nr}, V {nv} (dense: {nIb * nIb * nGb}, {nIb * (nIb + 1) // 2 * nGb})")
     assert 0 < nr < nIb * nIb * nGb and 0 < nv < nIb * (nIb + 1) // 2 * nGb
     idx = np.random.default_rng(3).choice(len(pts), 3000, replace=False)
