@@ -230,30 +230,33 @@ __global__ __launch_bounds__(kWaveT) void vmat_kernel(const double* __restrict__
   // the next one's operands are loaded into registers while the current tile
   // product runs
   static_assert(kBatch / kB / kVChunks <= 2 * kWaveT, "grid blocks per chunk");
-  unsigned long long bits[2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int Gh = Gb + kWaveT * h + t;
-    bits[h] = __ballot(Gh < Ge && mask[static_cast<size_t>(I) * nGb + Gh] &&
-                       mask[static_cast<size_t>(J) * nGb + Gh]);
-  }
+  auto valid = [&](int Gh) {
+    return Gh < Ge && mask[static_cast<size_t>(I) * nGb + Gh] && mask[static_cast<size_t>(J) * nGb + Gh];
+  };
+  unsigned long long bits0 = __ballot(valid(Gb + t)), bits1 = __ballot(valid(Gb + kWaveT + t));
   auto next_g = [&](int) {
-    for (int h = 0; h < 2; ++h)
-      if (bits[h]) {
-        const int q = __ffsll(static_cast<long long>(bits[h])) - 1;
-        bits[h] &= bits[h] - 1;
-        return Gb + kWaveT * h + q;
-      }
+    if (bits0) {
+      const int q = __ffsll(static_cast<long long>(bits0)) - 1;
+      bits0 &= bits0 - 1;
+      return Gb + q;
+    }
+    if (bits1) {
+      const int q = __ffsll(static_cast<long long>(bits1)) - 1;
+      bits1 &= bits1 - 1;
+      return Gb + kWaveT + q;
+    }
     return Ge;
   };
   constexpr int PER = kB * kB / kWaveT;
   double ra[PER], rb[PER];
+  // element u of lane t is e = t + 64 u: AO row e / 32, grid point e % 32 = t % 32
+  // (the same point, so the same weight, for every u)
   auto fetch = [&](int G) {
+    const int gg = G * kB + (t % kB);
+    const double w = gg < ng ? wv[g0 + gg] : 0.0;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      const int e = t + kWaveT * u, i = e / kB, g = e % kB;
-      const int gg = G * kB + g;
-      const double w = gg < ng ? wv[g0 + gg] : 0.0;
+      const int i = (t + kWaveT * u) / kB;
       ra[u] = phi[static_cast<size_t>(I * kB + i) * GB + gg];
       rb[u] = w * phi[static_cast<size_t>(J * kB + i) * GB + gg];
     }
