@@ -103,3 +103,32 @@ def test_ao_component_order_and_centre():
     assert phi[py, 0] == pytest.approx(-phi[py, 1], rel=1e-15) and phi[py, 2] == 0.0
     assert phi[dxy, 0] == pytest.approx(-phi[dxy, 1], rel=1e-15)
     assert phi[dxy, 0] == pytest.approx(-phi[dxy, 3], rel=1e-15)
+
+
+def test_ao_gradient_by_central_differences():
+    mol = _tight_molecule()
+    rng = np.random.default_rng(8)
+    pts = rng.uniform(-1.5, 2.5, (40, 3))
+    g = xc_oracle.ao_grad(mol, pts)
+    h = 1e-5
+    for ax in range(3):
+        dp = np.zeros(3)
+        dp[ax] = h
+        fd = (xc_oracle.ao(mol, pts + dp) - xc_oracle.ao(mol, pts - dp)) / (2 * h)
+        np.testing.assert_allclose(g[ax], fd, rtol=1e-7, atol=1e-8)
+
+
+def test_density_gradient_integrates_to_zero_and_gga_matrix(box):
+    """grad rho of a localised density integrates to zero; with wv = 0 and a
+    constant wg the GGA matrix is the integral of grad_c(phi_mu phi_nu), also zero."""
+    mol, pts, w = box
+    rng = np.random.default_rng(6)
+    X = rng.normal(size=(20, 20))
+    D = X + X.T
+    gr = xc_oracle.rho_grad(mol, pts, D)[0]
+    scale = float(np.abs(xc_oracle.rho(mol, pts, D)).sum() * w)
+    assert np.abs(gr.sum(axis=1) * w).max() <= 1e-10 * scale
+    wg = np.zeros((3, len(pts)))
+    wg[1] = w
+    V = xc_oracle.vmat_gga(mol, pts, np.zeros(len(pts)), wg)
+    assert np.abs(V).max() <= 1e-10 * np.abs(_overlap(mol)).max()
