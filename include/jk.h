@@ -272,6 +272,22 @@ int jk_xc_rho(const jk_basis* basis, const double* grid, int32_t n_grid, const d
 int jk_xc_vmat(const jk_basis* basis, const double* grid, int32_t n_grid, const double* wv,
                double eps, double* V, int64_t* tiles, void* hip_stream);
 
+/* The same for gradient-corrected functionals (the paper's hybrids are GGA and
+ * meta-GGA): with the first derivatives of every basis function (the distance
+ * cut-off then also bounds them, and a block is zero when the values and the
+ * three derivatives are all below eps),
+ *   jk_xc_rho_gga:  rho as above, grad_rho[m][c][g] = 2 sum_{mu,nu} d_c phi_mu(g)
+ *                   D[m][mu][nu] phi_nu(g)   (DEVICE [n_dm][3][n_grid])
+ *   jk_xc_vmat_gga: V[mu][nu] = sum_g wv[g] phi_mu phi_nu + sum_c wg[c][g]
+ *                   (d_c phi_mu phi_nu + phi_mu d_c phi_nu)   (wg DEVICE [3][n_grid]:
+ *                   the grid weight times the functional's derivative with respect to
+ *                   the density-gradient component c)
+ * Workspace four times that of the calls above. */
+int jk_xc_rho_gga(const jk_basis* basis, const double* grid, int32_t n_grid, const double* D,
+                  int32_t n_dm, double eps, double* rho, double* grad_rho, void* hip_stream);
+int jk_xc_vmat_gga(const jk_basis* basis, const double* grid, int32_t n_grid, const double* wv,
+                   const double* wg, double eps, double* V, void* hip_stream);
+
 /* Counters of the last successful jk_build / jk_grad.  With opts.timing = 1
  * this waits for the recorded events. */
 int jk_get_stats(jk_ctx* ctx, jk_stats* out);

@@ -78,6 +78,71 @@ __global__ void ao_kernel(const XcShell* __restrict__ sh, const double* __restri
   for (int c = 0; c < nc; ++c) phi[static_cast<size_t>(S.bf0 + c) * GB + g] = v[c];
 }
 
+// Values and first derivatives of shell s at point g of the batch: phi, then
+// d/dx, d/dy, d/dz phi, each [NA][GB], `mat` doubles apart.  With R0 = sum_k c_k
+// e_k and R1 = sum_k c_k a_k e_k (e_k = exp(-a_k r^2)), a component with
+// polynomial P (in the offsets from the centre C) has
+// d phi / d c = (dP/dc) R0 - 2 (c - C_c) P R1.
+__global__ void ao_grad_kernel(const XcShell* __restrict__ sh, const double* __restrict__ exps,
+                               const double* __restrict__ coefs, const double* __restrict__ grid,
+                               int g0, int ng, int GB, size_t mat, double* __restrict__ phi) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (g >= GB) return;
+  const XcShell S = sh[s];
+  const int nc = (S.l + 1) * (S.l + 2) / 2;
+  double v[4][6] = {};
+  if (g < ng) {
+    const double d[3] = {grid[3 * static_cast<size_t>(g0 + g)] - S.x,
+                         grid[3 * static_cast<size_t>(g0 + g) + 1] - S.y,
+                         grid[3 * static_cast<size_t>(g0 + g) + 2] - S.z};
+    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (r2 <= S.rcut2) {
+      double R0 = 0.0, R1 = 0.0;
+      for (int k = 0; k < S.nprim; ++k) {
+        const double e = coefs[S.prim0 + k] * exp(-exps[S.prim0 + k] * r2);
+        R0 += e;
+        R1 += exps[S.prim0 + k] * e;
+      }
+      // Cartesian powers in the library's order (descending x, then y)
+      int c = 0;
+      for (int px = S.l; px >= 0; --px)
+        for (int py = S.l - px; py >= 0; --py, ++c) {
+          const int pw[3] = {px, py, S.l - px - py};
+          double xp[3][3];   // xp[a][q] = d_a^q
+          for (int a = 0; a < 3; ++a) { xp[a][0] = 1.0; xp[a][1] = d[a]; xp[a][2] = d[a] * d[a]; }
+          const double P = xp[0][pw[0]] * xp[1][pw[1]] * xp[2][pw[2]];
+          v[0][c] = P * R0;
+          for (int a = 0; a < 3; ++a) {
+            double dP = 0.0;
+            if (pw[a] > 0) {
+              dP = pw[a] * xp[a][pw[a] - 1];
+              for (int b2 = 0; b2 < 3; ++b2)
+                if (b2 != a) dP *= xp[b2][pw[b2]];
+            }
+            v[1 + a][c] = dP * R0 - 2.0 * d[a] * P * R1;
+          }
+        }
+    }
+  }
+  for (int q = 0; q < 4; ++q)
+    for (int c = 0; c < nc; ++c) phi[q * mat + static_cast<size_t>(S.bf0 + c) * GB + g] = v[q][c];
+}
+
+// Block mask over phi and its three derivatives: one wavefront per block.
+__global__ __launch_bounds__(64) void mask4_kernel(const double* __restrict__ phi, int GB, size_t mat,
+                                                   double eps, unsigned char* __restrict__ mask) {
+  const int G = blockIdx.x, I = blockIdx.y, t = threadIdx.x;
+  double m = 0.0;
+  for (int q = 0; q < 4; ++q)
+    for (int e = t; e < 32 * 32; e += 64) {
+      const int i = e / 32, g = e % 32;
+      m = fmax(m, fabs(phi[q * mat + static_cast<size_t>(I * 32 + i) * GB + G * 32 + g]));
+    }
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if (t == 0) mask[static_cast<size_t>(I) * gridDim.x + G] = m >= eps ? 1 : 0;
+}
+
 __global__ void fill_kernel(double* p, size_t count, double v) {
   const size_t k = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k < count) p[k] = v;
@@ -135,11 +200,14 @@ __device__ __forceinline__ void tile_mfma(const double (*a)[kLd], const double (
 // rho partials: workgroup (G = blockIdx.x, k = blockIdx.y) takes AO block I =
 // list[G][k]; X_IG = sum over J in list[G] of D_IJ phi_JG; partial[G][k][g] =
 // sum_i phi_IG[i][g] X_IG[i][g].
+// GGA: also 2 sum_i d_c phi_IG[i][g] X_IG[i][g] for c = x, y, z (the derivative
+// matrices follow phi at `mat` doubles apart), partials [4][nGb][nIb][32].
+template <bool GGA>
 __global__ __launch_bounds__(kWaveT) void rho_kernel(const double* __restrict__ phi, int GB,
                                                      const double* __restrict__ D, int n,
                                                      const int* __restrict__ list,
                                                      const int* __restrict__ count, int nIb,
-                                                     double* __restrict__ partial) {
+                                                     size_t mat, double* __restrict__ partial) {
   const int G = blockIdx.x, k = blockIdx.y, t = threadIdx.x;
   const int cnt = count[G];
   if (k >= cnt) return;
@@ -178,23 +246,28 @@ __global__ __launch_bounds__(kWaveT) void rho_kernel(const double* __restrict__ 
   // column sums of phi_IG * X_IG: each lane sums its 8 rows of its two columns,
   // then the four lane groups that share a column are added
   const int l16 = t & 15, kq = t >> 4;
-  double part[2];
 #pragma unroll
-  for (int sj = 0; sj < 2; ++sj) {
-    double v = 0.0;
+  for (int q = 0; q < (GGA ? 4 : 1); ++q) {
+    const double* src = phi + q * mat;
+    double part[2];
 #pragma unroll
-    for (int si = 0; si < 2; ++si)
+    for (int sj = 0; sj < 2; ++sj) {
+      double v = 0.0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        v += phi[static_cast<size_t>(I * kB + 16 * si + kq + 4 * r) * GB + G * kB + 16 * sj + l16] *
-             acc[si][sj][r];
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    part[sj] = v;
-  }
-  if (kq == 0) {
-    partial[(static_cast<size_t>(G) * nIb + k) * kB + l16] = part[0];
-    partial[(static_cast<size_t>(G) * nIb + k) * kB + 16 + l16] = part[1];
+      for (int si = 0; si < 2; ++si)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          v += src[static_cast<size_t>(I * kB + 16 * si + kq + 4 * r) * GB + G * kB + 16 * sj + l16] *
+               acc[si][sj][r];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      part[sj] = q ? 2.0 * v : v;
+    }
+    if (kq == 0) {
+      double* out = partial + ((static_cast<size_t>(q) * gridDim.x + G) * nIb + k) * kB;
+      out[l16] = part[0];
+      out[16 + l16] = part[1];
+    }
   }
 }
 
@@ -209,16 +282,37 @@ __global__ void rho_reduce_kernel(const double* __restrict__ partial, const int*
   rho[g] = s;
 }
 
+// rho and grad rho of the batch's points (GGA): fixed-order sums of the partials,
+// thread (g, q): q = 0 rho, 1..3 the gradient components.
+__global__ void rho_gga_reduce_kernel(const double* __restrict__ partial,
+                                      const int* __restrict__ count, int nIb, int nGb, int ng,
+                                      double* __restrict__ rho, double* __restrict__ grad,
+                                      int n_grid) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (g >= ng) return;
+  const int G = g / kB;
+  double s = 0.0;
+  for (int k = 0; k < count[G]; ++k)
+    s += partial[((static_cast<size_t>(q) * nGb + G) * nIb + k) * kB + g % kB];
+  if (q == 0) rho[g] = s;
+  else grad[static_cast<size_t>(q - 1) * n_grid + g] = s;
+}
+
 // V_acc[z][I][J] (I >= J) += sum over the grid blocks G of chunk z with both
 // blocks nonzero of phi_IG diag(wv_G) phi_JG^T; workgroup (J = blockIdx.x,
 // I = blockIdx.y, z = blockIdx.z); the chunks are summed in order at the end.
+// GGA: every block pair (I, J), with the second operand
+// wv/2 phi_JG + sum_c wg_c d_c phi_JG (wg [3][n_grid]); V = V_acc + V_acc^T then.
+template <bool GGA>
 __global__ __launch_bounds__(kWaveT) void vmat_kernel(const double* __restrict__ phi, int GB,
                                                       const unsigned char* __restrict__ mask,
                                                       int nGb, const double* __restrict__ wv,
-                                                      int g0, int ng, int NA,
+                                                      const double* __restrict__ wg, int n_grid,
+                                                      size_t mat, int g0, int ng, int NA,
                                                       double* __restrict__ vacc) {
   const int J = blockIdx.x, I = blockIdx.y, t = threadIdx.x;
-  if (I < J) return;
+  if (!GGA && I < J) return;
   const int per = (nGb + kVChunks - 1) / kVChunks;
   const int Gb = blockIdx.z * per, Ge = min(nGb, Gb + per);
   vacc += static_cast<size_t>(blockIdx.z) * NA * NA;
@@ -253,12 +347,18 @@ __global__ __launch_bounds__(kWaveT) void vmat_kernel(const double* __restrict__
   // (the same point, so the same weight, for every u)
   auto fetch = [&](int G) {
     const int gg = G * kB + (t % kB);
-    const double w = gg < ng ? wv[g0 + gg] : 0.0;
+    const double w = gg < ng ? (GGA ? 0.5 : 1.0) * wv[g0 + gg] : 0.0;
+    double wc[3] = {0.0, 0.0, 0.0};
+    if (GGA && gg < ng)
+      for (int c = 0; c < 3; ++c) wc[c] = wg[static_cast<size_t>(c) * n_grid + g0 + gg];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int i = (t + kWaveT * u) / kB;
+      const size_t oj = static_cast<size_t>(J * kB + i) * GB + gg;
       ra[u] = phi[static_cast<size_t>(I * kB + i) * GB + gg];
-      rb[u] = w * phi[static_cast<size_t>(J * kB + i) * GB + gg];
+      double v = w * phi[oj];
+      if (GGA) v += wc[0] * phi[mat + oj] + wc[1] * phi[2 * mat + oj] + wc[2] * phi[3 * mat + oj];
+      rb[u] = v;
     }
   };
   int G = next_g(0);
@@ -301,16 +401,37 @@ __global__ void vmat_finish_kernel(const double* __restrict__ vacc, int NA, int 
   V[e] = s;
 }
 
+// GGA: V = S + S^T with S the chunk sums of V_acc over every block pair.
+__global__ void vmat_gga_finish_kernel(const double* __restrict__ vacc, int NA, int n,
+                                       double* __restrict__ V) {
+  const size_t e = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= static_cast<size_t>(n) * n) return;
+  const int mu = static_cast<int>(e / n), nu = static_cast<int>(e % n);
+  double a = 0.0, b = 0.0;   // the two chunk sums, added last: V exactly symmetric
+  for (int z = 0; z < kVChunks; ++z) {
+    const double* vz = vacc + static_cast<size_t>(z) * NA * NA;
+    a += vz[static_cast<size_t>(mu) * NA + nu];
+    b += vz[static_cast<size_t>(nu) * NA + mu];
+  }
+  V[e] = a + b;
+}
+
 // Cut-off radius of a shell: the largest r with r^l sum_k |c_k| exp(-a_k r^2) >= eps
 // (past the last maximum of every term, the bound only decreases).
-double cutoff_radius(int l, const double* a, const double* c, int np, double eps) {
+// With derivatives (deriv), the bound also covers every first derivative:
+// sum_k |c_k| (l r^(l-1) + 2 a_k r^(l+1)) exp(-a_k r^2).
+double cutoff_radius(int l, const double* a, const double* c, int np, double eps, bool deriv) {
   auto f = [&](double r) {
-    double s = 0.0;
-    for (int k = 0; k < np; ++k) s += std::fabs(c[k]) * std::exp(-a[k] * r * r);
-    return std::pow(r, l) * s;
+    double s = 0.0, sd = 0.0;
+    for (int k = 0; k < np; ++k) {
+      const double e = std::fabs(c[k]) * std::exp(-a[k] * r * r);
+      s += e;
+      sd += e * ((l > 0 ? l * std::pow(r, l - 1) : 0.0) + 2.0 * a[k] * std::pow(r, l + 1));
+    }
+    return deriv ? std::max(std::pow(r, l) * s, sd) : std::pow(r, l) * s;
   };
-  double lo = 0.0;
-  for (int k = 0; k < np; ++k) lo = std::max(lo, std::sqrt(0.5 * l / a[k]));
+  double lo = 0.0;   // past every term's last maximum (l + 1 covers the derivatives)
+  for (int k = 0; k < np; ++k) lo = std::max(lo, std::sqrt(0.5 * (deriv ? l + 1 : l) / a[k]));
   double hi = std::max(2.0 * lo, 1.0);
   while (f(hi) >= eps && hi < 1e4) hi *= 2.0;
   if (f(lo) < eps) return lo;
@@ -326,6 +447,7 @@ struct XcCall {
   hipStream_t s = nullptr;
   std::vector<void*> bufs;
   int n = 0, NA = 0, nIb = 0, ns = 0;
+  bool gga = false;   // phi and its three derivatives
   XcShell* shells = nullptr;
   double *exps = nullptr, *coefs = nullptr, *phi = nullptr;
   unsigned char* mask = nullptr;
@@ -344,7 +466,7 @@ struct XcCall {
   }
 };
 
-int xc_setup(XcCall& x, const jk_basis* b, double eps) {
+int xc_setup(XcCall& x, const jk_basis* b, double eps, bool gga) {
   int32_t n = 0;
   const int rc = jk_validate_basis(b, &n);
   if (rc != JK_OK) return rc;
@@ -352,6 +474,7 @@ int xc_setup(XcCall& x, const jk_basis* b, double eps) {
   x.NA = (n + kB - 1) / kB * kB;
   x.nIb = x.NA / kB;
   x.ns = b->n_shells;
+  x.gga = gga;
   if (x.ns > 65535) return JK_EUNSUPPORTED;
   std::vector<XcShell> hs(x.ns);
   int np = 0, bf = 0;
@@ -359,14 +482,15 @@ int xc_setup(XcCall& x, const jk_basis* b, double eps) {
   for (int s = 0; s < x.ns; ++s) {
     const int l = b->shell_l[s], a = b->shell_atom[s];
     const double r = cutoff_radius(l, b->exps + b->shell_prim0[s], b->coefs + b->shell_prim0[s],
-                                   b->shell_nprim[s], eps);
+                                   b->shell_nprim[s], eps, gga);
     hs[s] = XcShell{b->xyz[3 * a], b->xyz[3 * a + 1], b->xyz[3 * a + 2], r * r, l,
                     b->shell_nprim[s], bf, b->shell_prim0[s]};
     bf += (l + 1) * (l + 2) / 2;
   }
   const int nGb = kBatch / kB;
   if (!x.alloc(&x.shells, hs.size() * sizeof(XcShell)) || !x.alloc(&x.exps, np * 8) ||
-      !x.alloc(&x.coefs, np * 8) || !x.alloc(&x.phi, static_cast<size_t>(x.NA) * kBatch * 8) ||
+      !x.alloc(&x.coefs, np * 8) ||
+      !x.alloc(&x.phi, static_cast<size_t>(gga ? 4 : 1) * x.NA * kBatch * 8) ||
       !x.alloc(&x.mask, static_cast<size_t>(x.nIb) * nGb) ||
       !x.alloc(&x.list, static_cast<size_t>(nGb) * x.nIb * 4) || !x.alloc(&x.count, nGb * 4))
     return JK_ENOMEM;
@@ -381,13 +505,21 @@ int xc_setup(XcCall& x, const jk_basis* b, double eps) {
 // AO values, mask and lists of one batch (points g0 .. g0+ng-1).
 void xc_batch(XcCall& x, const double* grid, int g0, int ng, int GB, double eps) {
   const int nGb = GB / kB;
+  const size_t mat = static_cast<size_t>(x.NA) * GB;
   // padding rows (functions n .. NA-1) are zero at this batch's row stride
   const size_t pad = static_cast<size_t>(x.NA - x.n) * GB;
-  if (pad) hipLaunchKernelGGL(fill_kernel, dim3((pad + 255) / 256), dim3(256), 0, x.s,
-                              x.phi + static_cast<size_t>(x.n) * GB, pad, 0.0);
-  hipLaunchKernelGGL(ao_kernel, dim3((GB + 255) / 256, x.ns), dim3(256), 0, x.s, x.shells, x.exps,
-                     x.coefs, grid, g0, ng, GB, x.phi);
-  hipLaunchKernelGGL(mask_kernel, dim3(nGb, x.nIb), dim3(kWaveT), 0, x.s, x.phi, GB, eps, x.mask);
+  for (int q = 0; q < (x.gga ? 4 : 1); ++q)
+    if (pad) hipLaunchKernelGGL(fill_kernel, dim3((pad + 255) / 256), dim3(256), 0, x.s,
+                                x.phi + q * mat + static_cast<size_t>(x.n) * GB, pad, 0.0);
+  if (x.gga) {
+    hipLaunchKernelGGL(ao_grad_kernel, dim3((GB + 255) / 256, x.ns), dim3(256), 0, x.s, x.shells,
+                       x.exps, x.coefs, grid, g0, ng, GB, mat, x.phi);
+    hipLaunchKernelGGL(mask4_kernel, dim3(nGb, x.nIb), dim3(64), 0, x.s, x.phi, GB, mat, eps, x.mask);
+  } else {
+    hipLaunchKernelGGL(ao_kernel, dim3((GB + 255) / 256, x.ns), dim3(256), 0, x.s, x.shells, x.exps,
+                       x.coefs, grid, g0, ng, GB, x.phi);
+    hipLaunchKernelGGL(mask_kernel, dim3(nGb, x.nIb), dim3(kWaveT), 0, x.s, x.phi, GB, eps, x.mask);
+  }
   hipLaunchKernelGGL(list_kernel, dim3((nGb + 63) / 64), dim3(64), 0, x.s, x.mask, x.nIb, nGb,
                      x.list, x.count);
 }
@@ -414,7 +546,7 @@ int jk_xc_rho(const jk_basis* basis, const double* grid, int32_t n_grid, const d
     return JK_EINVAL;
   XcCall x;
   x.s = static_cast<hipStream_t>(hip_stream);
-  int rc = xc_setup(x, basis, eps);
+  int rc = xc_setup(x, basis, eps, false);
   if (rc != JK_OK) return rc;
   double* partial = nullptr;
   if (!x.alloc(&partial, static_cast<size_t>(kBatch / kB) * x.nIb * kB * 8)) return JK_ENOMEM;
@@ -427,8 +559,8 @@ int jk_xc_rho(const jk_basis* basis, const double* grid, int32_t n_grid, const d
                          n_dm, reinterpret_cast<unsigned long long*>(tiles));
     for (int m = 0; m < n_dm; ++m) {
       const double* Dm = D + static_cast<size_t>(m) * x.n * x.n;
-      hipLaunchKernelGGL(rho_kernel, dim3(nGb, x.nIb), dim3(kWaveT), 0, x.s, x.phi, GB, Dm, x.n,
-                         x.list, x.count, x.nIb, partial);
+      hipLaunchKernelGGL(rho_kernel<false>, dim3(nGb, x.nIb), dim3(kWaveT), 0, x.s, x.phi, GB, Dm,
+                         x.n, x.list, x.count, x.nIb, size_t(0), partial);
       hipLaunchKernelGGL(rho_reduce_kernel, dim3((ng + 255) / 256), dim3(256), 0, x.s, partial,
                          x.count, x.nIb, ng, rho + static_cast<size_t>(m) * n_grid + g0);
     }
@@ -441,7 +573,7 @@ int jk_xc_vmat(const jk_basis* basis, const double* grid, int32_t n_grid, const 
   if (!grid || !wv || !V || n_grid < 1 || !check_eps(eps)) return JK_EINVAL;
   XcCall x;
   x.s = static_cast<hipStream_t>(hip_stream);
-  int rc = xc_setup(x, basis, eps);
+  int rc = xc_setup(x, basis, eps, false);
   if (rc != JK_OK) return rc;
   double* vacc = nullptr;
   const size_t na2 = static_cast<size_t>(x.NA) * x.NA * kVChunks;
@@ -454,11 +586,66 @@ int jk_xc_vmat(const jk_basis* basis, const double* grid, int32_t n_grid, const 
     if (tiles)
       hipLaunchKernelGGL(tiles_kernel, dim3((nGb + 255) / 256), dim3(256), 0, x.s, x.count, nGb, 1,
                          1, reinterpret_cast<unsigned long long*>(tiles));
-    hipLaunchKernelGGL(vmat_kernel, dim3(x.nIb, x.nIb, kVChunks), dim3(kWaveT), 0, x.s, x.phi, GB, x.mask,
-                       nGb, wv, g0, ng, x.NA, vacc);
+    hipLaunchKernelGGL(vmat_kernel<false>, dim3(x.nIb, x.nIb, kVChunks), dim3(kWaveT), 0, x.s,
+                       x.phi, GB, x.mask, nGb, wv, static_cast<const double*>(nullptr), n_grid,
+                       size_t(0), g0, ng, x.NA, vacc);
   }
   const size_t nn = static_cast<size_t>(x.n) * x.n;
   hipLaunchKernelGGL(vmat_finish_kernel, dim3((nn + 255) / 256), dim3(256), 0, x.s, vacc, x.NA,
+                     x.n, V);
+  return hipGetLastError() == hipSuccess ? JK_OK : JK_EHIP;
+}
+
+int jk_xc_rho_gga(const jk_basis* basis, const double* grid, int32_t n_grid, const double* D,
+                  int32_t n_dm, double eps, double* rho, double* grad_rho, void* hip_stream) {
+  if (!grid || !D || !rho || !grad_rho || n_grid < 1 || n_dm < 1 || n_dm > JK_MAX_NDM ||
+      !check_eps(eps))
+    return JK_EINVAL;
+  XcCall x;
+  x.s = static_cast<hipStream_t>(hip_stream);
+  int rc = xc_setup(x, basis, eps, true);
+  if (rc != JK_OK) return rc;
+  double* partial = nullptr;
+  if (!x.alloc(&partial, static_cast<size_t>(4) * (kBatch / kB) * x.nIb * kB * 8)) return JK_ENOMEM;
+  for (int g0 = 0; g0 < n_grid; g0 += kBatch) {
+    const int ng = std::min(kBatch, n_grid - g0);
+    const int GB = (ng + kB - 1) / kB * kB, nGb = GB / kB;
+    const size_t mat = static_cast<size_t>(x.NA) * GB;
+    xc_batch(x, grid, g0, ng, GB, eps);
+    for (int m = 0; m < n_dm; ++m) {
+      const double* Dm = D + static_cast<size_t>(m) * x.n * x.n;
+      hipLaunchKernelGGL(rho_kernel<true>, dim3(nGb, x.nIb), dim3(kWaveT), 0, x.s, x.phi, GB, Dm,
+                         x.n, x.list, x.count, x.nIb, mat, partial);
+      hipLaunchKernelGGL(rho_gga_reduce_kernel, dim3((ng + 255) / 256, 4), dim3(256), 0, x.s,
+                         partial, x.count, x.nIb, nGb, ng,
+                         rho + static_cast<size_t>(m) * n_grid + g0,
+                         grad_rho + static_cast<size_t>(m) * 3 * n_grid + g0, n_grid);
+    }
+  }
+  return hipGetLastError() == hipSuccess ? JK_OK : JK_EHIP;
+}
+
+int jk_xc_vmat_gga(const jk_basis* basis, const double* grid, int32_t n_grid, const double* wv,
+                   const double* wg, double eps, double* V, void* hip_stream) {
+  if (!grid || !wv || !wg || !V || n_grid < 1 || !check_eps(eps)) return JK_EINVAL;
+  XcCall x;
+  x.s = static_cast<hipStream_t>(hip_stream);
+  int rc = xc_setup(x, basis, eps, true);
+  if (rc != JK_OK) return rc;
+  double* vacc = nullptr;
+  const size_t na2 = static_cast<size_t>(x.NA) * x.NA * kVChunks;
+  if (!x.alloc(&vacc, na2 * 8)) return JK_ENOMEM;
+  hipLaunchKernelGGL(fill_kernel, dim3((na2 + 255) / 256), dim3(256), 0, x.s, vacc, na2, 0.0);
+  for (int g0 = 0; g0 < n_grid; g0 += kBatch) {
+    const int ng = std::min(kBatch, n_grid - g0);
+    const int GB = (ng + kB - 1) / kB * kB, nGb = GB / kB;
+    const size_t mat = static_cast<size_t>(x.NA) * GB;
+    xc_batch(x, grid, g0, ng, GB, eps);
+    hipLaunchKernelGGL(vmat_kernel<true>, dim3(x.nIb, x.nIb, kVChunks), dim3(kWaveT), 0, x.s,
+                       x.phi, GB, x.mask, nGb, wv, wg, n_grid, mat, g0, ng, x.NA, vacc);
+  }
+  const size_t nn = static_cast<size_t>(x.n) * x.n;
+  hipLaunchKernelGGL(vmat_gga_finish_kernel, dim3((nn + 255) / 256), dim3(256), 0, x.s, vacc, x.NA,
                      x.n, V);
   return hipGetLastError() == hipSuccess ? JK_OK : JK_EHIP;
 }

@@ -25,7 +25,8 @@ ERR_NAMES = {1: "JK_EINVAL", 2: "JK_EUNSUPPORTED", 3: "JK_ENOMEM", 4: "JK_EHIP"}
 EXPORTS = ["jk_opts_default", "jk_ctx_create", "jk_ctx_destroy", "jk_validate_basis", "jk_build",
            "jk_build_noalloc", "jk_grad", "jk_get_stats", "jk_last_error", "jk_pure_count",
            "jk_pure_to_cart", "jk_cart_to_pure", "jk_scf_create", "jk_scf_destroy", "jk_scf_diag",
-           "jk_scf_diis", "jk_scf_diis_reset", "jk_xc_rho", "jk_xc_vmat"]
+           "jk_scf_diis", "jk_scf_diis_reset", "jk_xc_rho", "jk_xc_vmat", "jk_xc_rho_gga",
+           "jk_xc_vmat_gga"]
 
 
 class JkError(RuntimeError):
@@ -103,6 +104,10 @@ def load():
                               ctypes.c_double, vp, vp, vp]
     lib.jk_xc_vmat.argtypes = [ctypes.POINTER(jk_basis), vp, ctypes.c_int32, vp, ctypes.c_double,
                                vp, vp, vp]
+    lib.jk_xc_rho_gga.argtypes = [ctypes.POINTER(jk_basis), vp, ctypes.c_int32, vp, ctypes.c_int32,
+                                  ctypes.c_double, vp, vp, vp]
+    lib.jk_xc_vmat_gga.argtypes = [ctypes.POINTER(jk_basis), vp, ctypes.c_int32, vp, vp,
+                                   ctypes.c_double, vp, vp]
     _lib = lib
     return lib
 
@@ -376,6 +381,47 @@ def xc_vmat(mol, grid, wv, eps: float = 1e-12, tiles=None):
                            _stream_ptr(torch, grid.device))
     if rc != JK_OK:
         raise JkError(rc, "jk_xc_vmat")
+    return V
+
+
+def xc_rho_gga(mol, grid, D, eps: float = 1e-12):
+    """(rho [n_dm][n_grid], grad rho [n_dm][3][n_grid]) (jk_xc_rho_gga); D [n][n]
+    gives [n_grid] and [3][n_grid]."""
+    import torch
+    basis = mol if isinstance(mol, Basis) else Basis(mol)
+    n = jk_validate_basis(basis)
+    squeeze = D.dim() == 2
+    Dd = (D.unsqueeze(0) if squeeze else D).contiguous()
+    _check_dev(grid, (grid.shape[0], 3), "grid")
+    _check_dev(Dd, (Dd.shape[0], n, n), "D")
+    ng = grid.shape[0]
+    rho = torch.empty((Dd.shape[0], ng), dtype=torch.float64, device=grid.device)
+    grad = torch.empty((Dd.shape[0], 3, ng), dtype=torch.float64, device=grid.device)
+    rc = load().jk_xc_rho_gga(ctypes.byref(basis.c), ctypes.c_void_p(grid.data_ptr()), int(ng),
+                              ctypes.c_void_p(Dd.data_ptr()), int(Dd.shape[0]), float(eps),
+                              ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                              _stream_ptr(torch, grid.device))
+    if rc != JK_OK:
+        raise JkError(rc, "jk_xc_rho_gga")
+    return (rho[0], grad[0]) if squeeze else (rho, grad)
+
+
+def xc_vmat_gga(mol, grid, wv, wg, eps: float = 1e-12):
+    """V with the density-gradient terms (jk_xc_vmat_gga); wv [n_grid], wg [3][n_grid]."""
+    import torch
+    basis = mol if isinstance(mol, Basis) else Basis(mol)
+    n = jk_validate_basis(basis)
+    ng = grid.shape[0]
+    _check_dev(grid, (ng, 3), "grid")
+    _check_dev(wv, (ng,), "wv")
+    _check_dev(wg, (3, ng), "wg")
+    V = torch.empty((n, n), dtype=torch.float64, device=grid.device)
+    rc = load().jk_xc_vmat_gga(ctypes.byref(basis.c), ctypes.c_void_p(grid.data_ptr()), int(ng),
+                               ctypes.c_void_p(wv.data_ptr()), ctypes.c_void_p(wg.data_ptr()),
+                               float(eps), ctypes.c_void_p(V.data_ptr()),
+                               _stream_ptr(torch, grid.device))
+    if rc != JK_OK:
+        raise JkError(rc, "jk_xc_vmat_gga")
     return V
 
 

@@ -101,3 +101,36 @@ def test_xc_argument_checks():
     assert lib.jk_xc_vmat(ctypes.byref(b.c), p(G), 10, None, 1e-12, p(D), None, s) == jkb.JK_EINVAL
     torch.cuda.synchronize()
     assert bool((rho == 7.0).all())
+
+
+GGA_CASES = [("w4", lambda: molgen.workload("w4"), (30, 50), 1e-14, 1e-11),
+             ("w30, three batches", lambda: molgen.workload("w30"), (30, 37), 1e-12, 1e-9)]
+
+
+@pytest.mark.parametrize("name,make,grid,eps,rel", GGA_CASES, ids=[c[0] for c in GGA_CASES])
+def test_xc_gga_against_oracle(name, make, grid, eps, rel):
+    """Gradient-corrected terms: rho, grad rho and the GGA matrix against the dense
+    oracle (analytic AO derivatives)."""
+    import torch
+    from paper_2406_11185_amd import jk as jkb
+    mol = make()
+    pts, w = molgen.atom_grid(mol, *grid)
+    wv = _wv(pts, w, 3)
+    rng = np.random.default_rng(4)
+    wg = np.stack([_wv(pts, w, 5 + c) * rng.uniform(0.5, 1.5) for c in range(3)])
+    say(f"case XC GGA {name} ({mol.n_bf} functions, {len(pts)} points, eps {eps})")
+    G = torch.as_tensor(pts, device="cuda")
+    D = torch.as_tensor(mol.D, device="cuda")
+    rho, grad = jkb.xc_rho_gga(mol, G, D, eps)
+    V = jkb.xc_vmat_gga(mol, G, torch.as_tensor(wv, device="cuda"),
+                        torch.as_tensor(wg, device="cuda").contiguous(), eps)
+    rho, grad, V = rho.cpu().numpy(), grad.cpu().numpy(), V.cpu().numpy()
+    ro = xc_oracle.rho(mol, pts, mol.D)
+    go = xc_oracle.rho_grad(mol, pts, mol.D)
+    Vo = xc_oracle.vmat_gga(mol, pts, wv, wg)
+    say(f"  max|drho|={np.abs(rho - ro).max():.2e} max|dgrad|={np.abs(grad - go).max():.2e} "
+        f"(max {np.abs(go).max():.2e}) max|dV|={np.abs(V - Vo).max():.2e} (max {np.abs(Vo).max():.2e})")
+    assert np.abs(rho - ro).max() <= rel * np.abs(ro).max()
+    assert np.abs(grad - go).max() <= rel * np.abs(go).max()
+    assert np.abs(V - Vo).max() <= rel * np.abs(Vo).max()
+    np.testing.assert_array_equal(V, V.T)
