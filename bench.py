@@ -340,8 +340,22 @@ def extra_measurements(args, jkb, molgen, ctx, mol, basis, D, J, K, E_head, tol,
             tf = int(tiles.cpu()[0]) / 2 * 2 * 32 ** 3 / (ms / 1e3) / 1e12
             xc[name] = {"ms": ms, "block_products": int(tiles.cpu()[0]) // 2,
                         "tflops_algorithmic": tf, "frac_of_fp64_vector_peak": tf / 78.6}
+        # gradient-corrected terms: rho with grad rho, and V with the grad-rho
+        # derivative terms (synthetic derivative weights)
+        wgd = torch.stack([wvd * (0.5 + 0.1 * c) for c in range(3)]).contiguous()
+        jkb.xc_rho_gga(mol, Gd, D0)
+        jkb.xc_vmat_gga(mol, Gd, wvd, wgd)
+        for name, call in (("rho_gga", lambda: jkb.xc_rho_gga(mol, Gd, D0)),
+                           ("vmat_gga", lambda: jkb.xc_vmat_gga(mol, Gd, wvd, wgd))):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(2):
+                call()
+            e1.record()
+            torch.cuda.synchronize()
+            xc[name] = {"ms": e0.elapsed_time(e1) / 2}
         ex["xc_grid"] = xc
-        progress("XC grid part (rho, V) done")
+        progress("XC grid part (rho, V, and their gradient-corrected forms) done")
     if n_dm == 1 and args.with_grad:
         # nuclear gradient of the 30-atom molecule, FP64 and mixed
         mg = molgen.workload("w30grad")
