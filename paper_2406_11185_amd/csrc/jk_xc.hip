@@ -302,8 +302,9 @@ __global__ void rho_gga_reduce_kernel(const double* __restrict__ partial,
 // V_acc[z][I][J] (I >= J) += sum over the grid blocks G of chunk z with both
 // blocks nonzero of phi_IG diag(wv_G) phi_JG^T; workgroup (J = blockIdx.x,
 // I = blockIdx.y, z = blockIdx.z); the chunks are summed in order at the end.
-// GGA: every block pair (I, J), with the second operand
-// wv/2 phi_JG + sum_c wg_c d_c phi_JG (wg [3][n_grid]); V = V_acc + V_acc^T then.
+// GGA: every block pair (I, J), with the second operand psi_JG = wv/2 phi_JG +
+// sum_c wg_c d_c phi_JG, formed beforehand in the d/dx slot (psi_kernel); V =
+// V_acc + V_acc^T then.
 template <bool GGA>
 __global__ __launch_bounds__(kWaveT) void vmat_kernel(const double* __restrict__ phi, int GB,
                                                       const unsigned char* __restrict__ mask,
@@ -347,18 +348,13 @@ __global__ __launch_bounds__(kWaveT) void vmat_kernel(const double* __restrict__
   // (the same point, so the same weight, for every u)
   auto fetch = [&](int G) {
     const int gg = G * kB + (t % kB);
-    const double w = gg < ng ? (GGA ? 0.5 : 1.0) * wv[g0 + gg] : 0.0;
-    double wc[3] = {0.0, 0.0, 0.0};
-    if (GGA && gg < ng)
-      for (int c = 0; c < 3; ++c) wc[c] = wg[static_cast<size_t>(c) * n_grid + g0 + gg];
+    const double w = !GGA && gg < ng ? wv[g0 + gg] : 0.0;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int i = (t + kWaveT * u) / kB;
       const size_t oj = static_cast<size_t>(J * kB + i) * GB + gg;
       ra[u] = phi[static_cast<size_t>(I * kB + i) * GB + gg];
-      double v = w * phi[oj];
-      if (GGA) v += wc[0] * phi[mat + oj] + wc[1] * phi[2 * mat + oj] + wc[2] * phi[3 * mat + oj];
-      rb[u] = v;
+      rb[u] = GGA ? phi[mat + oj] : w * phi[oj];
     }
   };
   int G = next_g(0);
@@ -399,6 +395,22 @@ __global__ void vmat_finish_kernel(const double* __restrict__ vacc, int NA, int 
   double s = 0.0;
   for (int z = 0; z < kVChunks; ++z) s += vacc[static_cast<size_t>(z) * NA * NA + o];
   V[e] = s;
+}
+
+// psi = wv/2 phi + sum_c wg_c d_c phi, elementwise over the batch, written over
+// the d/dx matrix (which is read first at the same element).
+__global__ void psi_kernel(double* __restrict__ phi, size_t mat, int GB, const double* __restrict__ wv,
+                           const double* __restrict__ wg, int n_grid, int g0, int ng) {
+  const size_t e = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= mat) return;
+  const int g = static_cast<int>(e % GB);
+  double v = 0.0;
+  if (g < ng) {
+    const size_t p = static_cast<size_t>(g0) + g;
+    v = 0.5 * wv[p] * phi[e] + wg[p] * phi[mat + e] + wg[n_grid + p] * phi[2 * mat + e] +
+        wg[2 * static_cast<size_t>(n_grid) + p] * phi[3 * mat + e];
+  }
+  phi[mat + e] = v;
 }
 
 // GGA: V = S + S^T with S the chunk sums of V_acc over every block pair.
@@ -641,6 +653,8 @@ int jk_xc_vmat_gga(const jk_basis* basis, const double* grid, int32_t n_grid, co
     const int GB = (ng + kB - 1) / kB * kB, nGb = GB / kB;
     const size_t mat = static_cast<size_t>(x.NA) * GB;
     xc_batch(x, grid, g0, ng, GB, eps);
+    hipLaunchKernelGGL(psi_kernel, dim3((mat + 255) / 256), dim3(256), 0, x.s, x.phi, mat, GB, wv,
+                       wg, n_grid, g0, ng);
     hipLaunchKernelGGL(vmat_kernel<true>, dim3(x.nIb, x.nIb, kVChunks), dim3(kWaveT), 0, x.s,
                        x.phi, GB, x.mask, nGb, wv, wg, n_grid, mat, g0, ng, x.NA, vacc);
   }
