@@ -78,21 +78,43 @@ __global__ void ao_kernel(const XcShell* __restrict__ sh, const double* __restri
   for (int c = 0; c < nc; ++c) phi[static_cast<size_t>(S.bf0 + c) * GB + g] = v[c];
 }
 
-// Values and first derivatives of shell s at point g of the batch: phi, then
-// d/dx, d/dy, d/dz phi, each [NA][GB], `mat` doubles apart.  With R0 = sum_k c_k
-// e_k and R1 = sum_k c_k a_k e_k (e_k = exp(-a_k r^2)), a component with
-// polynomial P (in the offsets from the centre C) has
-// d phi / d c = (dP/dc) R0 - 2 (c - C_c) P R1.
-__global__ void ao_grad_kernel(const XcShell* __restrict__ sh, const double* __restrict__ exps,
-                               const double* __restrict__ coefs, const double* __restrict__ grid,
-                               int g0, int ng, int GB, size_t mat, double* __restrict__ phi) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = blockIdx.y;
-  if (g >= GB) return;
-  const XcShell S = sh[s];
-  const int nc = (S.l + 1) * (S.l + 2) / 2;
+template <int L>
+__device__ __forceinline__ void ao_grad_values(const double d[3], double R0, double R1,
+                                               double v[4][6]) {
+  int c = 0;
+#pragma unroll
+  for (int px = L; px >= 0; --px)
+#pragma unroll
+    for (int py = L - px; py >= 0; --py, ++c) {
+      const int pw[3] = {px, py, L - px - py};
+      double xp[3][3];   // xp[a][q] = d_a^q
+#pragma unroll
+      for (int a = 0; a < 3; ++a) { xp[a][0] = 1.0; xp[a][1] = d[a]; xp[a][2] = d[a] * d[a]; }
+      const double P = xp[0][pw[0]] * xp[1][pw[1]] * xp[2][pw[2]];
+      v[0][c] = P * R0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        double dP = 0.0;
+        if (pw[a] > 0) {
+          dP = pw[a] * xp[a][pw[a] - 1];
+#pragma unroll
+          for (int b2 = 0; b2 < 3; ++b2)
+            if (b2 != a) dP *= xp[b2][pw[b2]];
+        }
+        v[1 + a][c] = dP * R0 - 2.0 * d[a] * P * R1;
+      }
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void ao_grad_shell(const XcShell& S, const double* __restrict__ exps,
+                                              const double* __restrict__ coefs,
+                                              const double* __restrict__ grid, int g0, int g,
+                                              bool in, int GB, size_t mat,
+                                              double* __restrict__ phi) {
+  constexpr int NC = (L + 1) * (L + 2) / 2;
   double v[4][6] = {};
-  if (g < ng) {
+  if (in) {
     const double d[3] = {grid[3 * static_cast<size_t>(g0 + g)] - S.x,
                          grid[3 * static_cast<size_t>(g0 + g) + 1] - S.y,
                          grid[3 * static_cast<size_t>(g0 + g) + 2] - S.z};
@@ -104,29 +126,32 @@ __global__ void ao_grad_kernel(const XcShell* __restrict__ sh, const double* __r
         R0 += e;
         R1 += exps[S.prim0 + k] * e;
       }
-      // Cartesian powers in the library's order (descending x, then y)
-      int c = 0;
-      for (int px = S.l; px >= 0; --px)
-        for (int py = S.l - px; py >= 0; --py, ++c) {
-          const int pw[3] = {px, py, S.l - px - py};
-          double xp[3][3];   // xp[a][q] = d_a^q
-          for (int a = 0; a < 3; ++a) { xp[a][0] = 1.0; xp[a][1] = d[a]; xp[a][2] = d[a] * d[a]; }
-          const double P = xp[0][pw[0]] * xp[1][pw[1]] * xp[2][pw[2]];
-          v[0][c] = P * R0;
-          for (int a = 0; a < 3; ++a) {
-            double dP = 0.0;
-            if (pw[a] > 0) {
-              dP = pw[a] * xp[a][pw[a] - 1];
-              for (int b2 = 0; b2 < 3; ++b2)
-                if (b2 != a) dP *= xp[b2][pw[b2]];
-            }
-            v[1 + a][c] = dP * R0 - 2.0 * d[a] * P * R1;
-          }
-        }
+      ao_grad_values<L>(d, R0, R1, v);
     }
   }
+#pragma unroll
   for (int q = 0; q < 4; ++q)
-    for (int c = 0; c < nc; ++c) phi[q * mat + static_cast<size_t>(S.bf0 + c) * GB + g] = v[q][c];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) phi[q * mat + static_cast<size_t>(S.bf0 + c) * GB + g] = v[q][c];
+}
+
+// Values and first derivatives of shell s at point g of the batch: phi, then
+// d/dx, d/dy, d/dz phi, each [NA][GB], `mat` doubles apart.  With R0 = sum_k c_k
+// e_k and R1 = sum_k c_k a_k e_k (e_k = exp(-a_k r^2)), a component with
+// polynomial P (in the offsets from the centre C) has
+// d phi / d c = (dP/dc) R0 - 2 (c - C_c) P R1.  The angular momentum is a
+// template argument of the evaluation, so every array index is a constant.
+__global__ void ao_grad_kernel(const XcShell* __restrict__ sh, const double* __restrict__ exps,
+                               const double* __restrict__ coefs, const double* __restrict__ grid,
+                               int g0, int ng, int GB, size_t mat, double* __restrict__ phi) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (g >= GB) return;
+  const XcShell S = sh[s];
+  const bool in = g < ng;
+  if (S.l == 0) ao_grad_shell<0>(S, exps, coefs, grid, g0, g, in, GB, mat, phi);
+  else if (S.l == 1) ao_grad_shell<1>(S, exps, coefs, grid, g0, g, in, GB, mat, phi);
+  else ao_grad_shell<2>(S, exps, coefs, grid, g0, g, in, GB, mat, phi);
 }
 
 // Block mask over phi and its three derivatives: one wavefront per block.
