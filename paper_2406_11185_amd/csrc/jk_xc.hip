@@ -79,7 +79,7 @@ __global__ void ao_kernel(const XcShell* __restrict__ sh, const double* __restri
 }
 
 template <int L>
-__device__ __forceinline__ void ao_grad_values(const double d[3], double R0, double R1,
+__device__ __forceinline__ void ao_deriv_values(const double d[3], double R0, double R1,
                                                double v[4][6]) {
   int c = 0;
 #pragma unroll
@@ -107,7 +107,7 @@ __device__ __forceinline__ void ao_grad_values(const double d[3], double R0, dou
 }
 
 template <int L>
-__device__ __forceinline__ void ao_grad_shell(const XcShell& S, const double* __restrict__ exps,
+__device__ __forceinline__ void ao_deriv_shell(const XcShell& S, const double* __restrict__ exps,
                                               const double* __restrict__ coefs,
                                               const double* __restrict__ grid, int g0, int g,
                                               bool in, int GB, size_t mat,
@@ -126,7 +126,7 @@ __device__ __forceinline__ void ao_grad_shell(const XcShell& S, const double* __
         R0 += e;
         R1 += exps[S.prim0 + k] * e;
       }
-      ao_grad_values<L>(d, R0, R1, v);
+      ao_deriv_values<L>(d, R0, R1, v);
     }
   }
 #pragma unroll
@@ -141,7 +141,7 @@ __device__ __forceinline__ void ao_grad_shell(const XcShell& S, const double* __
 // polynomial P (in the offsets from the centre C) has
 // d phi / d c = (dP/dc) R0 - 2 (c - C_c) P R1.  The angular momentum is a
 // template argument of the evaluation, so every array index is a constant.
-__global__ void ao_grad_kernel(const XcShell* __restrict__ sh, const double* __restrict__ exps,
+__global__ void ao_deriv_kernel(const XcShell* __restrict__ sh, const double* __restrict__ exps,
                                const double* __restrict__ coefs, const double* __restrict__ grid,
                                int g0, int ng, int GB, size_t mat, double* __restrict__ phi) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -149,9 +149,9 @@ __global__ void ao_grad_kernel(const XcShell* __restrict__ sh, const double* __r
   if (g >= GB) return;
   const XcShell S = sh[s];
   const bool in = g < ng;
-  if (S.l == 0) ao_grad_shell<0>(S, exps, coefs, grid, g0, g, in, GB, mat, phi);
-  else if (S.l == 1) ao_grad_shell<1>(S, exps, coefs, grid, g0, g, in, GB, mat, phi);
-  else ao_grad_shell<2>(S, exps, coefs, grid, g0, g, in, GB, mat, phi);
+  if (S.l == 0) ao_deriv_shell<0>(S, exps, coefs, grid, g0, g, in, GB, mat, phi);
+  else if (S.l == 1) ao_deriv_shell<1>(S, exps, coefs, grid, g0, g, in, GB, mat, phi);
+  else ao_deriv_shell<2>(S, exps, coefs, grid, g0, g, in, GB, mat, phi);
 }
 
 // Block mask over phi and its three derivatives: one wavefront per block.
@@ -549,7 +549,7 @@ void xc_batch(XcCall& x, const double* grid, int g0, int ng, int GB, double eps)
     if (pad) hipLaunchKernelGGL(fill_kernel, dim3((pad + 255) / 256), dim3(256), 0, x.s,
                                 x.phi + q * mat + static_cast<size_t>(x.n) * GB, pad, 0.0);
   if (x.gga) {
-    hipLaunchKernelGGL(ao_grad_kernel, dim3((GB + 255) / 256, x.ns), dim3(256), 0, x.s, x.shells,
+    hipLaunchKernelGGL(ao_deriv_kernel, dim3((GB + 255) / 256, x.ns), dim3(256), 0, x.s, x.shells,
                        x.exps, x.coefs, grid, g0, ng, GB, mat, x.phi);
     hipLaunchKernelGGL(mask4_kernel, dim3(nGb, x.nIb), dim3(64), 0, x.s, x.phi, GB, mat, eps, x.mask);
   } else {
