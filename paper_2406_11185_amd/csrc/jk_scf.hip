@@ -1,8 +1,7 @@
 // The SCF steps on either side of the J/K build, on the GPU (paper, "Key
-// Components Redesign and Implementation", SCF-iteration paragraph: once the
-// integrals run on the GPU, diagonalisation and DIIS become the bottleneck if
-// left on the CPU, so they move to the GPU; "DFT Calculation Flow" for the steps
-// themselves).
+// Components Redesign and Implementation", SCF-iteration paragraph, which puts
+// the Fock diagonalisation and the DIIS matrix work on the GPU too, with the
+// vendor solver and BLAS; "DFT Calculation Flow" for the steps themselves).
 //
 //   jk_scf_diag: F C = S C diag(eps) (rocSOLVER's generalised symmetric-definite
 //     divide-and-conquer solver) and the closed-shell density D = 2 C_occ C_occ^T
