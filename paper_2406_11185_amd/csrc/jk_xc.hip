@@ -111,7 +111,8 @@ __device__ __forceinline__ void ao_deriv_shell(const XcShell& S, const double* _
                                               const double* __restrict__ coefs,
                                               const double* __restrict__ grid, int g0, int g,
                                               bool in, int GB, size_t mat,
-                                              double* __restrict__ phi) {
+                                              double* __restrict__ phi, double eps, int nGb,
+                                              unsigned char* __restrict__ mask) {
   constexpr int NC = (L + 1) * (L + 2) / 2;
   double v[4][6] = {};
   if (in) {
@@ -133,6 +134,13 @@ __device__ __forceinline__ void ao_deriv_shell(const XcShell& S, const double* _
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int c = 0; c < NC; ++c) phi[q * mat + static_cast<size_t>(S.bf0 + c) * GB + g] = v[q][c];
+  // block mask (zeroed before the launch): a block with any value or derivative
+  // >= eps is nonzero; every writer stores the same 1
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double m = fmax(fmax(fabs(v[0][c]), fabs(v[1][c])), fmax(fabs(v[2][c]), fabs(v[3][c])));
+    if (m >= eps) mask[static_cast<size_t>((S.bf0 + c) / 32) * nGb + g / 32] = 1;
+  }
 }
 
 // Values and first derivatives of shell s at point g of the batch: phi, then
@@ -143,29 +151,22 @@ __device__ __forceinline__ void ao_deriv_shell(const XcShell& S, const double* _
 // template argument of the evaluation, so every array index is a constant.
 __global__ void ao_deriv_kernel(const XcShell* __restrict__ sh, const double* __restrict__ exps,
                                const double* __restrict__ coefs, const double* __restrict__ grid,
-                               int g0, int ng, int GB, size_t mat, double* __restrict__ phi) {
+                               int g0, int ng, int GB, size_t mat, double* __restrict__ phi,
+                               double eps, unsigned char* __restrict__ mask) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
   if (g >= GB) return;
   const XcShell S = sh[s];
   const bool in = g < ng;
-  if (S.l == 0) ao_deriv_shell<0>(S, exps, coefs, grid, g0, g, in, GB, mat, phi);
-  else if (S.l == 1) ao_deriv_shell<1>(S, exps, coefs, grid, g0, g, in, GB, mat, phi);
-  else ao_deriv_shell<2>(S, exps, coefs, grid, g0, g, in, GB, mat, phi);
+  const int nGb = GB / 32;
+  if (S.l == 0) ao_deriv_shell<0>(S, exps, coefs, grid, g0, g, in, GB, mat, phi, eps, nGb, mask);
+  else if (S.l == 1) ao_deriv_shell<1>(S, exps, coefs, grid, g0, g, in, GB, mat, phi, eps, nGb, mask);
+  else ao_deriv_shell<2>(S, exps, coefs, grid, g0, g, in, GB, mat, phi, eps, nGb, mask);
 }
 
-// Block mask over phi and its three derivatives: one wavefront per block.
-__global__ __launch_bounds__(64) void mask4_kernel(const double* __restrict__ phi, int GB, size_t mat,
-                                                   double eps, unsigned char* __restrict__ mask) {
-  const int G = blockIdx.x, I = blockIdx.y, t = threadIdx.x;
-  double m = 0.0;
-  for (int q = 0; q < 4; ++q)
-    for (int e = t; e < 32 * 32; e += 64) {
-      const int i = e / 32, g = e % 32;
-      m = fmax(m, fabs(phi[q * mat + static_cast<size_t>(I * 32 + i) * GB + G * 32 + g]));
-    }
-  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-  if (t == 0) mask[static_cast<size_t>(I) * gridDim.x + G] = m >= eps ? 1 : 0;
+__global__ void fill_bytes_kernel(unsigned char* p, size_t count) {
+  const size_t k = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k < count) p[k] = 0;
 }
 
 __global__ void fill_kernel(double* p, size_t count, double v) {
@@ -549,9 +550,10 @@ void xc_batch(XcCall& x, const double* grid, int g0, int ng, int GB, double eps)
     if (pad) hipLaunchKernelGGL(fill_kernel, dim3((pad + 255) / 256), dim3(256), 0, x.s,
                                 x.phi + q * mat + static_cast<size_t>(x.n) * GB, pad, 0.0);
   if (x.gga) {
+    const size_t nm = static_cast<size_t>(x.nIb) * nGb;
+    hipLaunchKernelGGL(fill_bytes_kernel, dim3((nm + 255) / 256), dim3(256), 0, x.s, x.mask, nm);
     hipLaunchKernelGGL(ao_deriv_kernel, dim3((GB + 255) / 256, x.ns), dim3(256), 0, x.s, x.shells,
-                       x.exps, x.coefs, grid, g0, ng, GB, mat, x.phi);
-    hipLaunchKernelGGL(mask4_kernel, dim3(nGb, x.nIb), dim3(64), 0, x.s, x.phi, GB, mat, eps, x.mask);
+                       x.exps, x.coefs, grid, g0, ng, GB, mat, x.phi, eps, x.mask);
   } else {
     hipLaunchKernelGGL(ao_kernel, dim3((GB + 255) / 256, x.ns), dim3(256), 0, x.s, x.shells, x.exps,
                        x.coefs, grid, g0, ng, GB, x.phi);
